@@ -1,0 +1,250 @@
+"""CPU oracle for the work-forwarding hot path -- TEST INFRASTRUCTURE ONLY.
+
+Thin numpy/ctypes front end of ``rafi_oracle.c``. Only ``tests/``, the smoke
+check and the benchmark's CPU-baseline leg may import this package; the
+product library never does, and the two share no code. See the C file for
+the definitions each function follows and the passages of the paper they
+restate.
+
+Parity status of every function is recorded in the C file's header notes and
+in the tests under ``tests/test_oracle_*.py`` (each function is pinned by at
+least one check that does not reuse the oracle's own arithmetic).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rafi_oracle.c")
+_LIB = os.path.join(_HERE, "librafi_oracle.so")
+
+DONE = -1
+SL_LIVE, SL_STAGNANT, SL_EXITED, SL_MAXSTEPS = 0, 1, 2, 3
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (no fast-math, no contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+               "-fno-fast-math", "-Wall", "-Wextra", "-Wno-unused-parameter",
+               "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        _declare(_lib)
+    return _lib
+
+
+class EAParams(C.Structure):
+    _fields_ = [("n", C.c_int32), ("g", C.c_int32 * 3), ("dt", C.c_float), ("c", C.c_float)]
+
+
+class SLParams(C.Structure):
+    _fields_ = [("n", C.c_int32), ("g", C.c_int32 * 3), ("h", C.c_float), ("max_steps", C.c_int32)]
+
+
+_p = C.c_void_p
+
+
+def _declare(L):
+    L.oracle_multisplit.argtypes = [C.c_uint64, C.c_uint32, _p, _p, C.c_int32, _p, _p, _p, _p, _p]
+    L.oracle_multisplit.restype = C.c_int
+    L.oracle_trilinear.argtypes = [_p, C.c_int32, C.c_float, C.c_float, C.c_float]
+    L.oracle_trilinear.restype = C.c_double
+    L.oracle_ea_render.argtypes = [_p, C.POINTER(EAParams), _p, C.c_int32, _p, _p, _p, C.c_int32,
+                                   _p, _p, C.c_uint64, _p, _p, C.c_int32]
+    L.oracle_ea_render.restype = C.c_int
+    L.oracle_ea_brute.argtypes = [_p, C.POINTER(EAParams), _p, C.c_int32, _p, C.c_int64, _p, _p,
+                                  _p, C.c_int32]
+    L.oracle_ea_brute.restype = C.c_int
+    L.oracle_ea_ray_samples.argtypes = [_p, C.POINTER(EAParams), _p, C.c_int32, C.c_int64, _p, C.c_int32]
+    L.oracle_ea_ray_samples.restype = C.c_int32
+    L.oracle_ea_loss_grad.argtypes = [_p, C.POINTER(EAParams), _p, C.c_int32, _p, _p, C.c_int64,
+                                      _p, _p, _p]
+    L.oracle_ea_loss_grad.restype = C.c_int
+    L.oracle_streamlines.argtypes = [_p, C.POINTER(SLParams), _p, C.c_int64, C.c_int32, _p, _p, _p,
+                                     C.c_int32, _p, _p, C.c_uint64, _p, _p, C.c_int32]
+    L.oracle_streamlines.restype = C.c_int
+    L.oracle_streamlines_brute.argtypes = [_p, C.POINTER(SLParams), _p, C.c_int64, _p, _p, _p, _p,
+                                           C.c_int32]
+    L.oracle_streamlines_brute.restype = C.c_int
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+# ------------------------------------------------------------ multisplit ---
+
+def multisplit(items: np.ndarray, dest: np.ndarray, n_domains: int):
+    """Stable split of ``items`` (shape (n, ...), any dtype, one row per slot)
+    by ``dest``. Returns (out, counts, offsets, n_done, n_bad); ``out`` holds
+    offsets[-1] rows."""
+    items = np.ascontiguousarray(items)
+    dest = np.ascontiguousarray(dest, dtype=np.int32)
+    n = dest.shape[0]
+    assert items.shape[0] == n
+    row_bytes = items.itemsize * (int(np.prod(items.shape[1:])) if items.ndim > 1 else 1)
+    out = np.empty_like(items)
+    counts = np.zeros(n_domains, dtype=np.uint64)
+    offsets = np.zeros(n_domains + 1, dtype=np.uint64)
+    nd, nb = C.c_uint64(0), C.c_uint64(0)
+    rc = lib().oracle_multisplit(n, row_bytes, _ptr(items), _ptr(dest), n_domains, _ptr(out),
+                                 _ptr(counts), _ptr(offsets), C.byref(nd), C.byref(nb))
+    if rc != 0:
+        raise RuntimeError(f"oracle_multisplit failed: {rc}")
+    return out[: int(offsets[-1])], counts, offsets, nd.value, nb.value
+
+
+# ------------------------------------------------------------------- EA ---
+
+def trilinear(volume: np.ndarray, q) -> float:
+    vol = np.ascontiguousarray(volume, dtype=np.float64)
+    return lib().oracle_trilinear(_ptr(vol), vol.shape[0], float(q[0]), float(q[1]), float(q[2]))
+
+
+def _ea_params(n, grid, dt, c):
+    return EAParams(int(n), (C.c_int32 * 3)(*[int(g) for g in grid]), float(dt), float(c))
+
+
+def n_rays_of(views) -> int:
+    return int(sum(int(v["width"]) * int(v["height"]) for v in views))
+
+
+def ea_render(volume, grid, views, dt=0.5, c=0.025, max_rounds=256, queue_cap=0,
+              visit_stride=0, want_rounds=True):
+    """Partitioned round loop (O2 + O3). Returns a dict with image, tau, klast,
+    rounds, round_counts [rounds, D], queue (ray ids per forward step,
+    concatenated) and visits [n_rays, visit_stride]."""
+    vol = np.ascontiguousarray(volume, dtype=np.float64)
+    n = vol.shape[0]
+    views = np.ascontiguousarray(views)
+    nr = n_rays_of(views)
+    D = int(np.prod(grid))
+    P = _ea_params(n, grid, dt, c)
+    image = np.zeros(nr, dtype=np.float64)
+    tau = np.zeros(nr, dtype=np.float64)
+    klast = np.zeros(nr, dtype=np.int32)
+    rc = np.zeros((max_rounds, D), dtype=np.uint64) if want_rounds else None
+    q = np.zeros(max(queue_cap, 1), dtype=np.int64) if queue_cap else None
+    qlen = C.c_uint64(0)
+    vis = np.zeros((nr, visit_stride), dtype=np.int32) if visit_stride else None
+    rounds = lib().oracle_ea_render(_ptr(vol), C.byref(P), _ptr(views), len(views), _ptr(image),
+                                    _ptr(tau), _ptr(klast), max_rounds, _ptr(rc), _ptr(q),
+                                    queue_cap, C.byref(qlen), _ptr(vis), visit_stride)
+    if rounds < 0:
+        raise RuntimeError(f"oracle_ea_render failed: {rounds}")
+    out = dict(image=image, tau=tau, klast=klast, rounds=rounds, visits=vis)
+    if rc is not None:
+        out["round_counts"] = rc[:rounds]
+    if q is not None:
+        out["queue"] = q[: min(qlen.value, queue_cap)]
+        out["queue_len"] = qlen.value
+    return out
+
+
+def ea_brute(volume, grid, views, dt=0.5, c=0.025, ray_ids=None, visit_stride=0):
+    vol = np.ascontiguousarray(volume, dtype=np.float64)
+    views = np.ascontiguousarray(views)
+    P = _ea_params(vol.shape[0], grid, dt, c)
+    ids = None if ray_ids is None else np.ascontiguousarray(ray_ids, dtype=np.int64)
+    m = n_rays_of(views) if ids is None else len(ids)
+    image = np.zeros(m, dtype=np.float64)
+    tau = np.zeros(m, dtype=np.float64)
+    vis = np.zeros((m, visit_stride), dtype=np.int32) if visit_stride else None
+    lib().oracle_ea_brute(_ptr(vol), C.byref(P), _ptr(views), len(views), _ptr(ids),
+                          0 if ids is None else len(ids), _ptr(image), _ptr(tau), _ptr(vis),
+                          visit_stride)
+    return dict(image=image, tau=tau, visits=vis)
+
+
+def ea_ray_samples(volume, grid, views, ray, dt=0.5, c=0.025):
+    vol = np.ascontiguousarray(volume, dtype=np.float64)
+    views = np.ascontiguousarray(views)
+    P = _ea_params(vol.shape[0], grid, dt, c)
+    cap = int(max(v["n_samples"] for v in views))
+    buf = np.zeros(cap, dtype=np.float64)
+    m = lib().oracle_ea_ray_samples(_ptr(vol), C.byref(P), _ptr(views), len(views), int(ray),
+                                    _ptr(buf), cap)
+    return buf[:m]
+
+
+def ea_loss_grad(volume, grid, views, target, dt=0.5, c=0.025, ray_ids=None, want_grad=True):
+    """Loss sum (I - I*)^2 and its float64 gradient w.r.t. the voxels (O6)."""
+    vol = np.ascontiguousarray(volume, dtype=np.float64)
+    views = np.ascontiguousarray(views)
+    tgt = np.ascontiguousarray(target, dtype=np.float64)
+    P = _ea_params(vol.shape[0], grid, dt, c)
+    ids = None if ray_ids is None else np.ascontiguousarray(ray_ids, dtype=np.int64)
+    m = n_rays_of(views) if ids is None else len(ids)
+    image = np.zeros(m, dtype=np.float64)
+    grad = np.zeros(vol.shape, dtype=np.float64) if want_grad else None
+    loss = C.c_double(0.0)
+    rc = lib().oracle_ea_loss_grad(_ptr(vol), C.byref(P), _ptr(views), len(views), _ptr(tgt),
+                                   _ptr(ids), 0 if ids is None else len(ids), _ptr(image),
+                                   _ptr(grad), C.byref(loss))
+    if rc != 0:
+        raise RuntimeError(f"oracle_ea_loss_grad failed: {rc}")
+    return loss.value, grad, image
+
+
+# ----------------------------------------------------------- streamlines ---
+
+def _sl_params(n, grid, h, max_steps):
+    return SLParams(int(n), (C.c_int32 * 3)(*[int(g) for g in grid]), float(h), int(max_steps))
+
+
+def streamlines(field, grid, seeds, h=0.25, max_steps=2000, one_step=False, max_rounds=100000,
+                queue_cap=0, visit_stride=0, want_rounds=True):
+    f = np.ascontiguousarray(field, dtype=np.float32)
+    n = f.shape[0]
+    s = np.ascontiguousarray(seeds, dtype=np.float32)
+    N = s.shape[0]
+    D = int(np.prod(grid))
+    P = _sl_params(n, grid, h, max_steps)
+    ep = np.zeros((N, 3), dtype=np.float32)
+    st = np.zeros(N, dtype=np.int32)
+    why = np.zeros(N, dtype=np.int32)
+    rc = np.zeros((max_rounds, D), dtype=np.uint64) if want_rounds else None
+    q = np.zeros(max(queue_cap, 1), dtype=np.int32) if queue_cap else None
+    qlen = C.c_uint64(0)
+    vis = np.zeros((N, visit_stride), dtype=np.int32) if visit_stride else None
+    rounds = lib().oracle_streamlines(_ptr(f), C.byref(P), _ptr(s), N, int(one_step), _ptr(ep),
+                                      _ptr(st), _ptr(why), max_rounds, _ptr(rc), _ptr(q), queue_cap,
+                                      C.byref(qlen), _ptr(vis), visit_stride)
+    if rounds < 0:
+        raise RuntimeError(f"oracle_streamlines failed: {rounds}")
+    out = dict(endpoint=ep, steps=st, reason=why, rounds=rounds, visits=vis)
+    if rc is not None:
+        out["round_counts"] = rc[:rounds]
+    if q is not None:
+        out["queue"] = q[: min(qlen.value, queue_cap)]
+        out["queue_len"] = qlen.value
+    return out
+
+
+def streamlines_brute(field, grid, seeds, h=0.25, max_steps=2000, visit_stride=0):
+    f = np.ascontiguousarray(field, dtype=np.float32)
+    s = np.ascontiguousarray(seeds, dtype=np.float32)
+    N = s.shape[0]
+    P = _sl_params(f.shape[0], grid, h, max_steps)
+    ep = np.zeros((N, 3), dtype=np.float32)
+    st = np.zeros(N, dtype=np.int32)
+    why = np.zeros(N, dtype=np.int32)
+    vis = np.zeros((N, visit_stride), dtype=np.int32) if visit_stride else None
+    lib().oracle_streamlines_brute(_ptr(f), C.byref(P), _ptr(s), N, _ptr(ep), _ptr(st), _ptr(why),
+                                   _ptr(vis), visit_stride)
+    return dict(endpoint=ep, steps=st, reason=why, visits=vis)

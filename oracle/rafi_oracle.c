@@ -1,0 +1,723 @@
+/*
+ * rafi_oracle.c -- CPU oracle for the work-forwarding hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY. This is a plain, slow, obviously-correct CPU
+ * statement of what the forwarding path computes. Only the test suite, the
+ * smoke check and the benchmark's CPU-baseline leg load it; the product
+ * library never calls it, and it shares no source, header, table or constant
+ * with the HIP path. Single-threaded.
+ *
+ * Precision: floating point that decides an integer (sample positions, which
+ * brick owns a point, RK4 trajectories that decide routing and step counts) is
+ * carried in float32 with every operation spelled out (fmaf where the method
+ * fuses), exactly as the GPU kernels take those decisions. Integrals and
+ * gradients, which decide nothing, are carried in float64.
+ *
+ * Compile with -ffp-contract=off and without -ffast-math so that every
+ * float32 operation below is rounded exactly once.
+ *
+ * Paper references are to "RaFI" (arXiv 2605.30294): Sec. 3.2 ray queues,
+ * Sec. 3.3 device interface, Sec. 3.4 host context, Sec. 4.2.1 sorting by
+ * destination, Sec. 4.2.2 exchanging rays, Sec. 4.2.3 wrap-up, Sec. 5.1
+ * VoPaT (ray-march-and-forward), Sec. 5.4 particle tracing.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_DONE (-1)
+
+/* ======================================================================
+ * O1. The forward step = a stable counting sort by destination.
+ *
+ * Sec. 4.2.1 sorts the emitted items by the 64-bit key (dest << 32 | i) and
+ * gathers them, so items bound for the same destination keep their emission
+ * order. Sec. 4.2.2 tallies per-destination begin/end (empty destinations get
+ * zero) and exchanges count and offset arrays. On one device the result of
+ * all of this is: item i with destination e lands at
+ *     offset[e] + #{ j < i : dest[j] == e },
+ * with offset[] the exclusive prefix sum of the per-destination counts.
+ * That is counting sort (CLRS 8.2), written out directly here.
+ *
+ * dest == -1 (ORC_DONE) means "leaves the system"; any other value outside
+ * [0, n_domains) is an invalid destination: both kinds are dropped and counted.
+ * Items are opaque bytes (Sec. 3.1: the library never looks inside).
+ * ====================================================================== */
+int oracle_multisplit(uint64_t n, uint32_t item_bytes, const uint8_t *items,
+                      const int32_t *dest, int32_t n_domains, uint8_t *out,
+                      uint64_t *counts, uint64_t *offsets, uint64_t *n_done,
+                      uint64_t *n_bad)
+{
+    if (n_domains <= 0) return -1;
+    uint64_t done = 0, bad = 0;
+    for (int32_t e = 0; e < n_domains; ++e) counts[e] = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        int32_t d = dest[i];
+        if (d == ORC_DONE) done++;
+        else if (d < 0 || d >= n_domains) bad++;
+        else counts[d]++;
+    }
+    offsets[0] = 0;
+    for (int32_t e = 0; e < n_domains; ++e) offsets[e + 1] = offsets[e] + counts[e];
+    uint64_t *cursor = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n_domains);
+    if (!cursor) return -2;
+    for (int32_t e = 0; e < n_domains; ++e) cursor[e] = offsets[e];
+    for (uint64_t i = 0; i < n; ++i) {
+        int32_t d = dest[i];
+        if (d < 0 || d >= n_domains) continue;
+        memcpy(out + cursor[d] * item_bytes, items + i * item_bytes, item_bytes);
+        cursor[d]++;
+    }
+    free(cursor);
+    if (n_done) *n_done = done;
+    if (n_bad) *n_bad = bad;
+    return 0;
+}
+
+/* ======================================================================
+ * Geometry shared by the volume and the field workloads (oracle-local).
+ *
+ * Cube of n^3 voxels, voxel centres at i + 0.5, world box [0, n)^3, split into
+ * g[0] x g[1] x g[2] equal bricks ("domains", the paper's ranks) of edge
+ * n / g[a]. Domain id d = bx + g0 * (by + g1 * bz). A point belongs to the
+ * brick containing it (half-open bricks: a point on a brick plane belongs to
+ * the upper brick); a point outside the box belongs to nobody (-1).
+ * ====================================================================== */
+static int32_t owner_of(const float p[3], int32_t n, const int32_t g[3])
+{
+    const float fn = (float)n;
+    int32_t b[3];
+    for (int a = 0; a < 3; ++a) {
+        if (!(p[a] >= 0.0f) || !(p[a] < fn)) return -1;
+        int32_t cell = (int32_t)floorf(p[a]);
+        b[a] = cell / (n / g[a]);
+    }
+    return b[0] + g[0] * (b[1] + g[1] * b[2]);
+}
+
+/* Trilinear interpolation of voxel-centred samples with clamp-to-edge, in
+ * float64: the plain definition, sum over the 8 corners of the product of the
+ * per-axis weights. Weights come from u = clamp(q - 1/2, 0, n - 1),
+ * i0 = min(floor(u), n - 2), f = u - i0. */
+static void tri_setup(const float q[3], int32_t n, int32_t i0[3], double f[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        double u = (double)q[a] - 0.5;
+        if (u < 0.0) u = 0.0;
+        if (u > (double)(n - 1)) u = (double)(n - 1);
+        int32_t i = (int32_t)floor(u);
+        if (i > n - 2) i = n - 2;
+        i0[a] = i;
+        f[a] = u - (double)i;
+    }
+}
+
+static double tri_scalar(const double *vol, int32_t n, const float q[3])
+{
+    int32_t i0[3];
+    double f[3];
+    tri_setup(q, n, i0, f);
+    double s = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        int32_t dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
+        double w = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) * (dz ? f[2] : 1.0 - f[2]);
+        size_t idx = (size_t)(i0[0] + dx) + (size_t)n * ((size_t)(i0[1] + dy) + (size_t)n * (size_t)(i0[2] + dz));
+        s += w * vol[idx];
+    }
+    return s;
+}
+
+/* Exposed for the interpolation pins (linear fields, voxel centres, clamping). */
+double oracle_trilinear(const double *vol, int32_t n, float qx, float qy, float qz)
+{
+    float q[3] = {qx, qy, qz};
+    return tri_scalar(vol, n, q);
+}
+
+/* ======================================================================
+ * O3. Emission-absorption ray march through a bricked scalar volume.
+ *
+ * Each brick advances the rays it owns sample by sample while the samples stay
+ * inside it, carrying the partial integral in the item (the pattern of the
+ * volume renderers in Sec. 5.1-5.3: a forwarded ray packages its integration
+ * state and continues in the next domain); on leaving it is forwarded to the
+ * owner of its next sample, or finishes when it leaves the volume.
+ *
+ * Sample k of a ray: t_k = (k + 1/2) dt, p_k = fma(t_k, dir, org) in float32,
+ * with org = fma(py, dv, fma(px, du, org0)). The sample density is
+ * rho_k = V(p_k); with sigma_k = c * rho_k (c = kappa * dt),
+ *     I = sum_k exp(-tau_k) (1 - exp(-sigma_k)) rho_k,   tau_k = sum_{j<k} sigma_j,
+ * over the samples inside the volume (emission equal to density).
+ * ====================================================================== */
+typedef struct {
+    float org0[3], du[3], dv[3], dir[3];
+    int32_t width, height, n_samples, pad;
+} orc_view;
+
+static void ray_origin(const orc_view *v, int32_t px, int32_t py, float org[3])
+{
+    for (int a = 0; a < 3; ++a)
+        org[a] = fmaf((float)py, v->dv[a], fmaf((float)px, v->du[a], v->org0[a]));
+}
+
+static void sample_pos(const float org[3], const float dir[3], float dt, int32_t k, float p[3])
+{
+    float t = ((float)k + 0.5f) * dt;
+    for (int a = 0; a < 3; ++a) p[a] = fmaf(t, dir[a], org[a]);
+}
+
+static void ray_of(const orc_view *views, int64_t r, const orc_view **v, int32_t *px, int32_t *py)
+{
+    int64_t per = 0, base = 0;
+    int32_t vi = 0;
+    for (;;) {
+        per = (int64_t)views[vi].width * views[vi].height;
+        if (r < base + per) break;
+        base += per;
+        vi++;
+    }
+    *v = &views[vi];
+    int64_t local = r - base;
+    *px = (int32_t)(local % views[vi].width);
+    *py = (int32_t)(local / views[vi].width);
+}
+
+/* The oracle's own work item: ray id, next sample, optical depth and the
+ * partial integral in float64. */
+typedef struct {
+    int64_t ray;
+    int32_t k;
+    int32_t pad;
+    double tau;
+    double I;
+} orc_ray;
+
+typedef struct {
+    int32_t n;
+    int32_t g[3];
+    float dt;
+    float c;
+} orc_ea_params;
+
+/* Advance one ray inside domain d; returns the destination (ORC_DONE when it
+ * leaves the volume or runs out of samples). Optionally records the number of
+ * samples taken in this brick. */
+static int32_t ea_advance(const double *vol, const orc_ea_params *P, const orc_view *v,
+                          const float org[3], orc_ray *it, int32_t d)
+{
+    const double c = (double)P->c;
+    for (;;) {
+        if (it->k >= v->n_samples) return ORC_DONE;
+        float p[3];
+        sample_pos(org, v->dir, P->dt, it->k, p);
+        int32_t e = owner_of(p, P->n, P->g);
+        if (e < 0) return ORC_DONE;
+        if (e != d) return e;
+        double rho = tri_scalar(vol, P->n, p);
+        double sigma = c * rho;
+        it->I += exp(-it->tau) * (-expm1(-sigma)) * rho;
+        it->tau += sigma;
+        it->k++;
+    }
+}
+
+/* First sample index inside the volume (the ray generator's job), or -1. */
+static int32_t ea_first_inside(const orc_ea_params *P, const orc_view *v, const float org[3],
+                               int32_t *owner)
+{
+    for (int32_t k = 0; k < v->n_samples; ++k) {
+        float p[3];
+        sample_pos(org, v->dir, P->dt, k, p);
+        int32_t e = owner_of(p, P->n, P->g);
+        if (e >= 0) { *owner = e; return k; }
+    }
+    return -1;
+}
+
+/*
+ * O2 + O3: the round loop of Sec. 3.4 / 4.2.3 with per-domain queues.
+ *
+ * Round 0 generates one item per ray and sends it to the owner of its first
+ * inside sample (rays that miss the volume finish with I = 0). Every later
+ * round walks the domains in order and each domain's queue in order, advances
+ * every item, and collects the emitted items in that order; the forward step
+ * (O1) then regroups them by destination. The loop ends when no item is left
+ * (the returned total of Sec. 3.4), or fails at max_rounds.
+ *
+ * Outputs (any may be NULL):
+ *   image[r]        final integral per ray (0 for rays that miss)
+ *   tau_out[r]      final optical depth per ray
+ *   klast_out[r]    index one past the last inside sample (0 for misses)
+ *   round_counts    [max_rounds][D] number of items per domain delivered by
+ *                   each forward step (round 0 = after ray generation)
+ *   queue_log       ray ids in queue order after every forward step,
+ *                   concatenated over rounds; capacity queue_cap entries
+ *   visit_log       [n_rays][visit_stride] domain ids each ray visited, -1 padded
+ * Returns the number of forward steps taken, or a negative error.
+ */
+int oracle_ea_render(const double *vol, const orc_ea_params *P, const orc_view *views,
+                     int32_t n_views, double *image, double *tau_out, int32_t *klast_out,
+                     int32_t max_rounds, uint64_t *round_counts, int64_t *queue_log,
+                     uint64_t queue_cap, uint64_t *queue_len, int32_t *visit_log,
+                     int32_t visit_stride)
+{
+    const int32_t D = P->g[0] * P->g[1] * P->g[2];
+    int64_t n_rays = 0;
+    for (int32_t i = 0; i < n_views; ++i) n_rays += (int64_t)views[i].width * views[i].height;
+
+    orc_ray *O = (orc_ray *)malloc(sizeof(orc_ray) * (size_t)(n_rays ? n_rays : 1));
+    orc_ray *Q = (orc_ray *)malloc(sizeof(orc_ray) * (size_t)(n_rays ? n_rays : 1));
+    int32_t *odest = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_rays ? n_rays : 1));
+    uint64_t *counts = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)D);
+    uint64_t *offs = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(D + 1));
+    int32_t *nvis = (int32_t *)calloc((size_t)(n_rays ? n_rays : 1), sizeof(int32_t));
+    if (!O || !Q || !odest || !counts || !offs || !nvis) return -2;
+    if (visit_log)
+        for (int64_t i = 0; i < n_rays * visit_stride; ++i) visit_log[i] = -1;
+    uint64_t qlen = 0;
+
+    /* Round 0: ray generation; one output slot per ray. */
+    uint64_t n_out = 0;
+    for (int64_t r = 0; r < n_rays; ++r) {
+        const orc_view *v;
+        int32_t px, py, own = -1;
+        ray_of(views, r, &v, &px, &py);
+        float org[3];
+        ray_origin(v, px, py, org);
+        int32_t k0 = ea_first_inside(P, v, org, &own);
+        orc_ray it = {r, k0 < 0 ? 0 : k0, 0, 0.0, 0.0};
+        O[n_out] = it;
+        odest[n_out] = (k0 < 0) ? ORC_DONE : own;
+        n_out++;
+        if (k0 < 0) {
+            if (image) image[r] = 0.0;
+            if (tau_out) tau_out[r] = 0.0;
+            if (klast_out) klast_out[r] = 0;
+        }
+    }
+
+    int32_t rounds = 0;
+    uint64_t total = 0;
+    for (;;) {
+        /* Forward step (O1) on the emitted slots. */
+        oracle_multisplit(n_out, (uint32_t)sizeof(orc_ray), (const uint8_t *)O, odest, D,
+                          (uint8_t *)Q, counts, offs, NULL, NULL);
+        total = offs[D];
+        if (rounds >= max_rounds) { rounds = -6; break; }
+        if (round_counts)
+            for (int32_t e = 0; e < D; ++e) round_counts[(size_t)rounds * D + e] = counts[e];
+        for (uint64_t i = 0; i < total; ++i) {
+            if (queue_log && qlen < queue_cap) queue_log[qlen] = Q[i].ray;
+            qlen++;
+        }
+        /* Record the visit of every delivered item. */
+        for (int32_t d = 0; d < D; ++d)
+            for (uint64_t i = offs[d]; i < offs[d + 1]; ++i) {
+                int64_t r = Q[i].ray;
+                if (visit_log && nvis[r] < visit_stride) visit_log[r * visit_stride + nvis[r]] = d;
+                nvis[r]++;
+            }
+        rounds++;
+        if (total == 0) break;
+
+        /* Domain kernels: walk domains in order, items in queue order. */
+        n_out = 0;
+        for (int32_t d = 0; d < D; ++d) {
+            for (uint64_t i = offs[d]; i < offs[d + 1]; ++i) {
+                orc_ray it = Q[i];
+                const orc_view *v;
+                int32_t px, py;
+                ray_of(views, it.ray, &v, &px, &py);
+                float org[3];
+                ray_origin(v, px, py, org);
+                int32_t e = ea_advance(vol, P, v, org, &it, d);
+                O[n_out] = it;
+                odest[n_out] = e;
+                n_out++;
+                if (e == ORC_DONE) {
+                    if (image) image[it.ray] = it.I;
+                    if (tau_out) tau_out[it.ray] = it.tau;
+                    if (klast_out) klast_out[it.ray] = it.k;
+                }
+            }
+        }
+    }
+    if (queue_len) *queue_len = qlen;
+    free(O); free(Q); free(odest); free(counts); free(offs); free(nvis);
+    return rounds;
+}
+
+/*
+ * Unpartitioned brute force: march every ray through all of its samples in
+ * one go, never forwarding. The paper states that forwarding changes neither
+ * which rays are traced nor what they compute (Sec. 5.1), so the partitioned
+ * round loop must reproduce this bit for bit. The visit sequence is the
+ * run-length-compressed sequence of owning bricks along the samples.
+ * ray_ids selects a subset of rays (NULL = all, in order); outputs are indexed
+ * by position in that list.
+ */
+int oracle_ea_brute(const double *vol, const orc_ea_params *P, const orc_view *views,
+                    int32_t n_views, const int64_t *ray_ids, int64_t n_ids, double *image,
+                    double *tau_out, int32_t *visit_log, int32_t visit_stride)
+{
+    const double c = (double)P->c;
+    int64_t n_rays = 0;
+    for (int32_t i = 0; i < n_views; ++i) n_rays += (int64_t)views[i].width * views[i].height;
+    if (!ray_ids) n_ids = n_rays;
+    for (int64_t q = 0; q < n_ids; ++q) {
+        int64_t r = ray_ids ? ray_ids[q] : q;
+        const orc_view *v;
+        int32_t px, py;
+        ray_of(views, r, &v, &px, &py);
+        float org[3];
+        ray_origin(v, px, py, org);
+        double tau = 0.0, I = 0.0;
+        int32_t last = -2, nv = 0;
+        if (visit_log)
+            for (int32_t s = 0; s < visit_stride; ++s) visit_log[q * visit_stride + s] = -1;
+        for (int32_t k = 0; k < v->n_samples; ++k) {
+            float p[3];
+            sample_pos(org, v->dir, P->dt, k, p);
+            int32_t e = owner_of(p, P->n, P->g);
+            if (e < 0) continue;
+            if (e != last) {
+                if (visit_log && nv < visit_stride) visit_log[q * visit_stride + nv] = e;
+                nv++;
+                last = e;
+            }
+            double rho = tri_scalar(vol, P->n, p);
+            double sigma = c * rho;
+            I += exp(-tau) * (-expm1(-sigma)) * rho;
+            tau += sigma;
+        }
+        if (image) image[q] = I;
+        if (tau_out) tau_out[q] = tau;
+    }
+    return 0;
+}
+
+/* Per-sample densities of one ray (inside samples only, in order), for the
+ * compositing-identity pin. Returns the number written. */
+int32_t oracle_ea_ray_samples(const double *vol, const orc_ea_params *P, const orc_view *views,
+                              int32_t n_views, int64_t ray, double *rho_out, int32_t cap)
+{
+    const orc_view *v;
+    int32_t px, py, m = 0;
+    (void)n_views;
+    ray_of(views, ray, &v, &px, &py);
+    float org[3];
+    ray_origin(v, px, py, org);
+    for (int32_t k = 0; k < v->n_samples; ++k) {
+        float p[3];
+        sample_pos(org, v->dir, P->dt, k, p);
+        if (owner_of(p, P->n, P->g) < 0) continue;
+        if (m < cap) rho_out[m] = tri_scalar(vol, P->n, p);
+        m++;
+    }
+    return m;
+}
+
+/* ======================================================================
+ * O6. Gradient of the image loss L = sum_r (I_r - I*_r)^2 with respect to the
+ * voxel densities (the adjoint of O3), float64.
+ *
+ * With T_k = exp(-tau_k), a_k = 1 - exp(-sigma_k) and I = sum_k T_k a_k rho_k,
+ *   dI/drho_k = T_k [ a_k + c exp(-sigma_k) (rho_k - B_{k+1}) ],
+ * where B_{k+1} = sum_{j>k} (T_j / T_{k+1}) a_j rho_j is the part of the
+ * integral behind sample k, obeying B_k = a_k rho_k + (1 - a_k) B_{k+1},
+ * B_end = 0. Densities are trilinear in the voxels, so
+ *   dL/dV_v = sum_r 2 (I_r - I*_r) sum_k dI_r/drho_k w_v(p_k).
+ * Each ray is swept front to back (storing tau_k and rho_k), then back to front.
+ * ray_ids selects a subset (NULL = all rays); target is indexed by ray id.
+ * ====================================================================== */
+int oracle_ea_loss_grad(const double *vol, const orc_ea_params *P, const orc_view *views,
+                        int32_t n_views, const double *target, const int64_t *ray_ids,
+                        int64_t n_ids, double *image, double *grad, double *loss)
+{
+    const double c = (double)P->c;
+    const int32_t n = P->n;
+    int64_t n_rays = 0;
+    int32_t maxs = 0;
+    for (int32_t i = 0; i < n_views; ++i) {
+        n_rays += (int64_t)views[i].width * views[i].height;
+        if (views[i].n_samples > maxs) maxs = views[i].n_samples;
+    }
+    if (!ray_ids) n_ids = n_rays;
+    double *tau_k = (double *)malloc(sizeof(double) * (size_t)(maxs + 1));
+    double *rho_k = (double *)malloc(sizeof(double) * (size_t)(maxs + 1));
+    int32_t *ks = (int32_t *)malloc(sizeof(int32_t) * (size_t)(maxs + 1));
+    if (!tau_k || !rho_k || !ks) return -2;
+    double L = 0.0;
+    for (int64_t q = 0; q < n_ids; ++q) {
+        int64_t r = ray_ids ? ray_ids[q] : q;
+        const orc_view *v;
+        int32_t px, py;
+        ray_of(views, r, &v, &px, &py);
+        float org[3];
+        ray_origin(v, px, py, org);
+        double tau = 0.0, I = 0.0;
+        int32_t m = 0;
+        for (int32_t k = 0; k < v->n_samples; ++k) {
+            float p[3];
+            sample_pos(org, v->dir, P->dt, k, p);
+            if (owner_of(p, n, P->g) < 0) continue;
+            double rho = tri_scalar(vol, n, p);
+            double sigma = c * rho;
+            tau_k[m] = tau;
+            rho_k[m] = rho;
+            ks[m] = k;
+            m++;
+            I += exp(-tau) * (-expm1(-sigma)) * rho;
+            tau += sigma;
+        }
+        if (image) image[q] = I;
+        double resid = I - target[r];
+        L += resid * resid;
+        if (!grad) continue;
+        double gI = 2.0 * resid;
+        double B = 0.0;
+        for (int32_t s = m - 1; s >= 0; --s) {
+            double rho = rho_k[s], sigma = c * rho;
+            double T = exp(-tau_k[s]);
+            double a = -expm1(-sigma);
+            double dIdrho = T * (a + c * exp(-sigma) * (rho - B));
+            float p[3];
+            sample_pos(org, v->dir, P->dt, ks[s], p);
+            int32_t i0[3];
+            double f[3];
+            tri_setup(p, n, i0, f);
+            for (int cc = 0; cc < 8; ++cc) {
+                int32_t dx = cc & 1, dy = (cc >> 1) & 1, dz = (cc >> 2) & 1;
+                double w = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) * (dz ? f[2] : 1.0 - f[2]);
+                size_t idx = (size_t)(i0[0] + dx) + (size_t)n * ((size_t)(i0[1] + dy) + (size_t)n * (size_t)(i0[2] + dz));
+                grad[idx] += gI * dIdrho * w;
+            }
+            B = a * rho + (1.0 - a) * B;
+        }
+    }
+    if (loss) *loss = L;
+    free(tau_k); free(rho_k); free(ks);
+    return 0;
+}
+
+/* ======================================================================
+ * O4. RK4 streamlines through a bricked vector field (Sec. 5.4).
+ *
+ * One item per particle: id, position (float3) and step count. A brick
+ * integrates its particles with classical RK4 (step h) while they stay inside
+ * it; a particle finishes when a step does not move it, when it leaves the
+ * field, or at max_steps; otherwise it is forwarded to the brick that now owns
+ * it. All of this decides integers (routing, step counts), so it runs in
+ * float32 with each operation written out:
+ *   k1 = V(p), k2 = V(p + (h/2) k1), k3 = V(p + (h/2) k2), k4 = V(p + h k3)
+ *   s = k1 + 2 k2 + 2 k3 + k4 (as fma(2,k2,k1), fma(2,k3,.), + k4)
+ *   p' = fma(h/6, s, p)                       componentwise.
+ * V is float32 trilinear interpolation of the voxel-centred field with
+ * clamp-to-edge, lerping along x, then y, then z, lerp(a,b,t) = fma(t, b-a, a).
+ * ====================================================================== */
+typedef struct {
+    int32_t n;
+    int32_t g[3];
+    float h;
+    int32_t max_steps;
+} orc_sl_params;
+
+enum { ORC_SL_LIVE = 0, ORC_SL_STAGNANT = 1, ORC_SL_EXITED = 2, ORC_SL_MAXSTEPS = 3 };
+
+static float lerpf(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+static void tri_vec3(const float *field, int32_t n, const float q[3], float out[3])
+{
+    int32_t i0[3];
+    float f[3];
+    for (int a = 0; a < 3; ++a) {
+        float u = q[a] - 0.5f;
+        u = fminf(fmaxf(u, 0.0f), (float)(n - 1));
+        int32_t i = (int32_t)floorf(u);
+        if (i > n - 2) i = n - 2;
+        i0[a] = i;
+        f[a] = u - (float)i;
+    }
+#define FV(dx, dy, dz, comp) field[3 * ((size_t)(i0[0] + (dx)) + (size_t)n * ((size_t)(i0[1] + (dy)) + (size_t)n * (size_t)(i0[2] + (dz)))) + (comp)]
+    for (int comp = 0; comp < 3; ++comp) {
+        float x00 = lerpf(FV(0, 0, 0, comp), FV(1, 0, 0, comp), f[0]);
+        float x10 = lerpf(FV(0, 1, 0, comp), FV(1, 1, 0, comp), f[0]);
+        float x01 = lerpf(FV(0, 0, 1, comp), FV(1, 0, 1, comp), f[0]);
+        float x11 = lerpf(FV(0, 1, 1, comp), FV(1, 1, 1, comp), f[0]);
+        float y0 = lerpf(x00, x10, f[1]);
+        float y1 = lerpf(x01, x11, f[1]);
+        out[comp] = lerpf(y0, y1, f[2]);
+    }
+#undef FV
+}
+
+/* One RK4 step from p into pn. */
+static void rk4_step(const float *field, int32_t n, float h, const float p[3], float pn[3])
+{
+    const float hh = h * 0.5f;
+    const float h6 = (float)((double)h / 6.0);
+    float k1[3], k2[3], k3[3], k4[3], q[3];
+    tri_vec3(field, n, p, k1);
+    for (int a = 0; a < 3; ++a) q[a] = fmaf(hh, k1[a], p[a]);
+    tri_vec3(field, n, q, k2);
+    for (int a = 0; a < 3; ++a) q[a] = fmaf(hh, k2[a], p[a]);
+    tri_vec3(field, n, q, k3);
+    for (int a = 0; a < 3; ++a) q[a] = fmaf(h, k3[a], p[a]);
+    tri_vec3(field, n, q, k4);
+    for (int a = 0; a < 3; ++a) {
+        float s = fmaf(2.0f, k2[a], k1[a]);
+        s = fmaf(2.0f, k3[a], s);
+        s = s + k4[a];
+        pn[a] = fmaf(h6, s, p[a]);
+    }
+}
+
+typedef struct {
+    int32_t id;
+    int32_t steps;
+    float p[3];
+    int32_t pad;
+} orc_particle;
+
+/* Advance one particle inside brick d. Returns its destination; on finish
+ * sets *reason. With one_step set, at most one RK4 step is taken and a
+ * particle that stays inside d is forwarded to d itself (the paper's
+ * one-update-per-round form, Sec. 5.4). */
+static int32_t sl_advance(const float *field, const orc_sl_params *P, orc_particle *it,
+                          int32_t d, int one_step, int32_t *reason)
+{
+    for (;;) {
+        float pn[3];
+        rk4_step(field, P->n, P->h, it->p, pn);
+        it->steps++;
+        int same = memcmp(pn, it->p, sizeof(pn)) == 0;
+        memcpy(it->p, pn, sizeof(pn));
+        if (same) { *reason = ORC_SL_STAGNANT; return ORC_DONE; }
+        int32_t e = owner_of(pn, P->n, P->g);
+        if (e < 0) { *reason = ORC_SL_EXITED; return ORC_DONE; }
+        if (it->steps >= P->max_steps) { *reason = ORC_SL_MAXSTEPS; return ORC_DONE; }
+        if (e != d || one_step) return e;
+    }
+}
+
+/*
+ * O2 + O4: the streamline round loop. Round 0 sends every seed to its owning
+ * brick (seeds outside the field finish immediately with 0 steps, reason
+ * "exited"). Outputs per particle id: endpoint, step count, finish reason.
+ * round_counts / queue_log (particle ids) / visit_log as in oracle_ea_render.
+ */
+int oracle_streamlines(const float *field, const orc_sl_params *P, const float *seeds,
+                       int64_t n_seeds, int32_t one_step, float *endpoint, int32_t *steps,
+                       int32_t *reason, int32_t max_rounds, uint64_t *round_counts,
+                       int32_t *queue_log, uint64_t queue_cap, uint64_t *queue_len,
+                       int32_t *visit_log, int32_t visit_stride)
+{
+    const int32_t D = P->g[0] * P->g[1] * P->g[2];
+    size_t cap = (size_t)(n_seeds ? n_seeds : 1);
+    orc_particle *O = (orc_particle *)malloc(sizeof(orc_particle) * cap);
+    orc_particle *Q = (orc_particle *)malloc(sizeof(orc_particle) * cap);
+    int32_t *odest = (int32_t *)malloc(sizeof(int32_t) * cap);
+    uint64_t *counts = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)D);
+    uint64_t *offs = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(D + 1));
+    int32_t *nvis = (int32_t *)calloc(cap, sizeof(int32_t));
+    if (!O || !Q || !odest || !counts || !offs || !nvis) return -2;
+    if (visit_log)
+        for (int64_t i = 0; i < n_seeds * visit_stride; ++i) visit_log[i] = -1;
+    uint64_t qlen = 0, n_out = 0;
+
+    for (int64_t i = 0; i < n_seeds; ++i) {
+        orc_particle it;
+        memset(&it, 0, sizeof(it));
+        it.id = (int32_t)i;
+        memcpy(it.p, seeds + 3 * i, sizeof(it.p));
+        int32_t e = owner_of(it.p, P->n, P->g);
+        O[n_out] = it;
+        odest[n_out] = e;
+        n_out++;
+        if (e < 0) {
+            memcpy(endpoint + 3 * i, it.p, sizeof(it.p));
+            steps[i] = 0;
+            if (reason) reason[i] = ORC_SL_EXITED;
+        }
+    }
+    int32_t rounds = 0;
+    for (;;) {
+        oracle_multisplit(n_out, (uint32_t)sizeof(orc_particle), (const uint8_t *)O, odest, D,
+                          (uint8_t *)Q, counts, offs, NULL, NULL);
+        uint64_t total = offs[D];
+        if (rounds >= max_rounds) { rounds = -6; break; }
+        if (round_counts)
+            for (int32_t e = 0; e < D; ++e) round_counts[(size_t)rounds * D + e] = counts[e];
+        for (uint64_t i = 0; i < total; ++i) {
+            if (queue_log && qlen < queue_cap) queue_log[qlen] = Q[i].id;
+            qlen++;
+        }
+        for (int32_t d = 0; d < D; ++d)
+            for (uint64_t i = offs[d]; i < offs[d + 1]; ++i) {
+                int32_t id = Q[i].id;
+                if (visit_log && nvis[id] < visit_stride) visit_log[(size_t)id * visit_stride + nvis[id]] = d;
+                nvis[id]++;
+            }
+        rounds++;
+        if (total == 0) break;
+        n_out = 0;
+        for (int32_t d = 0; d < D; ++d) {
+            for (uint64_t i = offs[d]; i < offs[d + 1]; ++i) {
+                orc_particle it = Q[i];
+                int32_t why = ORC_SL_LIVE;
+                int32_t e = sl_advance(field, P, &it, d, one_step, &why);
+                O[n_out] = it;
+                odest[n_out] = e;
+                n_out++;
+                if (e == ORC_DONE) {
+                    memcpy(endpoint + 3 * (size_t)it.id, it.p, sizeof(it.p));
+                    steps[it.id] = it.steps;
+                    if (reason) reason[it.id] = why;
+                }
+            }
+        }
+    }
+    if (queue_len) *queue_len = qlen;
+    free(O); free(Q); free(odest); free(counts); free(offs); free(nvis);
+    return rounds;
+}
+
+/* Unpartitioned brute force: integrate every seed to completion without ever
+ * forwarding; the visit sequence is the run-length-compressed owner sequence
+ * of the positions the particle occupies between steps. */
+int oracle_streamlines_brute(const float *field, const orc_sl_params *P, const float *seeds,
+                             int64_t n_seeds, float *endpoint, int32_t *steps, int32_t *reason,
+                             int32_t *visit_log, int32_t visit_stride)
+{
+    for (int64_t i = 0; i < n_seeds; ++i) {
+        float p[3];
+        memcpy(p, seeds + 3 * i, sizeof(p));
+        int32_t st = 0, why = ORC_SL_LIVE, nv = 0;
+        if (visit_log)
+            for (int32_t s = 0; s < visit_stride; ++s) visit_log[(size_t)i * visit_stride + s] = -1;
+        int32_t e = owner_of(p, P->n, P->g);
+        if (e < 0) why = ORC_SL_EXITED;
+        int32_t last = -2;
+        while (why == ORC_SL_LIVE) {
+            if (e != last) {
+                if (visit_log && nv < visit_stride) visit_log[(size_t)i * visit_stride + nv] = e;
+                nv++;
+                last = e;
+            }
+            float pn[3];
+            rk4_step(field, P->n, P->h, p, pn);
+            st++;
+            int same = memcmp(pn, p, sizeof(pn)) == 0;
+            memcpy(p, pn, sizeof(p));
+            if (same) { why = ORC_SL_STAGNANT; break; }
+            e = owner_of(p, P->n, P->g);
+            if (e < 0) { why = ORC_SL_EXITED; break; }
+            if (st >= P->max_steps) { why = ORC_SL_MAXSTEPS; break; }
+        }
+        memcpy(endpoint + 3 * i, p, sizeof(p));
+        steps[i] = st;
+        if (reason) reason[i] = why;
+    }
+    return 0;
+}
