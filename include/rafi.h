@@ -1,0 +1,280 @@
+/*
+ * rafi.h -- host C ABI of the single-GPU work-forwarding library (librafi.so).
+ *
+ * The library follows the forwarding model of RaFI (arXiv 2605.30294):
+ * application kernels read work items from an input queue and emit each item
+ * with a destination domain (Sec. 3.2, 3.3); a forward step then regroups the
+ * emitted items by destination and hands every domain its new input queue,
+ * returning the number of items still alive (Sec. 3.4, 4.2). Here all domains
+ * live on one GPU, so the forward step is a device-local stable multi-split.
+ *
+ * Conventions for every call below:
+ *   - Pointers documented as "device" are HIP device allocations the caller
+ *     owns; "host" pointers are ordinary host memory. No call takes ownership
+ *     of caller memory. A context owns its queues (Sec. 3.2: the library
+ *     manages the arrays itself once told their capacity).
+ *   - Work is stream-ordered on the context's stream (rafi_set_stream;
+ *     default: the null stream). Calls that return host-visible results
+ *     (rafi_round's counts and total) synchronise that stream.
+ *   - A context is not thread-safe: one host thread per context.
+ *   - Every int-returning call returns RAFI_OK (0) or a negative RAFI_ERR_*
+ *     code; rafi_strerror() names it. On RAFI_ERR_ARG nothing was launched.
+ *
+ * The device-side half (reading inputs and emitting items from a kernel) is
+ * in rafi_device.h.
+ */
+#ifndef RAFI_H
+#define RAFI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    RAFI_OK = 0,
+    RAFI_ERR_ARG = -1,        /* invalid argument; nothing was done */
+    RAFI_ERR_OOM = -2,        /* device allocation failed */
+    RAFI_ERR_HIP = -3,        /* a HIP runtime call failed */
+    RAFI_ERR_OVERFLOW = -4,   /* emits beyond the slot range were dropped (Sec. 3.3) */
+    RAFI_ERR_BAD_DEST = -5,   /* slots carried a destination outside {-1} U [0, n_domains) */
+    RAFI_ERR_MAX_ROUNDS = -6, /* a driver loop hit its round limit with items still alive */
+    RAFI_ERR_STATE = -7       /* call not valid in the context's current state */
+};
+
+/* Destination of an item that leaves the system (the -1 of Sec. 3.2). */
+#define RAFI_DONE (-1)
+/* Destination pre-filled into unwritten slots in debug mode. */
+#define RAFI_POISON (-2)
+
+/* Largest number of domains one context or split supports. */
+#define RAFI_MAX_DOMAINS 8192
+/* Largest item size in bytes (items are copied as 4-byte words). */
+#define RAFI_MAX_ITEM_BYTES 256
+
+typedef struct rafi_ctx rafi_ctx;
+
+/*
+ * Plain-old-data view of a context's queues, passed by value to kernels
+ * (the device interface of Sec. 3.3). Valid until the next rafi_round,
+ * rafi_begin or rafi_resize on the context.
+ *
+ * Input queue: n_in items; those of domain d are items
+ *   [in_offsets[d], in_offsets[d+1]) of in_items, in forward order.
+ * Output: n_slots slots. The kernel that handles input item i owns slot i
+ *   and writes it exactly once, with rafi_forward or rafi_done (slot-ordered
+ *   emission: the destination order within a domain is then deterministic).
+ * in_tile_offsets[d] is the index of domain d's first tile when every
+ *   domain's items are cut into tiles of tile_items; in_tile_offsets[D] is
+ *   the number of tiles (a launch grid for domain-pure workgroups).
+ */
+typedef struct rafi_device_view {
+    const void *in_items;             /* device */
+    const uint64_t *in_offsets;       /* device [n_domains + 1] */
+    const uint32_t *in_tile_offsets;  /* device [n_domains + 1] */
+    void *out_items;                  /* device [capacity * item_bytes] */
+    int32_t *out_dest;                /* device [capacity] */
+    unsigned long long *dropped;      /* device counter of emits to slots >= n_slots */
+    uint64_t n_in;                    /* number of input items */
+    uint64_t n_slots;                 /* output slots the next rafi_round consumes */
+    uint64_t capacity;                /* queue capacity in items */
+    uint32_t item_bytes;
+    int32_t n_domains;
+    uint32_t tile_items;
+    uint32_t n_tiles;                 /* host copy of in_tile_offsets[n_domains] */
+} rafi_device_view;
+
+typedef struct rafi_stats {
+    uint64_t rounds;     /* rafi_round calls since creation */
+    uint64_t forwarded;  /* items delivered to a domain queue, summed over rounds */
+    uint64_t done;       /* slots that carried RAFI_DONE */
+    uint64_t bad_dest;   /* slots with an invalid destination (poison included) */
+    uint64_t dropped;    /* emits to a slot outside [0, n_slots) */
+    uint64_t last_total; /* total returned by the last rafi_round */
+} rafi_stats;
+
+/*
+ * Create a context for n_domains domains of items of item_bytes bytes, with
+ * queues of `capacity` items (host context creation + resizeRayQueues,
+ * Sec. 3.4). n_domains in [1, RAFI_MAX_DOMAINS]; item_bytes a multiple of 4
+ * in [4, RAFI_MAX_ITEM_BYTES]; capacity in [1, 2^32 - 1]. Allocates two
+ * item buffers, the destination array and the split workspace on the current
+ * HIP device. *out receives the context (NULL on failure).
+ */
+int rafi_create(int32_t n_domains, uint32_t item_bytes, uint64_t capacity, rafi_ctx **out);
+
+/* Free a context and everything it allocated. NULL is ignored. */
+void rafi_destroy(rafi_ctx *ctx);
+
+/* Change the queue capacity (resizeRayQueues, Sec. 3.4). Drops the current
+ * queue contents. */
+int rafi_resize(rafi_ctx *ctx, uint64_t capacity);
+
+/* Stream for all later work on this context (a hipStream_t, passed as void*).
+ * The stream must outlive its use by the context. */
+int rafi_set_stream(rafi_ctx *ctx, void *hip_stream);
+
+/* Debug mode: when on, every rafi_begin/rafi_round pre-fills the output
+ * destinations with RAFI_POISON, so slots a kernel never wrote are counted
+ * as bad destinations. */
+int rafi_set_debug(rafi_ctx *ctx, int32_t on);
+
+/* Tile size used to build in_tile_offsets (default 256; any value >= 1). */
+int rafi_set_tile_items(rafi_ctx *ctx, uint32_t tile_items);
+
+/* Fill *out with the current device view (getDeviceInterface, Sec. 3.4). */
+int rafi_view(const rafi_ctx *ctx, rafi_device_view *out);
+
+/* Start a new wave of work: empty the input queue and open n_slots output
+ * slots (n_slots <= capacity) for a generator kernel (ray generation /
+ * seeding) that emits into slots [0, n_slots). */
+int rafi_begin(rafi_ctx *ctx, uint64_t n_slots);
+
+/*
+ * Forward step (forwardRays, Sec. 3.4 and 4.2): stable multi-split of the
+ * n_slots output slots by destination into the next input queue. An item
+ * with destination e lands at in_offsets[e] + (number of earlier slots with
+ * destination e). RAFI_DONE slots leave the system; slots with invalid
+ * destinations are dropped and counted. Afterwards n_slots = n_in = total.
+ *   counts: host [n_domains] items per domain, or NULL.
+ *   total:  host, items now alive (the distributed-termination total, Sec. 4.2.3), or NULL.
+ * Synchronises the context stream. Returns RAFI_ERR_BAD_DEST or
+ * RAFI_ERR_OVERFLOW (after completing the split) if such slots occurred in
+ * this round.
+ */
+int rafi_round(rafi_ctx *ctx, uint64_t *counts, uint64_t *total);
+
+/* Copy the current input queue (n_in items, device-to-device, stream-ordered)
+ * into items_dst (device, >= n_in * item_bytes bytes) and its per-domain
+ * offsets into offsets_dst (device, n_domains + 1 uint64); either may be NULL. */
+int rafi_copy_queue(const rafi_ctx *ctx, void *items_dst, uint64_t *offsets_dst);
+
+/* Cumulative statistics (host copy, updated by rafi_round). */
+int rafi_get_stats(const rafi_ctx *ctx, rafi_stats *out);
+
+/* Static string naming an error code. */
+const char *rafi_strerror(int code);
+
+/*
+ * Stateless split (the forward step without a context). items: device
+ * [n * item_bytes]; dest: device [n]; out: device [n * item_bytes], receives
+ * the kept items grouped by destination, stable; offsets: device
+ * [n_domains + 1] uint64 exclusive prefix of the per-destination counts;
+ * summary: device [4] uint64 = {total kept, done, bad, 0}. workspace: device,
+ * at least rafi_multisplit_workspace() bytes. item_bytes, n_domains as for
+ * rafi_create; n < 2^32. Follows Sec. 4.2.1-4.2.2.
+ */
+int rafi_multisplit_workspace(uint64_t n, int32_t n_domains, uint32_t item_bytes,
+                              uint64_t *bytes);
+int rafi_multisplit(const void *items, const int32_t *dest, uint64_t n, uint32_t item_bytes,
+                    int32_t n_domains, void *out, uint64_t *offsets, uint64_t *summary,
+                    void *workspace, uint64_t workspace_bytes, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Emission-absorption volume ray march over bricked domains (the
+ * march-and-forward pattern of Sec. 5.1-5.3).
+ *
+ * Volume: n^3 float32 densities at voxel centres (i + 1/2), x fastest, split
+ * into grid[0] x grid[1] x grid[2] bricks of n/grid[a] voxels (domain id
+ * bx + grid0*(by + grid1*bz); a point on a brick plane belongs to the upper
+ * brick). Ray (px, py) of view v starts at org = org0 + py*dv + px*du
+ * (computed as fma(py, dv, fma(px, du, org0))) and sample k sits at
+ * p_k = fma((k + 1/2) dt, dir, org), k < n_samples. With rho_k the trilinear
+ * (clamp-to-edge) density at p_k and sigma_k = c rho_k,
+ *   I = sum over inside samples of exp(-tau_k) (1 - exp(-sigma_k)) rho_k,
+ *   tau_k = sum_{j<k} sigma_j.
+ * Each brick advances its rays while their samples stay inside it and then
+ * forwards them to the owner of the next sample, or finishes them.
+ * ------------------------------------------------------------------------ */
+typedef struct rafi_ortho_view {
+    float org0[3], du[3], dv[3], dir[3];
+    int32_t width, height, n_samples, pad;
+} rafi_ortho_view; /* 64 bytes */
+
+typedef struct rafi_ea_job {
+    const float *volume;            /* device [n^3] */
+    const rafi_ortho_view *views;   /* device [n_views], all width x height */
+    float *image;                   /* device [n_views * height * width] result per ray */
+    float *tau;                     /* device, optional: final optical depth per ray */
+    int32_t *klast;                 /* device, optional: one past the last inside sample */
+    int32_t n;
+    int32_t grid[3];
+    int32_t n_views, width, height;
+    float dt;                       /* sample spacing along the ray */
+    float c;                        /* extinction per unit density per sample (kappa * dt) */
+    int32_t pad;
+} rafi_ea_job;
+
+/* Item size a context needs for the march (16 bytes: ray id, next sample,
+ * optical depth, partial integral). */
+#define RAFI_EA_ITEM_BYTES 16
+
+/* Ray generation (round 0): opens one slot per ray (rafi_begin) and emits
+ * every ray to the owner of its first inside sample; rays that miss the
+ * volume finish with image = 0. The context needs n_domains = grid volume,
+ * item_bytes = RAFI_EA_ITEM_BYTES, capacity >= number of rays. */
+int rafi_ea_raygen(rafi_ctx *ctx, const rafi_ea_job *job);
+
+/* One domain-kernel launch: every input item advances through its brick and
+ * is forwarded or finished (result written to job->image). */
+int rafi_ea_march(rafi_ctx *ctx, const rafi_ea_job *job);
+
+/* Whole render: raygen, then rafi_round / rafi_ea_march until no item is
+ * left. *rounds receives the number of forward steps taken. */
+int rafi_ea_render(rafi_ctx *ctx, const rafi_ea_job *job, int32_t max_rounds, int32_t *rounds);
+
+/* ------------------------------------------------------------------------
+ * RK4 streamlines over bricked domains (particle tracing, Sec. 5.4).
+ *
+ * Field: n^3 float32 velocity triples at voxel centres, x fastest, in voxels
+ * per unit time; packed once by rafi_sl_pack into a 16-byte-per-voxel copy.
+ * Step: k1 = V(p), k2 = V(p + h/2 k1), k3 = V(p + h/2 k2), k4 = V(p + h k3),
+ * p' = fma(h/6, fma(2,k3,fma(2,k2,k1)) + k4, p), componentwise, V trilinear
+ * with clamp-to-edge (lerp x, then y, then z; lerp(a,b,t) = fma(t,b-a,a)).
+ * A particle finishes when a step leaves it bitwise unchanged (stagnant), when
+ * it leaves the box [0,n)^3 (exited), or at max_steps; otherwise it is
+ * forwarded when it crosses into another brick.
+ * ------------------------------------------------------------------------ */
+typedef struct rafi_sl_job {
+    const float *field4;   /* device [n^3 * 4] packed field from rafi_sl_pack */
+    float *endpoint;       /* device [n_seeds * 3] final position per particle id */
+    int32_t *steps;        /* device [n_seeds] steps taken */
+    int32_t *reason;       /* device [n_seeds] 1 stagnant, 2 exited, 3 max steps; optional */
+    int32_t n;
+    int32_t grid[3];
+    float h;
+    int32_t max_steps;
+} rafi_sl_job;
+
+/* Item: position (3 x float32) and particle id; the step count lives in
+ * job->steps[id] between visits. */
+#define RAFI_SL_ITEM_BYTES 16
+#define RAFI_SL_STAGNANT 1
+#define RAFI_SL_EXITED 2
+#define RAFI_SL_MAXSTEPS 3
+
+/* Repack field [n^3 * 3] (device) into field4 [n^3 * 4] (device). */
+int rafi_sl_pack(const float *field, int32_t n, float *field4, void *hip_stream);
+
+/* Round 0: opens one slot per seed and emits seed i (id i, position
+ * seeds[3i..3i+2], device) to its owning brick. */
+int rafi_sl_seed(rafi_ctx *ctx, const rafi_sl_job *job, const float *seeds, uint64_t n_seeds);
+
+/* One domain-kernel launch: every particle integrates until it leaves its
+ * brick or finishes. With one_step != 0 it takes exactly one step and is
+ * forwarded even to its own brick (the one-update-per-round form). */
+int rafi_sl_advance(rafi_ctx *ctx, const rafi_sl_job *job, int32_t one_step);
+
+/* Whole trace: seed, then rafi_round / rafi_sl_advance until no particle is
+ * left. *rounds receives the number of forward steps; *forwarded (optional)
+ * the number of items delivered over all forward steps. */
+int rafi_sl_trace(rafi_ctx *ctx, const rafi_sl_job *job, const float *seeds, uint64_t n_seeds,
+                  int32_t max_rounds, int32_t *rounds, uint64_t *forwarded);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAFI_H */

@@ -1,0 +1,298 @@
+// Host context: queue ownership, the device view and the forward step
+// (Sec. 3.4 of the paper: create a context, size its queues, hand kernels a
+// device interface, call forwardRays() between kernel launches).
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace rafi {
+namespace {
+
+__global__ void fill_i32_kernel(int32_t *p, uint64_t n, int32_t v)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Empty queue: offsets, tile offsets and summary all zero; dropped counter reset.
+__global__ void reset_kernel(uint64_t *offsets, uint32_t *tile_offsets, int32_t D, uint64_t *summary,
+                             unsigned long long *dropped)
+{
+    for (int32_t e = threadIdx.x; e <= D; e += blockDim.x) {
+        offsets[e] = 0;
+        tile_offsets[e] = 0;
+    }
+    if (threadIdx.x < 4) summary[threadIdx.x] = 0;
+    if (threadIdx.x == 0) *dropped = 0;
+}
+
+__global__ void clear_dropped_kernel(unsigned long long *dropped) { *dropped = 0; }
+
+bool valid_shape(int32_t D, uint32_t S)
+{
+    return D >= 1 && D <= RAFI_MAX_DOMAINS && S >= 4 && S <= RAFI_MAX_ITEM_BYTES && S % 4 == 0;
+}
+
+void free_queues(rafi_ctx *c)
+{
+    for (void *&b : c->buf) {
+        if (b) (void)hipFree(b);
+        b = nullptr;
+    }
+    if (c->dest) (void)hipFree(c->dest);
+    if (c->ws) (void)hipFree(c->ws);
+    c->dest = nullptr;
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+}
+
+int alloc_queues(rafi_ctx *c, uint64_t cap)
+{
+    const SplitPlan p = split_plan_bound(cap, c->D, c->S);
+    if (hipMalloc(&c->buf[0], cap * c->S) != hipSuccess || hipMalloc(&c->buf[1], cap * c->S) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&c->dest), cap * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&c->ws, p.bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        free_queues(c);
+        return RAFI_ERR_OOM;
+    }
+    c->ws_bytes = p.bytes;
+    c->cap = cap;
+    return RAFI_OK;
+}
+
+int empty_queue(rafi_ctx *c)
+{
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(1024), 0, c->stream, c->offsets, c->tile_offsets, c->D,
+                       c->summary, c->dropped);
+    RAFI_LAUNCH_CHECK();
+    c->n_in = 0;
+    c->n_tiles = 0;
+    return RAFI_OK;
+}
+
+}  // namespace
+
+int ctx_fill_poison(rafi_ctx *c, uint64_t n)
+{
+    if (!c->debug || n == 0) return RAFI_OK;
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(blocks), dim3(256), 0, c->stream, c->dest, n, RAFI_POISON);
+    RAFI_LAUNCH_CHECK();
+    return RAFI_OK;
+}
+
+}  // namespace rafi
+
+using namespace rafi;
+
+extern "C" {
+
+const char *rafi_strerror(int code)
+{
+    switch (code) {
+    case RAFI_OK: return "ok";
+    case RAFI_ERR_ARG: return "invalid argument";
+    case RAFI_ERR_OOM: return "out of device memory";
+    case RAFI_ERR_HIP: return "HIP runtime error";
+    case RAFI_ERR_OVERFLOW: return "emits beyond the slot range were dropped";
+    case RAFI_ERR_BAD_DEST: return "slots with an invalid destination were dropped";
+    case RAFI_ERR_MAX_ROUNDS: return "round limit reached with items still alive";
+    case RAFI_ERR_STATE: return "call not valid in the current state";
+    default: return "unknown error";
+    }
+}
+
+int rafi_create(int32_t n_domains, uint32_t item_bytes, uint64_t capacity, rafi_ctx **out)
+{
+    if (!out) return RAFI_ERR_ARG;
+    *out = nullptr;
+    if (!valid_shape(n_domains, item_bytes) || capacity == 0 || capacity >= (1ull << 32)) return RAFI_ERR_ARG;
+    rafi_ctx *c = new (std::nothrow) rafi_ctx();
+    if (!c) return RAFI_ERR_OOM;
+    c->D = n_domains;
+    c->S = item_bytes;
+    RAFI_HIP_CHECK(hipGetDevice(&c->device));
+    int rc = alloc_queues(c, capacity);
+    if (rc == RAFI_OK &&
+        (hipMalloc(reinterpret_cast<void **>(&c->offsets), sizeof(uint64_t) * (n_domains + 1)) != hipSuccess ||
+         hipMalloc(reinterpret_cast<void **>(&c->tile_offsets), sizeof(uint32_t) * (n_domains + 1)) != hipSuccess ||
+         hipMalloc(reinterpret_cast<void **>(&c->summary), sizeof(uint64_t) * 4) != hipSuccess ||
+         hipMalloc(reinterpret_cast<void **>(&c->dropped), sizeof(unsigned long long)) != hipSuccess ||
+         hipHostMalloc(reinterpret_cast<void **>(&c->host_summary), sizeof(uint64_t) * 8, hipHostMallocDefault) != hipSuccess))
+        rc = RAFI_ERR_OOM;
+    if (rc == RAFI_OK) rc = empty_queue(c);
+    if (rc == RAFI_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = RAFI_ERR_HIP;
+    if (rc != RAFI_OK) {
+        (void)hipGetLastError();
+        rafi_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return RAFI_OK;
+}
+
+void rafi_destroy(rafi_ctx *c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_queues(c);
+    if (c->offsets) (void)hipFree(c->offsets);
+    if (c->tile_offsets) (void)hipFree(c->tile_offsets);
+    if (c->summary) (void)hipFree(c->summary);
+    if (c->dropped) (void)hipFree(c->dropped);
+    if (c->host_summary) (void)hipHostFree(c->host_summary);
+    delete c;
+}
+
+int rafi_resize(rafi_ctx *c, uint64_t capacity)
+{
+    if (!c || capacity == 0 || capacity >= (1ull << 32)) return RAFI_ERR_ARG;
+    RAFI_HIP_CHECK(hipStreamSynchronize(c->stream));
+    free_queues(c);
+    int rc = alloc_queues(c, capacity);
+    if (rc != RAFI_OK) return rc;
+    c->n_slots = 0;
+    return empty_queue(c);
+}
+
+int rafi_set_stream(rafi_ctx *c, void *hip_stream)
+{
+    if (!c) return RAFI_ERR_ARG;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    return RAFI_OK;
+}
+
+int rafi_set_debug(rafi_ctx *c, int32_t on)
+{
+    if (!c) return RAFI_ERR_ARG;
+    c->debug = on ? 1 : 0;
+    return RAFI_OK;
+}
+
+int rafi_set_tile_items(rafi_ctx *c, uint32_t tile_items)
+{
+    if (!c || tile_items == 0) return RAFI_ERR_ARG;
+    c->tile_items = tile_items;
+    return RAFI_OK;
+}
+
+int rafi_view(const rafi_ctx *c, rafi_device_view *v)
+{
+    if (!c || !v) return RAFI_ERR_ARG;
+    v->in_items = c->buf[0];
+    v->in_offsets = c->offsets;
+    v->in_tile_offsets = c->tile_offsets;
+    v->out_items = c->buf[1];
+    v->out_dest = c->dest;
+    v->dropped = c->dropped;
+    v->n_in = c->n_in;
+    v->n_slots = c->n_slots;
+    v->capacity = c->cap;
+    v->item_bytes = c->S;
+    v->n_domains = c->D;
+    v->tile_items = c->tile_items;
+    v->n_tiles = c->n_tiles;
+    return RAFI_OK;
+}
+
+int rafi_begin(rafi_ctx *c, uint64_t n_slots)
+{
+    if (!c || n_slots > c->cap) return RAFI_ERR_ARG;
+    int rc = empty_queue(c);
+    if (rc != RAFI_OK) return rc;
+    c->n_slots = n_slots;
+    c->wave_slots = n_slots;
+    return ctx_fill_poison(c, n_slots);
+}
+
+int rafi_round(rafi_ctx *c, uint64_t *counts, uint64_t *total)
+{
+    if (!c) return RAFI_ERR_ARG;
+    const SplitPlan p = split_plan(c->n_slots, c->D, c->S);
+    if (p.bytes > c->ws_bytes) return RAFI_ERR_STATE;
+    int rc = split_run(p, c->buf[1], c->dest, c->buf[0], c->offsets, c->summary, c->tile_offsets,
+                       c->tile_items, c->ws, c->stream);
+    if (rc != RAFI_OK) return rc;
+    RAFI_HIP_CHECK(hipMemcpyAsync(c->host_summary, c->summary, sizeof(uint64_t) * 4, hipMemcpyDeviceToHost,
+                                  c->stream));
+    RAFI_HIP_CHECK(hipMemcpyAsync(c->host_summary + 4, c->dropped, sizeof(uint64_t), hipMemcpyDeviceToHost,
+                                  c->stream));
+    hipLaunchKernelGGL(clear_dropped_kernel, dim3(1), dim3(1), 0, c->stream, c->dropped);
+    RAFI_LAUNCH_CHECK();
+    if (counts) {
+        uint64_t *tmp = static_cast<uint64_t *>(std::malloc(sizeof(uint64_t) * (c->D + 1)));
+        if (!tmp) return RAFI_ERR_OOM;
+        hipError_t e = hipMemcpyAsync(tmp, c->offsets, sizeof(uint64_t) * (c->D + 1), hipMemcpyDeviceToHost,
+                                      c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess)
+            for (int32_t d = 0; d < c->D; ++d) counts[d] = tmp[d + 1] - tmp[d];
+        std::free(tmp);
+        RAFI_HIP_CHECK(e);
+    } else {
+        RAFI_HIP_CHECK(hipStreamSynchronize(c->stream));
+    }
+    const uint64_t *h = c->host_summary;
+    c->n_in = h[0];
+    c->n_slots = h[0];
+    c->n_tiles = (uint32_t)h[3];
+    c->stats.rounds++;
+    c->stats.forwarded += h[0];
+    c->stats.done += h[1];
+    c->stats.bad_dest += h[2];
+    c->stats.dropped += h[4];
+    c->stats.last_total = h[0];
+    if (total) *total = h[0];
+    rc = ctx_fill_poison(c, c->n_slots);
+    if (rc != RAFI_OK) return rc;
+    if (h[2]) return RAFI_ERR_BAD_DEST;
+    if (h[4]) return RAFI_ERR_OVERFLOW;
+    return RAFI_OK;
+}
+
+int rafi_copy_queue(const rafi_ctx *c, void *items_dst, uint64_t *offsets_dst)
+{
+    if (!c) return RAFI_ERR_ARG;
+    if (items_dst && c->n_in)
+        RAFI_HIP_CHECK(hipMemcpyAsync(items_dst, c->buf[0], c->n_in * c->S, hipMemcpyDeviceToDevice, c->stream));
+    if (offsets_dst)
+        RAFI_HIP_CHECK(hipMemcpyAsync(offsets_dst, c->offsets, sizeof(uint64_t) * (c->D + 1),
+                                      hipMemcpyDeviceToDevice, c->stream));
+    return RAFI_OK;
+}
+
+int rafi_get_stats(const rafi_ctx *c, rafi_stats *out)
+{
+    if (!c || !out) return RAFI_ERR_ARG;
+    *out = c->stats;
+    return RAFI_OK;
+}
+
+int rafi_multisplit_workspace(uint64_t n, int32_t n_domains, uint32_t item_bytes, uint64_t *bytes)
+{
+    if (!bytes || !valid_shape(n_domains, item_bytes) || n >= (1ull << 32)) return RAFI_ERR_ARG;
+    *bytes = split_plan(n, n_domains, item_bytes).bytes;
+    return RAFI_OK;
+}
+
+int rafi_multisplit(const void *items, const int32_t *dest, uint64_t n, uint32_t item_bytes, int32_t n_domains,
+                    void *out, uint64_t *offsets, uint64_t *summary, void *workspace, uint64_t workspace_bytes,
+                    void *hip_stream)
+{
+    if (!valid_shape(n_domains, item_bytes) || n >= (1ull << 32) || !offsets || !summary) return RAFI_ERR_ARG;
+    if (n && (!items || !dest || !out || !workspace)) return RAFI_ERR_ARG;
+    // 16-byte alignment for the vector paths (device allocations always have it)
+    if ((reinterpret_cast<uintptr_t>(items) | reinterpret_cast<uintptr_t>(out) |
+         reinterpret_cast<uintptr_t>(dest) | reinterpret_cast<uintptr_t>(workspace)) & 15)
+        return RAFI_ERR_ARG;
+    const SplitPlan p = split_plan(n, n_domains, item_bytes);
+    if (workspace_bytes < p.bytes) return RAFI_ERR_ARG;
+    return split_run(p, items, dest, out, offsets, summary, nullptr, 1, workspace,
+                     static_cast<hipStream_t>(hip_stream));
+}
+
+}  // extern "C"

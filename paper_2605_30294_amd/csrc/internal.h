@@ -1,0 +1,87 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+
+#include "rafi.h"
+
+#define RAFI_HIP_CHECK(expr)                                                        \
+    do {                                                                            \
+        hipError_t rafi_e_ = (expr);                                                \
+        if (rafi_e_ != hipSuccess) {                                                \
+            std::fprintf(stderr, "librafi: %s failed: %s (%s:%d)\n", #expr,         \
+                         hipGetErrorString(rafi_e_), __FILE__, __LINE__);           \
+            return RAFI_ERR_HIP;                                                    \
+        }                                                                           \
+    } while (0)
+
+#define RAFI_LAUNCH_CHECK()                                                         \
+    do {                                                                            \
+        hipError_t rafi_e_ = hipGetLastError();                                     \
+        if (rafi_e_ != hipSuccess) {                                                \
+            std::fprintf(stderr, "librafi: launch failed: %s (%s:%d)\n",            \
+                         hipGetErrorString(rafi_e_), __FILE__, __LINE__);           \
+            return RAFI_ERR_HIP;                                                    \
+        }                                                                           \
+    } while (0)
+
+namespace rafi {
+
+// ------------------------------------------------------------ split plan ---
+// The forward step runs as: per-tile destination histogram -> exclusive scan
+// over the (destination-major, tile-minor) count table -> stable scatter.
+struct SplitPlan {
+    uint64_t n = 0;          // slots
+    int32_t D = 0;           // domains
+    uint32_t S = 0;          // item bytes
+    uint32_t tile = 0;       // slots per tile
+    uint32_t n_tiles = 0;
+    uint64_t rows = 0;       // D + 2 (domains, done, bad)
+    uint64_t M = 0;          // rows * n_tiles table entries
+    uint32_t scan_blocks = 0;
+    uint64_t off_table = 0, off_part = 0, bytes = 0;  // workspace layout
+};
+
+SplitPlan split_plan(uint64_t n, int32_t D, uint32_t S);
+// A plan whose workspace covers every n <= cap.
+SplitPlan split_plan_bound(uint64_t cap, int32_t D, uint32_t S);
+
+// Run the split. offsets: device u64 [D+1]; summary: device u64 [4]
+// {total, done, bad, n_tiles_app}; tile_offsets (optional): device u32 [D+1]
+// built for tiles of tile_items.
+int split_run(const SplitPlan &p, const void *items, const int32_t *dest, void *out,
+              uint64_t *offsets, uint64_t *summary, uint32_t *tile_offsets, uint32_t tile_items,
+              void *workspace, hipStream_t stream);
+
+}  // namespace rafi
+
+// ------------------------------------------------------------- context ---
+struct rafi_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int32_t D = 0;
+    uint32_t S = 0;
+    uint64_t cap = 0;
+    void *buf[2] = {nullptr, nullptr};
+    int cur_in = 0;                     // buf[cur_in] is the input queue
+    int32_t *dest = nullptr;            // [cap]
+    uint64_t *offsets = nullptr;        // [D+1]
+    uint32_t *tile_offsets = nullptr;   // [D+1]
+    uint64_t *summary = nullptr;        // [4] device
+    unsigned long long *dropped = nullptr;  // device counter
+    uint64_t *host_summary = nullptr;   // pinned [8]
+    void *ws = nullptr;
+    uint64_t ws_bytes = 0;
+    uint64_t n_in = 0, n_slots = 0;
+    uint64_t wave_slots = 0;            // n_slots of the last rafi_begin (item ids stay below it)
+    uint32_t tile_items = 256, n_tiles = 0;
+    int debug = 0;
+    rafi_stats stats{};
+};
+
+namespace rafi {
+int ctx_fill_poison(rafi_ctx *ctx, uint64_t n);
+}

@@ -1,0 +1,413 @@
+// Stable multi-split by destination: the forward step of the library.
+//
+// What it computes (Sec. 4.2.1-4.2.2 of the paper, collapsed to one device):
+// slot i with destination e in [0, D) lands at
+//     offset[e] + #{ j < i : dest[j] == e },
+// offset[] being the exclusive prefix of the per-destination counts; slots
+// with RAFI_DONE leave, slots with any other out-of-range value are dropped;
+// both are counted. The paper reaches the same placement with a radix sort of
+// (dest << 32 | i) keys, a gather and a begin/end tally; here it is three
+// HBM-streaming passes:
+//
+//   1. hist    per tile of T slots, a destination histogram (LDS atomics),
+//              written destination-major: table[e * n_tiles + tile].
+//   2. scan    one exclusive scan over the flattened table. Entry
+//              (e, tile) then holds the output position of the tile's first
+//              item bound for e, and row starts are the offsets.
+//   3. scatter per tile, each wavefront owns a contiguous quarter; per-wave
+//              counts give each wave its base per destination, and inside a
+//              wave the rank of a lane among same-destination lanes comes from
+//              a ballot match over the destination bits. Items are copied as
+//              4-byte words (16-byte vectors when the size allows).
+#include "internal.h"
+
+#include <algorithm>
+
+namespace rafi {
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 16;                       // elements per thread
+constexpr int kScanChunk = kScanThreads * kScanPer;  // 4096
+constexpr int kPartThreads = 1024;
+constexpr int kPartMax = kPartThreads * kScanPer;  // 16384 partial sums
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive block scan; lds needs NT/64 + 1 words. Returns the exclusive
+// prefix of v and the block total in *total.
+template <int NT>
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *lds, uint32_t *total)
+{
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    uint32_t incl = wave_incl_scan(v);
+    if (lane == 63) lds[wave] = incl;
+    __syncthreads();
+    if (tid < 64) {
+        uint32_t w = tid < NW ? lds[tid] : 0u;
+        uint32_t wi = wave_incl_scan(w);
+        if (tid < NW) lds[tid] = wi - w;
+        if (tid == NW - 1) lds[NW] = wi;
+    }
+    __syncthreads();
+    uint32_t res = lds[wave] + incl - v;
+    *total = lds[NW];
+    __syncthreads();
+    return res;
+}
+
+__device__ inline uint32_t bucket_of(int32_t d, int32_t D)
+{
+    if (d >= 0 && d < D) return (uint32_t)d;
+    return d == RAFI_DONE ? (uint32_t)D : (uint32_t)D + 1u;
+}
+
+// ---------------------------------------------------------------- pass 1 ---
+__global__ void __launch_bounds__(256)
+hist_kernel(const int32_t *__restrict__ dest, uint64_t n, int32_t D, uint32_t T, uint32_t n_tiles,
+            uint32_t *__restrict__ table)
+{
+    extern __shared__ uint32_t h[];  // D + 2
+    const uint32_t rows = (uint32_t)D + 2u;
+    for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x) h[e] = 0;
+    __syncthreads();
+    const uint64_t start = (uint64_t)blockIdx.x * T;
+    const uint64_t end = min(start + T, n);
+    // T is a multiple of 1024 and dest is 16-byte aligned: whole int4 groups.
+    const uint64_t vend = start + ((end - start) & ~(uint64_t)3);
+    for (uint64_t i = start + 4ull * threadIdx.x; i < vend; i += 4ull * blockDim.x) {
+        int4 d4 = *reinterpret_cast<const int4 *>(dest + i);
+        atomicAdd(&h[bucket_of(d4.x, D)], 1u);
+        atomicAdd(&h[bucket_of(d4.y, D)], 1u);
+        atomicAdd(&h[bucket_of(d4.z, D)], 1u);
+        atomicAdd(&h[bucket_of(d4.w, D)], 1u);
+    }
+    for (uint64_t i = vend + threadIdx.x; i < end; i += blockDim.x) atomicAdd(&h[bucket_of(dest[i], D)], 1u);
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x)
+        table[(uint64_t)e * n_tiles + blockIdx.x] = h[e];
+}
+
+// ---------------------------------------------------------------- pass 2 ---
+__device__ inline void load16(const uint32_t *__restrict__ a, uint64_t M, uint64_t base, uint32_t v[kScanPer])
+{
+    if (base + kScanPer <= M) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(a + base);
+#pragma unroll
+        for (int k = 0; k < kScanPer / 4; ++k) {
+            uint4 q = p[k];
+            v[4 * k] = q.x; v[4 * k + 1] = q.y; v[4 * k + 2] = q.z; v[4 * k + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) v[k] = (base + k < M) ? a[base + k] : 0u;
+    }
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+scan_reduce_kernel(const uint32_t *__restrict__ a, uint64_t M, uint32_t *__restrict__ part)
+{
+    __shared__ uint32_t lds[kScanThreads / 64 + 1];
+    uint32_t v[kScanPer];
+    load16(a, M, (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanPer, v);
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) s += v[k];
+    uint32_t tot;
+    block_excl_scan<kScanThreads>(s, lds, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kPartThreads)
+scan_partials_kernel(uint32_t *__restrict__ part, uint32_t nb)
+{
+    __shared__ uint32_t lds[kPartThreads / 64 + 1];
+    uint32_t v[kScanPer];
+    const uint64_t base = (uint64_t)threadIdx.x * kScanPer;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) v[k] = (base + k < nb) ? part[base + k] : 0u;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) s += v[k];
+    uint32_t tot;
+    uint32_t run = block_excl_scan<kPartThreads>(s, lds, &tot);
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        if (base + k < nb) part[base + k] = run;
+        run += v[k];
+    }
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+scan_apply_kernel(uint32_t *__restrict__ a, uint64_t M, const uint32_t *__restrict__ part)
+{
+    __shared__ uint32_t lds[kScanThreads / 64 + 1];
+    uint32_t v[kScanPer];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanPer;
+    load16(a, M, base, v);
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) s += v[k];
+    uint32_t tot;
+    uint32_t run = block_excl_scan<kScanThreads>(s, lds, &tot) + part[blockIdx.x];
+    if (base + kScanPer <= M) {
+        uint4 *p = reinterpret_cast<uint4 *>(a + base);
+#pragma unroll
+        for (int k = 0; k < kScanPer / 4; ++k) {
+            uint4 q;
+            q.x = run; run += v[4 * k];
+            q.y = run; run += v[4 * k + 1];
+            q.z = run; run += v[4 * k + 2];
+            q.w = run; run += v[4 * k + 3];
+            p[k] = q;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            if (base + k < M) a[base + k] = run;
+            run += v[k];
+        }
+    }
+}
+
+// Offsets, summary and the tile table for domain-pure launches.
+__global__ void __launch_bounds__(1024)
+finalize_kernel(const uint32_t *__restrict__ table, uint32_t n_tiles, int32_t D, uint64_t n,
+                uint64_t *__restrict__ offsets, uint64_t *__restrict__ summary,
+                uint32_t *__restrict__ tile_offsets, uint32_t tile_items)
+{
+    __shared__ uint32_t lds[1024 / 64 + 1];
+    auto row_start = [&](int32_t e) -> uint64_t {
+        return n_tiles ? (uint64_t)table[(uint64_t)e * n_tiles] : 0ull;
+    };
+    for (int32_t e = threadIdx.x; e <= D; e += blockDim.x) offsets[e] = row_start(e);
+    const uint64_t total = row_start(D);
+    const uint64_t done_end = n_tiles ? row_start(D + 1) : 0ull;
+    // per-domain tile counts, scanned (each thread owns a contiguous run)
+    const int32_t per = (D + 1023) / 1024;
+    const int32_t e0 = threadIdx.x * per;
+    uint32_t local = 0;
+    for (int32_t e = e0; e < min(e0 + per, D); ++e) {
+        uint64_t c = row_start(e + 1) - row_start(e);
+        local += (uint32_t)((c + tile_items - 1) / tile_items);
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan<1024>(local, lds, &tot);
+    if (tile_offsets) {
+        for (int32_t e = e0; e < min(e0 + per, D); ++e) {
+            tile_offsets[e] = run;
+            uint64_t c = row_start(e + 1) - row_start(e);
+            run += (uint32_t)((c + tile_items - 1) / tile_items);
+        }
+        if (threadIdx.x == 0) tile_offsets[D] = tot;
+    }
+    if (threadIdx.x == 0) {
+        summary[0] = total;
+        summary[1] = done_end - total;
+        summary[2] = n - done_end;
+        summary[3] = tot;
+    }
+}
+
+// ---------------------------------------------------------------- pass 3 ---
+template <int NW>
+__device__ inline void copy_item(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst)
+{
+    if constexpr (NW % 4 == 0) {
+        const uint4 *s = reinterpret_cast<const uint4 *>(src);
+        uint4 *d = reinterpret_cast<uint4 *>(dst);
+#pragma unroll
+        for (int k = 0; k < NW / 4; ++k) d[k] = s[k];
+    } else if constexpr (NW % 2 == 0) {
+        const uint2 *s = reinterpret_cast<const uint2 *>(src);
+        uint2 *d = reinterpret_cast<uint2 *>(dst);
+#pragma unroll
+        for (int k = 0; k < NW / 2; ++k) d[k] = s[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < NW; ++k) dst[k] = src[k];
+    }
+}
+
+// Lanes of this wave whose key equals mine (only lanes with ok set take part).
+__device__ inline uint64_t match_peers(uint32_t key, bool ok, int nbits)
+{
+    uint64_t peers = __ballot(ok);
+    for (int b = 0; b < nbits; ++b) {
+        const bool bit = (key >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    return peers;
+}
+
+template <int NW>
+__global__ void __launch_bounds__(256)
+scatter_kernel(const uint32_t *__restrict__ items, const int32_t *__restrict__ dest, uint64_t n,
+               int32_t D, int nbits, uint32_t T, uint32_t n_tiles, const uint32_t *__restrict__ table,
+               uint32_t *__restrict__ out, uint32_t nw_runtime)
+{
+    extern __shared__ uint32_t cnt[];  // [4][D]
+    const uint32_t nw = NW > 0 ? (uint32_t)NW : nw_runtime;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const uint64_t start = (uint64_t)blockIdx.x * T;
+    const uint64_t end = min(start + T, n);
+    const uint64_t q = T / 4;
+    const uint64_t wstart = min(start + w * q, end), wend = min(wstart + q, end);
+    uint32_t *mycnt = cnt + (uint64_t)w * D;
+
+    for (uint32_t e = tid; e < 4u * (uint32_t)D; e += 256) cnt[e] = 0;
+    __syncthreads();
+    for (uint64_t i = wstart + lane; i < wend; i += 64) {
+        const int32_t d = dest[i];
+        if (d >= 0 && d < D) atomicAdd(&mycnt[d], 1u);
+    }
+    __syncthreads();
+    for (int32_t e = tid; e < D; e += 256) {
+        uint32_t run = table[(uint64_t)e * n_tiles + blockIdx.x];
+#pragma unroll
+        for (int ww = 0; ww < 4; ++ww) {
+            const uint32_t c = cnt[ww * D + e];
+            cnt[ww * D + e] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    const uint64_t lt = (1ull << lane) - 1ull;
+    for (uint64_t b = wstart; b < wend; b += 64) {
+        const uint64_t i = b + lane;
+        const bool in = i < wend;
+        const int32_t d = in ? dest[i] : RAFI_DONE;
+        const bool ok = in && d >= 0 && d < D;
+        const uint64_t peers = match_peers((uint32_t)d, ok, nbits);
+        uint32_t pos = 0;
+        if (ok) pos = mycnt[d] + (uint32_t)__popcll(peers & lt);
+        __builtin_amdgcn_wave_barrier();
+        if (ok && (peers & lt) == 0ull) mycnt[d] = pos + (uint32_t)__popcll(peers);
+        // positions of kept items are < n by construction; the guard keeps a
+        // corrupted table from ever writing outside the output buffer
+        if (ok && pos < n) {
+            const uint32_t *src = items + i * nw;
+            uint32_t *dst = out + (uint64_t)pos * nw;
+            if constexpr (NW > 0) {
+                copy_item<NW>(src, dst);
+            } else {
+                for (uint32_t k = 0; k < nw; ++k) dst[k] = src[k];
+            }
+        }
+    }
+}
+
+template <int NW>
+void launch_scatter(const SplitPlan &p, const uint32_t *items, const int32_t *dest,
+                    const uint32_t *table, uint32_t *out, hipStream_t s)
+{
+    int nbits = 1;
+    while ((1 << nbits) < p.D) ++nbits;
+    const size_t lds = sizeof(uint32_t) * 4 * (size_t)p.D;
+    hipLaunchKernelGGL(scatter_kernel<NW>, dim3(p.n_tiles), dim3(256), lds, s, items, dest, p.n,
+                       p.D, nbits, p.tile, p.n_tiles, table, out, p.S / 4);
+}
+
+}  // namespace
+
+namespace {
+constexpr uint64_t kMaxTiles = 4096;
+
+uint64_t min_tile(int32_t D)
+{
+    // at least 1024 slots and about one table byte per slot
+    const uint64_t t = std::max<uint64_t>(1024, 4ull * (uint64_t)(D + 2));
+    return (t + 1023) / 1024 * 1024;
+}
+
+void finish_plan(SplitPlan &p)
+{
+    p.rows = (uint64_t)p.D + 2;
+    p.M = p.rows * p.n_tiles;
+    p.scan_blocks = (uint32_t)((p.M + kScanChunk - 1) / kScanChunk);
+    p.off_table = 0;
+    p.off_part = (p.M * 4 + 255) / 256 * 256;
+    p.bytes = p.off_part + ((uint64_t)std::max<uint32_t>(p.scan_blocks, 1) * 4 + 255) / 256 * 256;
+}
+}  // namespace
+
+SplitPlan split_plan(uint64_t n, int32_t D, uint32_t S)
+{
+    SplitPlan p;
+    p.n = n;
+    p.D = D;
+    p.S = S;
+    uint64_t t = std::max<uint64_t>(min_tile(D), (n + kMaxTiles - 1) / kMaxTiles);
+    t = (t + 1023) / 1024 * 1024;
+    p.tile = (uint32_t)t;
+    p.n_tiles = (uint32_t)((n + t - 1) / t);
+    finish_plan(p);
+    return p;
+}
+
+SplitPlan split_plan_bound(uint64_t cap, int32_t D, uint32_t S)
+{
+    // every n <= cap uses a tile >= min_tile(D) and at most kMaxTiles tiles
+    SplitPlan p;
+    p.n = cap;
+    p.D = D;
+    p.S = S;
+    p.tile = (uint32_t)min_tile(D);
+    p.n_tiles = (uint32_t)std::min<uint64_t>(kMaxTiles, (cap + p.tile - 1) / p.tile);
+    finish_plan(p);
+    return p;
+}
+
+int split_run(const SplitPlan &p, const void *items, const int32_t *dest, void *out,
+              uint64_t *offsets, uint64_t *summary, uint32_t *tile_offsets, uint32_t tile_items,
+              void *workspace, hipStream_t s)
+{
+    if (p.scan_blocks > (uint32_t)kPartMax) return RAFI_ERR_ARG;
+    uint32_t *table = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + p.off_table);
+    uint32_t *part = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + p.off_part);
+    if (p.n_tiles > 0) {
+        hipLaunchKernelGGL(hist_kernel, dim3(p.n_tiles), dim3(256), sizeof(uint32_t) * p.rows, s,
+                           dest, p.n, p.D, p.tile, p.n_tiles, table);
+        RAFI_LAUNCH_CHECK();
+        hipLaunchKernelGGL(scan_reduce_kernel, dim3(p.scan_blocks), dim3(kScanThreads), 0, s, table,
+                           p.M, part);
+        hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kPartThreads), 0, s, part,
+                           p.scan_blocks);
+        hipLaunchKernelGGL(scan_apply_kernel, dim3(p.scan_blocks), dim3(kScanThreads), 0, s, table,
+                           p.M, part);
+        RAFI_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, s, table, p.n_tiles, p.D, p.n,
+                       offsets, summary, tile_offsets, tile_items ? tile_items : 1u);
+    RAFI_LAUNCH_CHECK();
+    if (p.n_tiles == 0) return RAFI_OK;
+    const uint32_t *it = static_cast<const uint32_t *>(items);
+    uint32_t *o = static_cast<uint32_t *>(out);
+    switch (p.S / 4) {
+    case 1: launch_scatter<1>(p, it, dest, table, o, s); break;
+    case 2: launch_scatter<2>(p, it, dest, table, o, s); break;
+    case 3: launch_scatter<3>(p, it, dest, table, o, s); break;
+    case 4: launch_scatter<4>(p, it, dest, table, o, s); break;
+    case 6: launch_scatter<6>(p, it, dest, table, o, s); break;
+    case 8: launch_scatter<8>(p, it, dest, table, o, s); break;
+    case 11: launch_scatter<11>(p, it, dest, table, o, s); break;
+    case 12: launch_scatter<12>(p, it, dest, table, o, s); break;
+    case 16: launch_scatter<16>(p, it, dest, table, o, s); break;
+    default: launch_scatter<0>(p, it, dest, table, o, s); break;
+    }
+    RAFI_LAUNCH_CHECK();
+    return RAFI_OK;
+}
+
+}  // namespace rafi

@@ -1,0 +1,246 @@
+// RK4 streamlines over bricked domains (particle tracing, Sec. 5.4 of the
+// paper): one thread per particle integrates with classical RK4 while the
+// particle stays in its brick, then forwards it to the brick it entered, or
+// finishes it (did not move / left the field / step limit).
+//
+// Every operation that decides routing or step counts is float32 with the
+// fused operations written out, so results are bitwise reproducible:
+//   k1 = V(p); k2 = V(fma(h/2, k1, p)); k3 = V(fma(h/2, k2, p)); k4 = V(fma(h, k3, p))
+//   s = fma(2, k2, k1); s = fma(2, k3, s); s = s + k4;  p' = fma(h/6, s, p)
+// with V trilinear over the voxel-centred field, clamp-to-edge, lerping x,
+// then y, then z (lerp(a, b, t) = fma(t, b - a, a)).
+#include "internal.h"
+#include "rafi_device.h"
+
+namespace rafi {
+namespace {
+
+struct SLItem {
+    float x, y, z;
+    int32_t id;
+};
+static_assert(sizeof(SLItem) == RAFI_SL_ITEM_BYTES, "item layout");
+
+__device__ inline float lerpf(float a, float b, float t) { return __fmaf_rn(t, b - a, a); }
+
+__device__ inline void field_at(const float4 *__restrict__ f, int32_t n, float qx, float qy, float qz,
+                                float &vx, float &vy, float &vz)
+{
+    const float hi = (float)(n - 1);
+    float u[3] = {qx - 0.5f, qy - 0.5f, qz - 0.5f};
+    int32_t i0[3];
+    float w[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float uc = fminf(fmaxf(u[a], 0.0f), hi);
+        const int32_t i = min((int32_t)floorf(uc), n - 2);
+        i0[a] = i;
+        w[a] = uc - (float)i;
+    }
+    const size_t sy = (size_t)n, sz = (size_t)n * n;
+    const float4 *b = f + i0[0] + sy * i0[1] + sz * i0[2];
+    const float4 c000 = b[0], c100 = b[1], c010 = b[sy], c110 = b[sy + 1];
+    const float4 c001 = b[sz], c101 = b[sz + 1], c011 = b[sz + sy], c111 = b[sz + sy + 1];
+#define TRI(comp)                                                       \
+    lerpf(lerpf(lerpf(c000.comp, c100.comp, w[0]), lerpf(c010.comp, c110.comp, w[0]), w[1]), \
+          lerpf(lerpf(c001.comp, c101.comp, w[0]), lerpf(c011.comp, c111.comp, w[0]), w[1]), w[2])
+    vx = TRI(x);
+    vy = TRI(y);
+    vz = TRI(z);
+#undef TRI
+}
+
+struct Geo {
+    int32_t n, g0, g1, g2, b0, b1, b2;
+};
+
+__device__ inline Geo make_geo(const rafi_sl_job &j)
+{
+    return Geo{j.n, j.grid[0], j.grid[1], j.grid[2], j.n / j.grid[0], j.n / j.grid[1], j.n / j.grid[2]};
+}
+
+__device__ inline int32_t owner_of(float x, float y, float z, const Geo &g)
+{
+    const float fn = (float)g.n;
+    if (!(x >= 0.0f) || !(x < fn) || !(y >= 0.0f) || !(y < fn) || !(z >= 0.0f) || !(z < fn)) return -1;
+    const int32_t bx = (int32_t)floorf(x) / g.b0;
+    const int32_t by = (int32_t)floorf(y) / g.b1;
+    const int32_t bz = (int32_t)floorf(z) / g.b2;
+    return bx + g.g0 * (by + g.g1 * bz);
+}
+
+__global__ void pack_kernel(const float *__restrict__ f3, uint64_t nvox, float4 *__restrict__ f4)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nvox;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        f4[i] = make_float4(f3[3 * i], f3[3 * i + 1], f3[3 * i + 2], 0.0f);
+}
+
+__global__ void __launch_bounds__(256)
+seed_kernel(rafi_device_view view, rafi_sl_job job, const float *__restrict__ seeds, uint64_t n_seeds)
+{
+    const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (i >= n_seeds) return;
+    const Geo g = make_geo(job);
+    SLItem it{seeds[3 * i], seeds[3 * i + 1], seeds[3 * i + 2], (int32_t)i};
+    job.steps[i] = 0;
+    const int32_t e = owner_of(it.x, it.y, it.z, g);
+    if (e >= 0) {
+        rafi_forward_t(view, i, it, e);
+    } else {
+        job.endpoint[3 * i] = it.x;
+        job.endpoint[3 * i + 1] = it.y;
+        job.endpoint[3 * i + 2] = it.z;
+        if (job.reason) job.reason[i] = RAFI_SL_EXITED;
+        rafi_done(view, i);
+    }
+}
+
+__device__ inline int32_t find_domain(const uint64_t *__restrict__ off, int32_t D, uint64_t i)
+{
+    int32_t lo = 0, hi = D;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256)
+advance_kernel(rafi_device_view view, rafi_sl_job job, int32_t one_step, uint64_t n_ids)
+{
+    const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (i >= view.n_in) return;
+    const Geo g = make_geo(job);
+    const int32_t d = find_domain(view.in_offsets, view.n_domains, i);
+    const int32_t bx = d % g.g0, by = (d / g.g0) % g.g1, bz = d / (g.g0 * g.g1);
+    const float lo0 = (float)(bx * g.b0), hi0 = (float)((bx + 1) * g.b0);
+    const float lo1 = (float)(by * g.b1), hi1 = (float)((by + 1) * g.b1);
+    const float lo2 = (float)(bz * g.b2), hi2 = (float)((bz + 1) * g.b2);
+    const float4 *__restrict__ F = reinterpret_cast<const float4 *>(job.field4);
+
+    SLItem it = static_cast<const SLItem *>(view.in_items)[i];
+    if ((uint64_t)(uint32_t)it.id >= n_ids) {  // never true for items this library emitted
+        rafi_forward_t(view, i, it, RAFI_POISON);
+        return;
+    }
+    int32_t steps = job.steps[it.id];
+    const float h = job.h, hh = job.h * 0.5f, h6 = (float)((double)job.h / 6.0);
+    float x = it.x, y = it.y, z = it.z;
+    int32_t dest = d, why = 0;
+    for (;;) {
+        float k1x, k1y, k1z, k2x, k2y, k2z, k3x, k3y, k3z, k4x, k4y, k4z;
+        field_at(F, g.n, x, y, z, k1x, k1y, k1z);
+        field_at(F, g.n, __fmaf_rn(hh, k1x, x), __fmaf_rn(hh, k1y, y), __fmaf_rn(hh, k1z, z), k2x, k2y, k2z);
+        field_at(F, g.n, __fmaf_rn(hh, k2x, x), __fmaf_rn(hh, k2y, y), __fmaf_rn(hh, k2z, z), k3x, k3y, k3z);
+        field_at(F, g.n, __fmaf_rn(h, k3x, x), __fmaf_rn(h, k3y, y), __fmaf_rn(h, k3z, z), k4x, k4y, k4z);
+        const float sx = __fmaf_rn(2.0f, k3x, __fmaf_rn(2.0f, k2x, k1x)) + k4x;
+        const float sy = __fmaf_rn(2.0f, k3y, __fmaf_rn(2.0f, k2y, k1y)) + k4y;
+        const float sz = __fmaf_rn(2.0f, k3z, __fmaf_rn(2.0f, k2z, k1z)) + k4z;
+        const float nx = __fmaf_rn(h6, sx, x), ny = __fmaf_rn(h6, sy, y), nz = __fmaf_rn(h6, sz, z);
+        ++steps;
+        const bool same = __float_as_uint(nx) == __float_as_uint(x) && __float_as_uint(ny) == __float_as_uint(y) &&
+                          __float_as_uint(nz) == __float_as_uint(z);
+        x = nx;
+        y = ny;
+        z = nz;
+        if (same) { why = RAFI_SL_STAGNANT; break; }
+        const bool inside = x >= lo0 && x < hi0 && y >= lo1 && y < hi1 && z >= lo2 && z < hi2;
+        const int32_t e = inside ? d : owner_of(x, y, z, g);
+        if (e < 0) { why = RAFI_SL_EXITED; break; }
+        if (steps >= job.max_steps) { why = RAFI_SL_MAXSTEPS; break; }
+        if (e != d || one_step) { dest = e; break; }
+    }
+    job.steps[it.id] = steps;
+    if (why) {
+        job.endpoint[3 * (size_t)it.id] = x;
+        job.endpoint[3 * (size_t)it.id + 1] = y;
+        job.endpoint[3 * (size_t)it.id + 2] = z;
+        if (job.reason) job.reason[it.id] = why;
+        rafi_done(view, i);
+    } else {
+        it.x = x;
+        it.y = y;
+        it.z = z;
+        rafi_forward_t(view, i, it, dest);
+    }
+}
+
+bool job_ok(const rafi_ctx *c, const rafi_sl_job *j)
+{
+    if (!c || !j || !j->field4 || !j->endpoint || !j->steps) return false;
+    if (j->n < 2 || j->max_steps < 1 || !(j->h > 0.0f)) return false;
+    for (int a = 0; a < 3; ++a)
+        if (j->grid[a] < 1 || j->n % j->grid[a] != 0) return false;
+    return c->D == j->grid[0] * j->grid[1] * j->grid[2] && c->S == RAFI_SL_ITEM_BYTES;
+}
+
+}  // namespace
+}  // namespace rafi
+
+using namespace rafi;
+
+extern "C" {
+
+int rafi_sl_pack(const float *field, int32_t n, float *field4, void *hip_stream)
+{
+    if (!field || !field4 || n < 2) return RAFI_ERR_ARG;
+    const uint64_t nvox = (uint64_t)n * n * n;
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((nvox + 255) / 256, 65536);
+    hipLaunchKernelGGL(pack_kernel, dim3(blocks), dim3(256), 0, static_cast<hipStream_t>(hip_stream), field, nvox,
+                       reinterpret_cast<float4 *>(field4));
+    RAFI_LAUNCH_CHECK();
+    return RAFI_OK;
+}
+
+int rafi_sl_seed(rafi_ctx *c, const rafi_sl_job *job, const float *seeds, uint64_t n_seeds)
+{
+    if (!job_ok(c, job) || (n_seeds && !seeds) || n_seeds > c->cap || n_seeds >= (1ull << 31)) return RAFI_ERR_ARG;
+    int rc = rafi_begin(c, n_seeds);
+    if (rc != RAFI_OK) return rc;
+    rafi_device_view v;
+    rafi_view(c, &v);
+    if (n_seeds)
+        hipLaunchKernelGGL(seed_kernel, dim3((uint32_t)((n_seeds + 255) / 256)), dim3(256), 0, c->stream, v, *job,
+                           seeds, n_seeds);
+    RAFI_LAUNCH_CHECK();
+    return RAFI_OK;
+}
+
+int rafi_sl_advance(rafi_ctx *c, const rafi_sl_job *job, int32_t one_step)
+{
+    if (!job_ok(c, job)) return RAFI_ERR_ARG;
+    rafi_device_view v;
+    rafi_view(c, &v);
+    if (v.n_in)
+        hipLaunchKernelGGL(advance_kernel, dim3((uint32_t)((v.n_in + 255) / 256)), dim3(256), 0, c->stream, v,
+                           *job, one_step, c->wave_slots);
+    RAFI_LAUNCH_CHECK();
+    return RAFI_OK;
+}
+
+int rafi_sl_trace(rafi_ctx *c, const rafi_sl_job *job, const float *seeds, uint64_t n_seeds, int32_t max_rounds,
+                  int32_t *rounds, uint64_t *forwarded)
+{
+    if (max_rounds < 1) return RAFI_ERR_ARG;
+    int rc = rafi_sl_seed(c, job, seeds, n_seeds);
+    if (rc != RAFI_OK) return rc;
+    int32_t r = 0;
+    uint64_t fwd = 0;
+    for (;;) {
+        uint64_t total = 0;
+        rc = rafi_round(c, nullptr, &total);
+        ++r;
+        fwd += total;
+        if (rc != RAFI_OK) break;
+        if (total == 0) break;
+        if (r >= max_rounds) { rc = RAFI_ERR_MAX_ROUNDS; break; }
+        rc = rafi_sl_advance(c, job, 0);
+        if (rc != RAFI_OK) break;
+    }
+    if (rounds) *rounds = r;
+    if (forwarded) *forwarded = fwd;
+    return rc;
+}
+
+}  // extern "C"

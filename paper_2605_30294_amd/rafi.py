@@ -1,0 +1,315 @@
+"""Python binding of librafi.so (ctypes): argument marshalling only.
+
+Every step of the forwarding path runs in the library's HIP kernels; this
+module converts torch tensors and numpy records into the C structs and
+pointers the C ABI (include/rafi.h) takes, calls it, and raises on error
+codes. PyTorch supplies device memory and the current stream.
+
+The library must have been built (``python -m paper_2605_30294_amd.build``);
+there is no fallback: importing the binding without it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+from . import workloads as W
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librafi.so")
+
+RAFI_OK = 0
+RAFI_DONE = -1
+RAFI_POISON = -2
+ERR_ARG, ERR_OOM, ERR_HIP, ERR_OVERFLOW, ERR_BAD_DEST, ERR_MAX_ROUNDS, ERR_STATE = range(-1, -8, -1)
+EA_ITEM_BYTES = 16
+SL_ITEM_BYTES = 16
+
+
+class RafiError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+class DeviceView(C.Structure):
+    _fields_ = [("in_items", C.c_void_p), ("in_offsets", C.c_void_p), ("in_tile_offsets", C.c_void_p),
+                ("out_items", C.c_void_p), ("out_dest", C.c_void_p), ("dropped", C.c_void_p),
+                ("n_in", C.c_uint64), ("n_slots", C.c_uint64), ("capacity", C.c_uint64),
+                ("item_bytes", C.c_uint32), ("n_domains", C.c_int32), ("tile_items", C.c_uint32),
+                ("n_tiles", C.c_uint32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("rounds", C.c_uint64), ("forwarded", C.c_uint64), ("done", C.c_uint64),
+                ("bad_dest", C.c_uint64), ("dropped", C.c_uint64), ("last_total", C.c_uint64)]
+
+
+class EAJob(C.Structure):
+    _fields_ = [("volume", C.c_void_p), ("views", C.c_void_p), ("image", C.c_void_p), ("tau", C.c_void_p),
+                ("klast", C.c_void_p), ("n", C.c_int32), ("grid", C.c_int32 * 3), ("n_views", C.c_int32),
+                ("width", C.c_int32), ("height", C.c_int32), ("dt", C.c_float), ("c", C.c_float),
+                ("pad", C.c_int32)]
+
+
+class SLJob(C.Structure):
+    _fields_ = [("field4", C.c_void_p), ("endpoint", C.c_void_p), ("steps", C.c_void_p), ("reason", C.c_void_p),
+                ("n", C.c_int32), ("grid", C.c_int32 * 3), ("h", C.c_float), ("max_steps", C.c_int32)]
+
+
+_P = C.c_void_p
+_U64P = C.POINTER(C.c_uint64)
+_SIGS = {
+    "rafi_create": ([C.c_int32, C.c_uint32, C.c_uint64, C.POINTER(C.c_void_p)], C.c_int),
+    "rafi_destroy": ([_P], None),
+    "rafi_resize": ([_P, C.c_uint64], C.c_int),
+    "rafi_set_stream": ([_P, _P], C.c_int),
+    "rafi_set_debug": ([_P, C.c_int32], C.c_int),
+    "rafi_set_tile_items": ([_P, C.c_uint32], C.c_int),
+    "rafi_view": ([_P, C.POINTER(DeviceView)], C.c_int),
+    "rafi_begin": ([_P, C.c_uint64], C.c_int),
+    "rafi_round": ([_P, _P, _U64P], C.c_int),
+    "rafi_copy_queue": ([_P, _P, _P], C.c_int),
+    "rafi_get_stats": ([_P, C.POINTER(Stats)], C.c_int),
+    "rafi_strerror": ([C.c_int], C.c_char_p),
+    "rafi_multisplit_workspace": ([C.c_uint64, C.c_int32, C.c_uint32, _U64P], C.c_int),
+    "rafi_multisplit": ([_P, _P, C.c_uint64, C.c_uint32, C.c_int32, _P, _P, _P, _P, C.c_uint64, _P], C.c_int),
+    "rafi_ea_raygen": ([_P, C.POINTER(EAJob)], C.c_int),
+    "rafi_ea_march": ([_P, C.POINTER(EAJob)], C.c_int),
+    "rafi_ea_render": ([_P, C.POINTER(EAJob), C.c_int32, C.POINTER(C.c_int32)], C.c_int),
+    "rafi_sl_pack": ([_P, C.c_int32, _P, _P], C.c_int),
+    "rafi_sl_seed": ([_P, C.POINTER(SLJob), _P, C.c_uint64], C.c_int),
+    "rafi_sl_advance": ([_P, C.POINTER(SLJob), C.c_int32], C.c_int),
+    "rafi_sl_trace": ([_P, C.POINTER(SLJob), _P, C.c_uint64, C.c_int32, C.POINTER(C.c_int32), _U64P], C.c_int),
+}
+
+_lib = None
+
+
+def lib():
+    """Load librafi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2605_30294_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().rafi_strerror(code).decode()
+
+
+def _check(code: int, what: str, ok=(RAFI_OK,)):
+    if code not in ok:
+        raise RafiError(code, what)
+    return code
+
+
+def _dptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA/HIP tensors"
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def views_to_device(views: np.ndarray, device) -> torch.Tensor:
+    """Copy VIEW_DTYPE records to the device as raw bytes."""
+    v = np.ascontiguousarray(views, dtype=W.VIEW_DTYPE)
+    return torch.from_numpy(v.view(np.uint8).copy()).to(device)
+
+
+# ------------------------------------------------------------- context ---
+
+class Context:
+    """One forwarding context (queues of `capacity` items of `item_bytes`)."""
+
+    def __init__(self, n_domains: int, item_bytes: int, capacity: int, stream=None, debug=False):
+        h = C.c_void_p()
+        _check(lib().rafi_create(n_domains, item_bytes, capacity, C.byref(h)), "rafi_create")
+        self._h = h
+        self.n_domains, self.item_bytes, self.capacity = n_domains, item_bytes, capacity
+        _check(lib().rafi_set_stream(self._h, _stream(stream)), "rafi_set_stream")
+        if debug:
+            _check(lib().rafi_set_debug(self._h, 1), "rafi_set_debug")
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().rafi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream=None):
+        _check(lib().rafi_set_stream(self._h, _stream(stream)), "rafi_set_stream")
+
+    def set_tile_items(self, t: int):
+        _check(lib().rafi_set_tile_items(self._h, t), "rafi_set_tile_items")
+
+    def view(self) -> DeviceView:
+        v = DeviceView()
+        _check(lib().rafi_view(self._h, C.byref(v)), "rafi_view")
+        return v
+
+    def begin(self, n_slots: int):
+        _check(lib().rafi_begin(self._h, n_slots), "rafi_begin")
+
+    def round(self, counts: bool = True, allow=(RAFI_OK,)):
+        """Forward step. Returns (counts array or None, total, return code)."""
+        cnt = np.zeros(self.n_domains, dtype=np.uint64) if counts else None
+        total = C.c_uint64(0)
+        rc = lib().rafi_round(self._h, None if cnt is None else cnt.ctypes.data_as(C.c_void_p), C.byref(total))
+        _check(rc, "rafi_round", ok=allow)
+        return cnt, total.value, rc
+
+    def copy_queue(self):
+        """(items as uint8 tensor [n_in, item_bytes], offsets uint64 numpy [D+1])."""
+        n_in = self.view().n_in
+        dev = torch.device("cuda", torch.cuda.current_device())
+        items = torch.empty((max(n_in, 1), self.item_bytes), dtype=torch.uint8, device=dev)
+        offs = torch.empty(self.n_domains + 1, dtype=torch.int64, device=dev)
+        _check(lib().rafi_copy_queue(self._h, _dptr(items), _dptr(offs)), "rafi_copy_queue")
+        torch.cuda.synchronize()
+        return items[:n_in], offs.cpu().numpy().astype(np.uint64)
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().rafi_get_stats(self._h, C.byref(s)), "rafi_get_stats")
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+
+# ----------------------------------------------------------- multisplit ---
+
+def multisplit_workspace(n: int, n_domains: int, item_bytes: int) -> int:
+    b = C.c_uint64(0)
+    _check(lib().rafi_multisplit_workspace(n, n_domains, item_bytes, C.byref(b)), "rafi_multisplit_workspace")
+    return b.value
+
+
+def multisplit(items: torch.Tensor, dest: torch.Tensor, n_domains: int, out=None, workspace=None,
+               stream=None):
+    """Stateless forward step on device tensors.
+
+    items: [n, item_bytes // 4] 32-bit words (any 4-byte dtype); dest: int32 [n].
+    Returns (out, offsets int64 tensor [D+1], summary int64 tensor [4]:
+    total, done, bad, 0)."""
+    n = dest.numel()
+    S = items.element_size() * (items.shape[1] if items.dim() > 1 else 1)
+    if out is None:
+        out = torch.empty_like(items)
+    offsets = torch.empty(n_domains + 1, dtype=torch.int64, device=dest.device)
+    summary = torch.empty(4, dtype=torch.int64, device=dest.device)
+    ws_bytes = multisplit_workspace(n, n_domains, S)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=dest.device)
+    _check(lib().rafi_multisplit(_dptr(items), _dptr(dest), n, S, n_domains, _dptr(out), _dptr(offsets),
+                                 _dptr(summary), _dptr(workspace), workspace.numel(), _stream(stream)),
+           "rafi_multisplit")
+    return out, offsets, summary
+
+
+# -------------------------------------------------------------- EA march ---
+
+def ea_job(volume: torch.Tensor, grid, views_dev: torch.Tensor, n_views: int, width: int, height: int,
+           image: torch.Tensor, tau=None, klast=None, dt=0.5, c=0.025) -> EAJob:
+    n = volume.shape[0]
+    return EAJob(_dptr(volume), _dptr(views_dev), _dptr(image), _dptr(tau), _dptr(klast), n,
+                 (C.c_int32 * 3)(*[int(g) for g in grid]), n_views, width, height, float(dt), float(c), 0)
+
+
+def ea_raygen(ctx: Context, job: EAJob):
+    _check(lib().rafi_ea_raygen(ctx.handle, C.byref(job)), "rafi_ea_raygen")
+
+
+def ea_march(ctx: Context, job: EAJob):
+    _check(lib().rafi_ea_march(ctx.handle, C.byref(job)), "rafi_ea_march")
+
+
+def ea_render_job(ctx: Context, job: EAJob, max_rounds: int = 1024) -> int:
+    r = C.c_int32(0)
+    _check(lib().rafi_ea_render(ctx.handle, C.byref(job), max_rounds, C.byref(r)), "rafi_ea_render")
+    return r.value
+
+
+def ea_render(volume: torch.Tensor, grid, views: np.ndarray, dt=0.5, c=0.025, ctx: Context | None = None,
+              max_rounds: int = 1024, want_tau=False):
+    """Render all rays of `views` through `volume` (device float32 [n,n,n]).
+    Returns dict(image, tau, klast, rounds)."""
+    dev = volume.device
+    nv = len(views)
+    w, h = int(views[0]["width"]), int(views[0]["height"])
+    n_rays = nv * w * h
+    if ctx is None:
+        ctx = Context(int(np.prod(grid)), EA_ITEM_BYTES, max(n_rays, 1))
+    vdev = views_to_device(views, dev)
+    image = torch.empty(n_rays, dtype=torch.float32, device=dev)
+    tau = torch.empty(n_rays, dtype=torch.float32, device=dev) if want_tau else None
+    klast = torch.empty(n_rays, dtype=torch.int32, device=dev) if want_tau else None
+    job = ea_job(volume, grid, vdev, nv, w, h, image, tau, klast, dt, c)
+    rounds = ea_render_job(ctx, job, max_rounds)
+    return dict(image=image, tau=tau, klast=klast, rounds=rounds, ctx=ctx)
+
+
+# ------------------------------------------------------------ streamlines ---
+
+def sl_pack(field: torch.Tensor) -> torch.Tensor:
+    n = field.shape[0]
+    f4 = torch.empty((n, n, n, 4), dtype=torch.float32, device=field.device)
+    _check(lib().rafi_sl_pack(_dptr(field), n, _dptr(f4), _stream()), "rafi_sl_pack")
+    return f4
+
+
+def sl_job(field4: torch.Tensor, grid, endpoint, steps, reason=None, h=0.25, max_steps=2000) -> SLJob:
+    return SLJob(_dptr(field4), _dptr(endpoint), _dptr(steps), _dptr(reason), field4.shape[0],
+                 (C.c_int32 * 3)(*[int(g) for g in grid]), float(h), int(max_steps))
+
+
+def sl_seed(ctx: Context, job: SLJob, seeds: torch.Tensor):
+    _check(lib().rafi_sl_seed(ctx.handle, C.byref(job), _dptr(seeds), seeds.shape[0]), "rafi_sl_seed")
+
+
+def sl_advance(ctx: Context, job: SLJob, one_step=False):
+    _check(lib().rafi_sl_advance(ctx.handle, C.byref(job), int(one_step)), "rafi_sl_advance")
+
+
+def sl_trace_job(ctx: Context, job: SLJob, seeds: torch.Tensor, max_rounds: int = 100000):
+    r = C.c_int32(0)
+    fwd = C.c_uint64(0)
+    _check(lib().rafi_sl_trace(ctx.handle, C.byref(job), _dptr(seeds), seeds.shape[0], max_rounds, C.byref(r),
+                               C.byref(fwd)), "rafi_sl_trace")
+    return r.value, fwd.value
+
+
+def sl_trace(field4: torch.Tensor, grid, seeds: torch.Tensor, h=0.25, max_steps=2000, ctx: Context | None = None,
+             max_rounds: int = 100000):
+    dev = field4.device
+    N = seeds.shape[0]
+    if ctx is None:
+        ctx = Context(int(np.prod(grid)), SL_ITEM_BYTES, max(N, 1))
+    endpoint = torch.empty((N, 3), dtype=torch.float32, device=dev)
+    steps = torch.empty(N, dtype=torch.int32, device=dev)
+    reason = torch.empty(N, dtype=torch.int32, device=dev)
+    job = sl_job(field4, grid, endpoint, steps, reason, h, max_steps)
+    rounds, fwd = sl_trace_job(ctx, job, seeds, max_rounds)
+    return dict(endpoint=endpoint, steps=steps, reason=reason, rounds=rounds, forwarded=fwd, ctx=ctx)

@@ -1,0 +1,96 @@
+"""GPU parity of the forward step (stable multi-split) against the oracle.
+
+Bit-exact on the permuted items, the per-destination offsets and the
+done/bad counts, over small and ragged sizes, many item sizes and domain
+counts, the 64M-item x 32-byte uniform and Zipf workloads, and through the
+context's round API (debug poison, bad destinations).
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import announce, device
+from paper_2605_30294_amd import rafi
+from paper_2605_30294_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _run_split(orc, n, D, words, seed, dist="mixed"):
+    dev = device()
+    rng = np.random.default_rng(seed)
+    if dist == "mixed":
+        dest = rng.integers(-2, D + 1, n).astype(np.int32)        # done, bad and valid
+    else:
+        dest = W.split_dest(n, D, dist, seed=seed)
+    items = rng.integers(0, 2**32, (n, words), dtype=np.uint64).astype(np.uint32)
+    announce(f"split n={n} D={D} S={4 * words} dist={dist}")
+    out, offsets, summary = rafi.multisplit(torch.from_numpy(items.view(np.int32)).to(dev),
+                                            torch.from_numpy(dest).to(dev), D)
+    torch.cuda.synchronize()
+    e_out, e_counts, e_off, e_done, e_bad = orc.multisplit(items, dest, D)
+    total = int(e_off[-1])
+    s = summary.cpu().numpy()
+    assert s[0] == total and s[1] == e_done and s[2] == e_bad
+    assert np.array_equal(offsets.cpu().numpy().astype(np.uint64), e_off)
+    assert np.array_equal(out[:total].cpu().numpy().view(np.uint32), e_out)
+
+
+@pytest.mark.parametrize("n,D,words", [
+    (0, 4, 4), (1, 1, 4), (3, 2, 1), (1000, 8, 4), (5000, 64, 8), (1023, 3, 11), (4097, 1024, 8),
+    (70001, 1024, 4), (100_000, 8192, 2), (65536 + 17, 17, 64), (250_000, 64, 3), (33_333, 5, 6),
+    (200_000, 1, 8), (131_072, 2048, 12),
+])
+def test_split_matches_oracle(orc, n, D, words):
+    _run_split(orc, n, D, words, seed=n * 7 + D)
+
+
+@pytest.mark.parametrize("dist", ["uniform", "zipf"])
+def test_split_full_size(orc, dist):
+    """The 64M x 32-byte microbenchmark, 1024 destinations."""
+    dev = device()
+    n, D = 1 << 26, 1024
+    dest = W.split_dest(n, D, dist)
+    items = W.split_items(n)
+    announce(f"split full size {dist}")
+    d_items = torch.from_numpy(items.view(np.int32)).to(dev)
+    d_dest = torch.from_numpy(dest).to(dev)
+    out, offsets, summary = rafi.multisplit(d_items, d_dest, D)
+    out2, offsets2, _ = rafi.multisplit(d_items, d_dest, D)      # determinism
+    torch.cuda.synchronize()
+    assert torch.equal(out, out2) and torch.equal(offsets, offsets2)
+    e_out, e_counts, e_off, e_done, e_bad = orc.multisplit(items, dest, D)
+    assert np.array_equal(offsets.cpu().numpy().astype(np.uint64), e_off)
+    assert int(summary[0]) == n and int(summary[1]) == 0 and int(summary[2]) == 0
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), e_out)
+
+
+def test_context_round_and_error_paths(orc):
+    dev = device()
+    D, S, cap = 16, 16, 10_000
+    ctx = rafi.Context(D, S, cap, debug=True)
+    ctx.begin(5000)
+    v = ctx.view()
+    # write slots from the host through torch: a stand-in for a generator kernel
+    rng = np.random.default_rng(3)
+    items = rng.integers(0, 2**31, (5000, 4)).astype(np.int32)
+    dest = rng.integers(-1, D, 5000).astype(np.int32)
+    dest[4000:] = rafi.RAFI_POISON                   # slots a "kernel" never wrote
+    t_items = torch.from_numpy(items).to(dev)
+    t_dest = torch.from_numpy(dest[:4000]).to(dev)
+    torch.cuda.synchronize()
+    import ctypes as C
+    hip = C.CDLL("libamdhip64.so.7")   # the runtime torch already loaded (matched by soname)
+    hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    assert hip.hipMemcpy(C.c_void_p(v.out_items), C.c_void_p(t_items.data_ptr()), 5000 * 16, 3) == 0
+    assert hip.hipMemcpy(C.c_void_p(v.out_dest), C.c_void_p(t_dest.data_ptr()), 4000 * 4, 3) == 0
+    counts, total, rc = ctx.round(allow=(rafi.RAFI_OK, rafi.ERR_BAD_DEST))
+    assert rc == rafi.ERR_BAD_DEST                    # 1000 poisoned slots counted as bad
+    e_out, e_counts, e_off, e_done, e_bad = orc.multisplit(items, dest, D)
+    assert total == int(e_off[-1]) and np.array_equal(counts, e_counts)
+    q, offs = ctx.copy_queue()
+    assert np.array_equal(q.cpu().numpy().view(np.int32).reshape(-1, 4), e_out.reshape(-1, 4))
+    assert np.array_equal(offs, e_off)
+    st = ctx.stats()
+    assert st["bad_dest"] == 1000 and st["done"] == e_done and st["rounds"] == 1
+    ctx.close()

@@ -1,0 +1,109 @@
+"""GPU parity of the RK4 streamline march-and-forward path.
+
+Endpoints, step counts, finish reasons, per-round counts and the particle
+ids in every domain queue must equal the oracle's bit for bit (the whole
+path is float32 with the same operations)."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import announce, device
+from paper_2605_30294_amd import rafi
+from paper_2605_30294_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _stepwise(field, grid, seeds, h=0.25, max_steps=2000, one_step=False):
+    dev = device()
+    N = len(seeds)
+    f4 = rafi.sl_pack(torch.from_numpy(np.ascontiguousarray(field)).to(dev))
+    ctx = rafi.Context(int(np.prod(grid)), rafi.SL_ITEM_BYTES, N, debug=True)
+    ep = torch.zeros((N, 3), dtype=torch.float32, device=dev)
+    st = torch.zeros(N, dtype=torch.int32, device=dev)
+    why = torch.zeros(N, dtype=torch.int32, device=dev)
+    job = rafi.sl_job(f4, grid, ep, st, why, h, max_steps)
+    rafi.sl_seed(ctx, job, torch.from_numpy(seeds).to(dev))
+    counts, queues = [], []
+    while True:
+        cnt, total, rc = ctx.round()
+        q, _ = ctx.copy_queue()
+        counts.append(cnt)
+        queues.append(q.cpu().numpy().view(np.int32).reshape(-1, 4)[:, 3].copy())
+        if total == 0:
+            break
+        rafi.sl_advance(ctx, job, one_step)
+    torch.cuda.synchronize()
+    stats = ctx.stats()
+    ctx.close()
+    return dict(endpoint=ep.cpu().numpy(), steps=st.cpu().numpy(), reason=why.cpu().numpy(),
+                counts=np.array(counts), queue=np.concatenate(queues), stats=stats)
+
+
+def _compare(g, o):
+    assert np.array_equal(g["endpoint"].view(np.uint32), o["endpoint"].view(np.uint32))
+    assert np.array_equal(g["steps"], o["steps"])
+    assert np.array_equal(g["reason"], o["reason"])
+    assert np.array_equal(g["counts"], o["round_counts"])
+    assert np.array_equal(g["queue"], o["queue"])
+    assert g["stats"]["bad_dest"] == 0 and g["stats"]["dropped"] == 0
+
+
+@pytest.mark.parametrize("n,grid,N,max_steps", [(64, (4, 4, 4), 4096, 2000), (64, (2, 1, 4), 3001, 500),
+                                                (32, (1, 1, 1), 100, 300), (96, (3, 4, 2), 2000, 800)])
+def test_abc_matches_oracle(orc, n, grid, N, max_steps):
+    field = W.abc_field(n)
+    seeds = W.streamline_seeds(N, n, seed=N + n)
+    announce(f"sl abc n={n} grid={grid} N={N}")
+    g = _stepwise(field, grid, seeds, max_steps=max_steps)
+    o = orc.streamlines(field, grid, seeds, max_steps=max_steps, queue_cap=1 << 24)
+    _compare(g, o)
+
+
+def test_one_step_per_round(orc):
+    field = W.abc_field(32)
+    seeds = W.streamline_seeds(256, 32, seed=5)
+    announce("sl one-step")
+    g = _stepwise(field, (2, 2, 2), seeds, max_steps=120, one_step=True)
+    o = orc.streamlines(field, (2, 2, 2), seeds, max_steps=120, one_step=True, max_rounds=1000,
+                        queue_cap=1 << 22)
+    _compare(g, o)
+
+
+def test_constant_field_exact(orc):
+    n = 256
+    field = W.constant_field(n, (0.5, 0.0, 0.0))
+    rng = np.random.default_rng(0)
+    x0 = rng.integers(1024, 250 * 1024, 500) / 1024.0
+    seeds = np.stack([x0, rng.uniform(0, n, 500), rng.uniform(0, n, 500)], 1).astype(np.float32)
+    announce("sl constant field")
+    g = _stepwise(field, (4, 4, 4), seeds, max_steps=100000)
+    steps = np.ceil((256.0 - x0) / 0.125).astype(np.int64)
+    assert np.array_equal(g["steps"], steps)
+    assert np.array_equal(g["endpoint"][:, 0].astype(np.float64), x0 + 0.125 * steps)
+
+
+def test_full_cfg1_sampled(orc):
+    """256^3 ABC, 4x4x4 bricks, 1M seeds, RK4 h = 0.25, <= 2000 steps: the whole
+    job on the GPU, a seeded sample of 4096 particles through the oracle."""
+    dev = device()
+    n, N = 256, 1 << 20
+    field = W.abc_field(n)
+    seeds = W.streamline_seeds(N, n)
+    announce("sl cfg1 full")
+    f4 = rafi.sl_pack(torch.from_numpy(field).to(dev))
+    r = rafi.sl_trace(f4, (4, 4, 4), torch.from_numpy(seeds).to(dev))
+    r2 = rafi.sl_trace(f4, (4, 4, 4), torch.from_numpy(seeds).to(dev))
+    torch.cuda.synchronize()
+    ep, st, why = r["endpoint"].cpu().numpy(), r["steps"].cpu().numpy(), r["reason"].cpu().numpy()
+    assert torch.equal(r["endpoint"], r2["endpoint"]) and r["forwarded"] == r2["forwarded"]
+    ids = np.sort(np.random.default_rng(2).choice(N, 4096, replace=False))
+    o = orc.streamlines_brute(field, (4, 4, 4), seeds[ids])
+    assert np.array_equal(ep[ids].view(np.uint32), o["endpoint"].view(np.uint32))
+    assert np.array_equal(st[ids], o["steps"])
+    assert np.array_equal(why[ids], o["reason"])
+    # properties over all particles
+    assert np.all((why >= 1) & (why <= 3)) and np.all((st >= 1) & (st <= 2000))
+    assert np.all(st[why == 3] == 2000)
+    out = np.any((ep < 0) | (ep >= n), axis=1)
+    assert np.array_equal(out, why == 2)
