@@ -17,6 +17,10 @@ pytestmark = pytest.mark.gpu
 
 C32 = float(np.float32(0.025))
 RTOL = 1e-5
+# float32 cannot hold per-sample terms below its normal range (2^-126 ~ 1.2e-38);
+# a ray sums at most a few hundred of them, so 1e-35 absolute covers underflow
+# and is far below any value that carries information.
+ATOL = 1e-35
 
 
 def _stepwise(vol_t, grid, views, dt=0.5, c=C32):
@@ -52,9 +56,9 @@ def _compare(g, o):
     assert np.array_equal(g["counts"], o["round_counts"])
     assert np.array_equal(g["queue"], o["queue"])
     assert np.array_equal(g["klast"], o["klast"])
-    ok, i, r = rel_close(g["image"], o["image"], RTOL)
+    ok, i, r = rel_close(g["image"], o["image"], RTOL, ATOL)
     assert ok, f"image ray {i}: gpu {g['image'][i]!r} oracle {o['image'][i]!r} ({r:.3g} x tol)"
-    ok, i, r = rel_close(g["tau"], o["tau"], RTOL)
+    ok, i, r = rel_close(g["tau"], o["tau"], RTOL, ATOL)
     assert ok, f"tau ray {i}: gpu {g['tau'][i]!r} oracle {o['tau'][i]!r}"
     assert g["stats"]["bad_dest"] == 0 and g["stats"]["dropped"] == 0
 
@@ -96,7 +100,7 @@ def test_render_entry_point_and_determinism(orc):
     assert torch.equal(a["image"], b["image"]) and a["rounds"] == b["rounds"]
     o = orc.ea_render(vol, (4, 4, 4), views, c=C32)
     assert a["rounds"] == o["rounds"]
-    ok, i, r = rel_close(a["image"].cpu().numpy(), o["image"], RTOL)
+    ok, i, r = rel_close(a["image"].cpu().numpy(), o["image"], RTOL, ATOL)
     assert ok, (i, r)
 
 
@@ -113,6 +117,6 @@ def test_adjoint_scale_forward_sampled(orc):
     rng = np.random.default_rng(1)
     ids = np.sort(rng.choice(img.size, 20000, replace=False))
     o = orc.ea_brute(vol, (4, 4, 4), views, c=C32, ray_ids=ids)
-    ok, i, rr = rel_close(img[ids], o["image"], RTOL)
+    ok, i, rr = rel_close(img[ids], o["image"], RTOL, ATOL)
     assert ok, (ids[i], img[ids[i]], o["image"][i], rr)
     assert 3 <= r["rounds"] <= 12
