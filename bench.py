@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Benchmark of the single-GPU work-forwarding hot path.
+
+One "step" is one whole streamline job: 1M seeds in a 256^3 ABC velocity
+field split into 4x4x4 domains, RK4 (h = 0.25 voxel, <= 2000 steps), every
+particle forwarded at each brick exit until no particle is left -- seeding,
+all forward steps (stable multi-split) and all domain-kernel launches, inputs
+resident in HBM before the timed region starts.
+
+Prints ONE JSON line. `value` is forwarded items per second over the whole
+job (items delivered by all forward steps, seeding round included, divided
+by the job's wall time on the GPU). Also reported: RK4 steps per second, the
+roofline of the dominant kernel (the RK4 brick kernel) from HIP events taken
+on the stream it runs on, the CPU oracle on a bounded sample, and extras: the
+64M-item x 32-byte multi-split microbenchmark (uniform and Zipf over 1024
+destinations) against the HBM roofline, and the 128^3 / 64-view
+emission-absorption forward render.
+
+    python bench.py [--steps K] [--warmup W] [--no-extras] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "forwarded items/s + ray samples/s on 1 MI355X, % HBM peak; batched/adjoint vs plain"
+HBM_PEAK_GBS = 8000.0
+# float32 VALU peak without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# = 39.3e12 lane-ops/s, i.e. 78.6 TFLOP/s counting an FMA as two flops.
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+# Algorithmic float32 flops of one RK4 step (FMA = 2): per trilinear vec3
+# sample 2 subs for the weights x 3 axes + 7 lerps (sub + fma) x 3 components
+# = 69; four samples = 276; three stage offsets (3 fma) = 18; the weighted
+# sum (2 fma + add) x 3 = 15; the update (3 fma) = 6.  Total 315.
+RK4_FLOPS_PER_STEP = 315
+# Algorithmic bytes per item of one forward step: read item + read dest +
+# write item.
+def split_bytes_per_item(item_bytes: int) -> int:
+    return 2 * item_bytes + 4
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def streamline_job(args, dev):
+    import numpy as np
+    import torch
+
+    from paper_2605_30294_amd import rafi
+    from paper_2605_30294_amd import workloads as W
+
+    n, grid, N, h, max_steps = 256, (4, 4, 4), 1 << 20, 0.25, 2000
+    field = W.abc_field(n, device=dev)
+    f4 = rafi.sl_pack(field)
+    del field
+    seeds_np = W.streamline_seeds(N, n)
+    seeds = torch.from_numpy(seeds_np).to(dev)
+    ctx = rafi.Context(64, rafi.SL_ITEM_BYTES, N)
+    endpoint = torch.empty((N, 3), dtype=torch.float32, device=dev)
+    steps = torch.empty(N, dtype=torch.int32, device=dev)
+    reason = torch.empty(N, dtype=torch.int32, device=dev)
+    job = rafi.sl_job(f4, grid, endpoint, steps, reason, h, max_steps)
+    for _ in range(args.warmup):
+        rafi.sl_trace_job(ctx, job, seeds)
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    fwd = rounds = 0
+    for _ in range(args.steps):
+        rounds, fwd = rafi.sl_trace_job(ctx, job, seeds)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    prof = ctx.profile()
+    rk4_steps = int(steps.sum().item())
+    ctx.set_profiling(False)
+    log(f"streamlines: {ms:.3f} ms/job, rounds {rounds}, forwarded {fwd}, rk4 steps {rk4_steps}")
+    per_job = 1.0 / args.steps
+    dom_ms = prof["domain_ms"] * per_job
+    split_ms = prof["split_ms"] * per_job
+    launches = prof["domain_calls"] * per_job
+    avg_launch_ms = dom_ms / max(launches, 1)
+    flops_per_launch = rk4_steps * RK4_FLOPS_PER_STEP / max(launches, 1)
+    achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
+    out = dict(ms=ms, rounds=rounds, forwarded=fwd, rk4_steps=rk4_steps, domain_ms=dom_ms, split_ms=split_ms,
+               launches=launches, avg_launch_ms=avg_launch_ms,
+               roofline={"kernel": "advance_kernel (RK4 brick march)", "bound": "alu",
+                         "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+                         "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None,
+                         "per_launch_flops": flops_per_launch, "avg_launch_ms": round(avg_launch_ms, 4)})
+    ctx.close()
+    return out, seeds_np
+
+
+def cpu_baseline(seeds_np, n_sample):
+    import numpy as np
+
+    import oracle
+    from paper_2605_30294_amd import workloads as W
+
+    field = W.abc_field(256)
+    sample = np.ascontiguousarray(seeds_np[:n_sample])
+    t = time.perf_counter()
+    r = oracle.streamlines(field, (4, 4, 4), sample, h=0.25, max_steps=2000)
+    dt = time.perf_counter() - t
+    fwd = int(r["round_counts"].sum())
+    log(f"cpu oracle: {n_sample} seeds in {dt:.2f} s, forwarded {fwd}")
+    return {"value": fwd / dt, "unit": "forwarded items/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_sample} of the 1M seeds, same field/grid/RK4 settings, "
+                      f"single-threaded C oracle ({dt:.1f} s, {int(r['steps'].sum())} RK4 steps)",
+            "rk4_steps_per_s": float(r["steps"].sum()) / dt}
+
+
+def split_microbench(dev, reps):
+    import numpy as np
+    import torch
+
+    from paper_2605_30294_amd import rafi
+    from paper_2605_30294_amd import workloads as W
+
+    N, D, S = 1 << 26, 1024, 32
+    items = torch.from_numpy(W.split_items(N).view(np.int32)).to(dev)
+    res = {}
+    ctx = rafi.Context(D, S, N)
+    for dist in ("uniform", "zipf"):
+        dest = torch.from_numpy(W.split_dest(N, D, dist)).to(dev)
+        ctx.begin(N)
+        ctx.emit_bulk(items, dest)
+        ctx.round(counts=False)                      # warm-up; slots are left intact
+        ctx.set_profiling(True)
+        for _ in range(reps):
+            ctx.round(counts=False)
+        p = ctx.profile()
+        ctx.set_profiling(False)
+        split_ms = p["split_ms"] / p["split_calls"]
+        scat_ms = p["scatter_ms"] / p["scatter_calls"]
+        alg = split_bytes_per_item(S) * N
+        res[dist] = {"split_ms": round(split_ms, 4), "scatter_ms": round(scat_ms, 4),
+                     "items_per_s": N / (split_ms * 1e-3), "GBps": alg / (split_ms * 1e-3) / 1e9,
+                     "frac_hbm": alg / (split_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        log(f"split {dist}: {split_ms:.3f} ms ({res[dist]['GBps']:.0f} GB/s algorithmic), scatter {scat_ms:.3f} ms")
+        del dest
+    ctx.close()
+    del items
+    torch.cuda.empty_cache()
+    return res
+
+
+def ea_forward(dev, reps):
+    import numpy as np
+    import torch
+
+    from paper_2605_30294_amd import rafi
+    from paper_2605_30294_amd import workloads as W
+
+    n, grid = 128, (4, 4, 4)
+    vol = W.blob_volume(n, W.SEED_ADJ_VOLUME, device=dev)
+    views = W.random_views(64, n, 256, 256)
+    c = float(np.float32(0.025))
+    r = rafi.ea_render(vol, grid, views, c=c, want_tau=True)
+    ctx, job = r["ctx"], r["job"]
+    torch.cuda.synchronize()
+    kl, kf = r["klast"], r["kfirst"]
+    samples = int((kl - kf).clamp(min=0).sum().item())
+    ctx.set_profiling(True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        rounds = rafi.ea_render_job(ctx, job)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    p = ctx.profile()
+    ctx.close()
+    out = {"workload": "128^3 blobs, 4x4x4 domains, 64 views x 256^2 rays", "ms": round(ms, 4),
+           "rounds": rounds, "samples": samples, "samples_per_s": samples / (ms * 1e-3),
+           "march_ms": round(p["domain_ms"] / reps, 4), "split_ms": round(p["split_ms"] / reps, 4),
+           "rays_forwarded_per_s": p["split_items"] / reps / (ms * 1e-3)}
+    log(f"ea forward: {ms:.3f} ms, {samples} samples, {out['samples_per_s']:.3g} samples/s")
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seeds", type=int, default=32768)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: every domain of the forwarding path is resident on a "
+              "single MI355X and there is no multi-GPU exchange in this build; run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    sl, seeds_np = streamline_job(args, dev)
+    extras = {}
+    if not args.no_extras:
+        extras["multisplit_64M_x32B_1024dest"] = split_microbench(dev, reps=20)
+        extras["ea_forward"] = ea_forward(dev, reps=5)
+    cpu = None if args.no_cpu else cpu_baseline(seeds_np, args.cpu_seeds)
+
+    value = sl["forwarded"] / (sl["ms"] * 1e-3)
+    line = {
+        "metric": METRIC, "value": value, "unit": "forwarded items/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sl["ms"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "streamlines: 256^3 ABC field (A=1, B=sqrt(2/3), C=sqrt(1/3)), 4x4x4 domains, "
+                               "1M uniform seeds, RK4 h=0.25 voxel, <=2000 steps, forwarded at every brick exit",
+                   "seeds": 1 << 20, "domains": 64, "item_bytes": 16},
+        "samples_per_s": sl["rk4_steps"] / (sl["ms"] * 1e-3),
+        "samples_unit": "RK4 steps/s",
+        "rounds": sl["rounds"], "forwarded_per_step": sl["forwarded"],
+        "time_split": {"domain_kernels_ms": round(sl["domain_ms"], 4), "forward_steps_ms": round(sl["split_ms"], 4)},
+        "roofline": sl["roofline"],
+        "cpu_baseline": cpu,
+        "extras": extras,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -132,6 +132,11 @@ int rafi_view(const rafi_ctx *ctx, rafi_device_view *out);
  * seeding) that emits into slots [0, n_slots). */
 int rafi_begin(rafi_ctx *ctx, uint64_t n_slots);
 
+/* Bulk emission from device arrays: copy items [n * item_bytes] and dest [n]
+ * (both device) into output slots [0, n) (n <= n_slots), as a generator
+ * kernel would with rafi_forward. Stream-ordered device-to-device copies. */
+int rafi_emit_bulk(rafi_ctx *ctx, const void *items, const int32_t *dest, uint64_t n);
+
 /*
  * Forward step (forwardRays, Sec. 3.4 and 4.2): stable multi-split of the
  * n_slots output slots by destination into the next input queue. An item
@@ -153,6 +158,25 @@ int rafi_copy_queue(const rafi_ctx *ctx, void *items_dst, uint64_t *offsets_dst)
 
 /* Cumulative statistics (host copy, updated by rafi_round). */
 int rafi_get_stats(const rafi_ctx *ctx, rafi_stats *out);
+
+/*
+ * Per-phase GPU time, measured with HIP events recorded on the context stream
+ * around every launch while profiling is on (rafi_set_profiling). Times are
+ * sums in milliseconds; *_calls count launches. "split" is the whole forward
+ * step, "scatter" its final pass alone, "domain" the domain kernels
+ * (rafi_ea_march, rafi_sl_advance, ...). Event pairs are resolved at the
+ * next rafi_round or rafi_get_profile (which synchronises the stream).
+ */
+typedef struct rafi_profile {
+    double split_ms, scatter_ms, domain_ms;
+    uint64_t split_calls, scatter_calls, domain_calls;
+    uint64_t split_slots;  /* slots consumed by the timed forward steps */
+    uint64_t split_items;  /* items they delivered */
+} rafi_profile;
+
+/* Turn event timing on (1) or off (0); turning it on clears the totals. */
+int rafi_set_profiling(rafi_ctx *ctx, int32_t on);
+int rafi_get_profile(rafi_ctx *ctx, rafi_profile *out);
 
 /* Static string naming an error code. */
 const char *rafi_strerror(int code);
@@ -199,6 +223,7 @@ typedef struct rafi_ea_job {
     float *image;                   /* device [n_views * height * width] result per ray */
     float *tau;                     /* device, optional: final optical depth per ray */
     int32_t *klast;                 /* device, optional: one past the last inside sample */
+    int32_t *kfirst;                /* device, optional: first inside sample (0 for misses) */
     int32_t n;
     int32_t grid[3];
     int32_t n_views, width, height;

@@ -85,6 +85,65 @@ int ctx_fill_poison(rafi_ctx *c, uint64_t n)
     return RAFI_OK;
 }
 
+namespace {
+hipEvent_t take_event(rafi_ctx *c)
+{
+    if (c->pool_size > 0) return c->pool[--c->pool_size];
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void give_event(rafi_ctx *c, hipEvent_t e)
+{
+    if (!e) return;
+    if (c->pool_size < 3 * rafi_ctx::kMaxPending) c->pool[c->pool_size++] = e;
+    else (void)hipEventDestroy(e);
+}
+}  // namespace
+
+int prof_resolve(rafi_ctx *c)
+{
+    if (c->n_pending == 0) return RAFI_OK;
+    RAFI_HIP_CHECK(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < c->n_pending; ++i) {
+        rafi_ctx::Pending &p = c->pending[i];
+        float a = 0.0f, b = 0.0f;
+        if (p.kind == 0) {
+            if (hipEventElapsedTime(&a, p.e[0], p.e[2]) == hipSuccess) c->prof.split_ms += a;
+            if (hipEventElapsedTime(&b, p.e[1], p.e[2]) == hipSuccess) c->prof.scatter_ms += b;
+            c->prof.split_calls++;
+            c->prof.scatter_calls++;
+            c->prof.split_slots += p.slots;
+        } else {
+            if (hipEventElapsedTime(&a, p.e[0], p.e[1]) == hipSuccess) c->prof.domain_ms += a;
+            c->prof.domain_calls++;
+        }
+        for (int k = 0; k < (p.kind == 0 ? 3 : 2); ++k) give_event(c, p.e[k]);
+    }
+    c->n_pending = 0;
+    return RAFI_OK;
+}
+
+int prof_domain_begin(rafi_ctx *c)
+{
+    if (!c->prof_on) return -1;
+    if (c->n_pending >= rafi_ctx::kMaxPending && prof_resolve(c) != RAFI_OK) return -1;
+    rafi_ctx::Pending &p = c->pending[c->n_pending];
+    p.kind = 1;
+    p.e[0] = take_event(c);
+    p.e[1] = take_event(c);
+    p.slots = 0;
+    if (!p.e[0] || !p.e[1] || hipEventRecord(p.e[0], c->stream) != hipSuccess) return -1;
+    return c->n_pending++;
+}
+
+void prof_domain_end(rafi_ctx *c, int h)
+{
+    if (h < 0) return;
+    (void)hipEventRecord(c->pending[h].e[1], c->stream);
+}
+
 }  // namespace rafi
 
 using namespace rafi;
@@ -145,6 +204,10 @@ void rafi_destroy(rafi_ctx *c)
     if (c->summary) (void)hipFree(c->summary);
     if (c->dropped) (void)hipFree(c->dropped);
     if (c->host_summary) (void)hipHostFree(c->host_summary);
+    for (int i = 0; i < c->n_pending; ++i)
+        for (int k = 0; k < (c->pending[i].kind == 0 ? 3 : 2); ++k)
+            if (c->pending[i].e[k]) (void)hipEventDestroy(c->pending[i].e[k]);
+    for (int i = 0; i < c->pool_size; ++i) (void)hipEventDestroy(c->pool[i]);
     delete c;
 }
 
@@ -209,13 +272,37 @@ int rafi_begin(rafi_ctx *c, uint64_t n_slots)
     return ctx_fill_poison(c, n_slots);
 }
 
+int rafi_emit_bulk(rafi_ctx *c, const void *items, const int32_t *dest, uint64_t n)
+{
+    if (!c || n > c->n_slots || (n && (!items || !dest))) return RAFI_ERR_ARG;
+    if (n == 0) return RAFI_OK;
+    RAFI_HIP_CHECK(hipMemcpyAsync(c->buf[1], items, n * c->S, hipMemcpyDeviceToDevice, c->stream));
+    RAFI_HIP_CHECK(hipMemcpyAsync(c->dest, dest, n * sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream));
+    return RAFI_OK;
+}
+
 int rafi_round(rafi_ctx *c, uint64_t *counts, uint64_t *total)
 {
     if (!c) return RAFI_ERR_ARG;
     const SplitPlan p = split_plan(c->n_slots, c->D, c->S);
     if (p.bytes > c->ws_bytes) return RAFI_ERR_STATE;
+    SplitEvents ev;
+    const SplitEvents *evp = nullptr;
+    if (c->prof_on && (c->n_pending < rafi_ctx::kMaxPending || prof_resolve(c) == RAFI_OK)) {
+        rafi_ctx::Pending &pp = c->pending[c->n_pending];
+        pp.kind = 0;
+        pp.slots = c->n_slots;
+        for (int k = 0; k < 3; ++k) pp.e[k] = take_event(c);
+        if (pp.e[0] && pp.e[1] && pp.e[2]) {
+            ev.begin = pp.e[0];
+            ev.before_scatter = pp.e[1];
+            ev.end = pp.e[2];
+            evp = &ev;
+            c->n_pending++;
+        }
+    }
     int rc = split_run(p, c->buf[1], c->dest, c->buf[0], c->offsets, c->summary, c->tile_offsets,
-                       c->tile_items, c->ws, c->stream);
+                       c->tile_items, c->ws, c->stream, evp);
     if (rc != RAFI_OK) return rc;
     RAFI_HIP_CHECK(hipMemcpyAsync(c->host_summary, c->summary, sizeof(uint64_t) * 4, hipMemcpyDeviceToHost,
                                   c->stream));
@@ -237,6 +324,11 @@ int rafi_round(rafi_ctx *c, uint64_t *counts, uint64_t *total)
         RAFI_HIP_CHECK(hipStreamSynchronize(c->stream));
     }
     const uint64_t *h = c->host_summary;
+    if (evp) c->prof.split_items += h[0];
+    if (c->n_pending) {
+        rc = prof_resolve(c);
+        if (rc != RAFI_OK) return rc;
+    }
     c->n_in = h[0];
     c->n_slots = h[0];
     c->n_tiles = (uint32_t)h[3];
@@ -262,6 +354,25 @@ int rafi_copy_queue(const rafi_ctx *c, void *items_dst, uint64_t *offsets_dst)
     if (offsets_dst)
         RAFI_HIP_CHECK(hipMemcpyAsync(offsets_dst, c->offsets, sizeof(uint64_t) * (c->D + 1),
                                       hipMemcpyDeviceToDevice, c->stream));
+    return RAFI_OK;
+}
+
+int rafi_set_profiling(rafi_ctx *c, int32_t on)
+{
+    if (!c) return RAFI_ERR_ARG;
+    int rc = prof_resolve(c);
+    if (rc != RAFI_OK) return rc;
+    c->prof_on = on ? 1 : 0;
+    if (on) c->prof = rafi_profile{};
+    return RAFI_OK;
+}
+
+int rafi_get_profile(rafi_ctx *c, rafi_profile *out)
+{
+    if (!c || !out) return RAFI_ERR_ARG;
+    int rc = prof_resolve(c);
+    if (rc != RAFI_OK) return rc;
+    *out = c->prof;
     return RAFI_OK;
 }
 

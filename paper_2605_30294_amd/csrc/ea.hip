@@ -157,8 +157,10 @@ raygen_kernel(rafi_device_view view, rafi_ea_job job, uint64_t n_rays)
         float p[3];
         sample_pos(org, dir, job.dt, k_lo, p);
         it.k = k_lo;
+        if (job.kfirst) job.kfirst[r] = k_lo;
         rafi_forward_t(view, r, it, owner_of(p, g));
     } else {
+        if (job.kfirst) job.kfirst[r] = 0;
         job.image[r] = 0.0f;
         if (job.tau) job.tau[r] = 0.0f;
         if (job.klast) job.klast[r] = 0;
@@ -272,9 +274,11 @@ int rafi_ea_march(rafi_ctx *c, const rafi_ea_job *job)
     if (!job_ok(c, job)) return RAFI_ERR_ARG;
     rafi_device_view v;
     rafi_view(c, &v);
+    const int ph = prof_domain_begin(c);
     if (v.n_in)
         hipLaunchKernelGGL(march_kernel, dim3((uint32_t)((v.n_in + 255) / 256)), dim3(256), 0, c->stream, v,
                            *job, (uint32_t)((uint64_t)job->n_views * job->width * job->height));
+    prof_domain_end(c, ph);
     RAFI_LAUNCH_CHECK();
     return RAFI_OK;
 }

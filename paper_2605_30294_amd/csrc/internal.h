@@ -49,12 +49,17 @@ SplitPlan split_plan(uint64_t n, int32_t D, uint32_t S);
 // A plan whose workspace covers every n <= cap.
 SplitPlan split_plan_bound(uint64_t cap, int32_t D, uint32_t S);
 
+// Optional events recorded around the split's passes (on the split stream).
+struct SplitEvents {
+    hipEvent_t begin = nullptr, before_scatter = nullptr, end = nullptr;
+};
+
 // Run the split. offsets: device u64 [D+1]; summary: device u64 [4]
 // {total, done, bad, n_tiles_app}; tile_offsets (optional): device u32 [D+1]
 // built for tiles of tile_items.
 int split_run(const SplitPlan &p, const void *items, const int32_t *dest, void *out,
               uint64_t *offsets, uint64_t *summary, uint32_t *tile_offsets, uint32_t tile_items,
-              void *workspace, hipStream_t stream);
+              void *workspace, hipStream_t stream, const SplitEvents *ev = nullptr);
 
 }  // namespace rafi
 
@@ -80,8 +85,27 @@ struct rafi_ctx {
     uint32_t tile_items = 256, n_tiles = 0;
     int debug = 0;
     rafi_stats stats{};
+    // profiling: event pairs waiting to be resolved
+    int prof_on = 0;
+    rafi_profile prof{};
+    struct Pending {
+        int kind;  // 0 split (3 events), 1 domain (2 events)
+        hipEvent_t e[3];
+        uint64_t slots;
+    };
+    static constexpr int kMaxPending = 64;
+    Pending pending[kMaxPending];
+    int n_pending = 0;
+    hipEvent_t pool[3 * kMaxPending];
+    int pool_size = 0;
 };
 
 namespace rafi {
 int ctx_fill_poison(rafi_ctx *ctx, uint64_t n);
+// Domain-kernel timing: prof_domain_begin returns a handle (or -1 when off)
+// to pass to prof_domain_end after the launch.
+int prof_domain_begin(rafi_ctx *ctx);
+void prof_domain_end(rafi_ctx *ctx, int h);
+// Resolve all pending event pairs (synchronises the context stream).
+int prof_resolve(rafi_ctx *ctx);
 }

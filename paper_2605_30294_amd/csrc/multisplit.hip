@@ -371,9 +371,10 @@ SplitPlan split_plan_bound(uint64_t cap, int32_t D, uint32_t S)
 
 int split_run(const SplitPlan &p, const void *items, const int32_t *dest, void *out,
               uint64_t *offsets, uint64_t *summary, uint32_t *tile_offsets, uint32_t tile_items,
-              void *workspace, hipStream_t s)
+              void *workspace, hipStream_t s, const SplitEvents *ev)
 {
     if (p.scan_blocks > (uint32_t)kPartMax) return RAFI_ERR_ARG;
+    if (ev) RAFI_HIP_CHECK(hipEventRecord(ev->begin, s));
     uint32_t *table = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + p.off_table);
     uint32_t *part = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + p.off_part);
     if (p.n_tiles > 0) {
@@ -391,7 +392,11 @@ int split_run(const SplitPlan &p, const void *items, const int32_t *dest, void *
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, s, table, p.n_tiles, p.D, p.n,
                        offsets, summary, tile_offsets, tile_items ? tile_items : 1u);
     RAFI_LAUNCH_CHECK();
-    if (p.n_tiles == 0) return RAFI_OK;
+    if (ev) RAFI_HIP_CHECK(hipEventRecord(ev->before_scatter, s));
+    if (p.n_tiles == 0) {
+        if (ev) RAFI_HIP_CHECK(hipEventRecord(ev->end, s));
+        return RAFI_OK;
+    }
     const uint32_t *it = static_cast<const uint32_t *>(items);
     uint32_t *o = static_cast<uint32_t *>(out);
     switch (p.S / 4) {
@@ -407,6 +412,7 @@ int split_run(const SplitPlan &p, const void *items, const int32_t *dest, void *
     default: launch_scatter<0>(p, it, dest, table, o, s); break;
     }
     RAFI_LAUNCH_CHECK();
+    if (ev) RAFI_HIP_CHECK(hipEventRecord(ev->end, s));
     return RAFI_OK;
 }
 

@@ -212,9 +212,11 @@ int rafi_sl_advance(rafi_ctx *c, const rafi_sl_job *job, int32_t one_step)
     if (!job_ok(c, job)) return RAFI_ERR_ARG;
     rafi_device_view v;
     rafi_view(c, &v);
+    const int ph = prof_domain_begin(c);
     if (v.n_in)
         hipLaunchKernelGGL(advance_kernel, dim3((uint32_t)((v.n_in + 255) / 256)), dim3(256), 0, c->stream, v,
                            *job, one_step, c->wave_slots);
+    prof_domain_end(c, ph);
     RAFI_LAUNCH_CHECK();
     return RAFI_OK;
 }

@@ -48,9 +48,15 @@ class Stats(C.Structure):
                 ("bad_dest", C.c_uint64), ("dropped", C.c_uint64), ("last_total", C.c_uint64)]
 
 
+class Profile(C.Structure):
+    _fields_ = [("split_ms", C.c_double), ("scatter_ms", C.c_double), ("domain_ms", C.c_double),
+                ("split_calls", C.c_uint64), ("scatter_calls", C.c_uint64), ("domain_calls", C.c_uint64),
+                ("split_slots", C.c_uint64), ("split_items", C.c_uint64)]
+
+
 class EAJob(C.Structure):
     _fields_ = [("volume", C.c_void_p), ("views", C.c_void_p), ("image", C.c_void_p), ("tau", C.c_void_p),
-                ("klast", C.c_void_p), ("n", C.c_int32), ("grid", C.c_int32 * 3), ("n_views", C.c_int32),
+                ("klast", C.c_void_p), ("kfirst", C.c_void_p), ("n", C.c_int32), ("grid", C.c_int32 * 3), ("n_views", C.c_int32),
                 ("width", C.c_int32), ("height", C.c_int32), ("dt", C.c_float), ("c", C.c_float),
                 ("pad", C.c_int32)]
 
@@ -72,8 +78,11 @@ _SIGS = {
     "rafi_view": ([_P, C.POINTER(DeviceView)], C.c_int),
     "rafi_begin": ([_P, C.c_uint64], C.c_int),
     "rafi_round": ([_P, _P, _U64P], C.c_int),
+    "rafi_emit_bulk": ([_P, _P, _P, C.c_uint64], C.c_int),
     "rafi_copy_queue": ([_P, _P, _P], C.c_int),
     "rafi_get_stats": ([_P, C.POINTER(Stats)], C.c_int),
+    "rafi_set_profiling": ([_P, C.c_int32], C.c_int),
+    "rafi_get_profile": ([_P, C.POINTER(Profile)], C.c_int),
     "rafi_strerror": ([C.c_int], C.c_char_p),
     "rafi_multisplit_workspace": ([C.c_uint64, C.c_int32, C.c_uint32, _U64P], C.c_int),
     "rafi_multisplit": ([_P, _P, C.c_uint64, C.c_uint32, C.c_int32, _P, _P, _P, _P, C.c_uint64, _P], C.c_int),
@@ -175,6 +184,9 @@ class Context:
     def begin(self, n_slots: int):
         _check(lib().rafi_begin(self._h, n_slots), "rafi_begin")
 
+    def emit_bulk(self, items: torch.Tensor, dest: torch.Tensor):
+        _check(lib().rafi_emit_bulk(self._h, _dptr(items), _dptr(dest), dest.numel()), "rafi_emit_bulk")
+
     def round(self, counts: bool = True, allow=(RAFI_OK,)):
         """Forward step. Returns (counts array or None, total, return code)."""
         cnt = np.zeros(self.n_domains, dtype=np.uint64) if counts else None
@@ -192,6 +204,14 @@ class Context:
         _check(lib().rafi_copy_queue(self._h, _dptr(items), _dptr(offs)), "rafi_copy_queue")
         torch.cuda.synchronize()
         return items[:n_in], offs.cpu().numpy().astype(np.uint64)
+
+    def set_profiling(self, on: bool):
+        _check(lib().rafi_set_profiling(self._h, int(on)), "rafi_set_profiling")
+
+    def profile(self) -> dict:
+        p = Profile()
+        _check(lib().rafi_get_profile(self._h, C.byref(p)), "rafi_get_profile")
+        return {k: getattr(p, k) for k, _ in Profile._fields_}
 
     def stats(self) -> dict:
         s = Stats()
@@ -232,9 +252,9 @@ def multisplit(items: torch.Tensor, dest: torch.Tensor, n_domains: int, out=None
 # -------------------------------------------------------------- EA march ---
 
 def ea_job(volume: torch.Tensor, grid, views_dev: torch.Tensor, n_views: int, width: int, height: int,
-           image: torch.Tensor, tau=None, klast=None, dt=0.5, c=0.025) -> EAJob:
+           image: torch.Tensor, tau=None, klast=None, dt=0.5, c=0.025, kfirst=None) -> EAJob:
     n = volume.shape[0]
-    return EAJob(_dptr(volume), _dptr(views_dev), _dptr(image), _dptr(tau), _dptr(klast), n,
+    return EAJob(_dptr(volume), _dptr(views_dev), _dptr(image), _dptr(tau), _dptr(klast), _dptr(kfirst), n,
                  (C.c_int32 * 3)(*[int(g) for g in grid]), n_views, width, height, float(dt), float(c), 0)
 
 
@@ -266,9 +286,11 @@ def ea_render(volume: torch.Tensor, grid, views: np.ndarray, dt=0.5, c=0.025, ct
     image = torch.empty(n_rays, dtype=torch.float32, device=dev)
     tau = torch.empty(n_rays, dtype=torch.float32, device=dev) if want_tau else None
     klast = torch.empty(n_rays, dtype=torch.int32, device=dev) if want_tau else None
-    job = ea_job(volume, grid, vdev, nv, w, h, image, tau, klast, dt, c)
+    kfirst = torch.empty(n_rays, dtype=torch.int32, device=dev) if want_tau else None
+    job = ea_job(volume, grid, vdev, nv, w, h, image, tau, klast, dt, c, kfirst)
     rounds = ea_render_job(ctx, job, max_rounds)
-    return dict(image=image, tau=tau, klast=klast, rounds=rounds, ctx=ctx)
+    return dict(image=image, tau=tau, klast=klast, kfirst=kfirst, rounds=rounds, ctx=ctx, job=job,
+                views_dev=vdev)
 
 
 # ------------------------------------------------------------ streamlines ---

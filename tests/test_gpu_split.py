@@ -70,20 +70,14 @@ def test_context_round_and_error_paths(orc):
     D, S, cap = 16, 16, 10_000
     ctx = rafi.Context(D, S, cap, debug=True)
     ctx.begin(5000)
-    v = ctx.view()
-    # write slots from the host through torch: a stand-in for a generator kernel
+    # bulk emission from device arrays stands in for a generator kernel
     rng = np.random.default_rng(3)
     items = rng.integers(0, 2**31, (5000, 4)).astype(np.int32)
     dest = rng.integers(-1, D, 5000).astype(np.int32)
     dest[4000:] = rafi.RAFI_POISON                   # slots a "kernel" never wrote
     t_items = torch.from_numpy(items).to(dev)
     t_dest = torch.from_numpy(dest[:4000]).to(dev)
-    torch.cuda.synchronize()
-    import ctypes as C
-    hip = C.CDLL("libamdhip64.so.7")   # the runtime torch already loaded (matched by soname)
-    hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
-    assert hip.hipMemcpy(C.c_void_p(v.out_items), C.c_void_p(t_items.data_ptr()), 5000 * 16, 3) == 0
-    assert hip.hipMemcpy(C.c_void_p(v.out_dest), C.c_void_p(t_dest.data_ptr()), 4000 * 4, 3) == 0
+    ctx.emit_bulk(t_items[:4000], t_dest)             # slots 4000.. stay poisoned
     counts, total, rc = ctx.round(allow=(rafi.RAFI_OK, rafi.ERR_BAD_DEST))
     assert rc == rafi.ERR_BAD_DEST                    # 1000 poisoned slots counted as bad
     e_out, e_counts, e_off, e_done, e_bad = orc.multisplit(items, dest, D)
