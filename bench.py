@@ -8,8 +8,12 @@ all forward steps (stable multi-split) and all domain-kernel launches, inputs
 resident in HBM before the timed region starts.
 
 Prints ONE JSON line. `value` is forwarded items per second over the whole
-job (items delivered by all forward steps, seeding round included, divided
-by the job's wall time on the GPU). Also reported: RK4 steps per second, the
+job: the forwards the workload itself requires (every seed delivered to its
+first brick plus every brick-exit forward; a property of the workload, the
+same for any schedule) divided by the job's GPU wall time. A particle that
+has taken `--steps-per-visit` steps in one launch is also forwarded to its
+own brick so that a round never waits on one long-lived particle; those
+same-brick forwards are reported separately and not counted in `value`. Also reported: RK4 steps per second, the
 roofline of the dominant kernel (the RK4 brick kernel) from HIP events taken
 on the stream it runs on, the CPU oracle on a bounded sample, and extras: the
 64M-item x 32-byte multi-split microbenchmark (uniform and Zipf over 1024
@@ -68,10 +72,12 @@ def streamline_job(args, dev):
     endpoint = torch.empty((N, 3), dtype=torch.float32, device=dev)
     steps = torch.empty(N, dtype=torch.int32, device=dev)
     reason = torch.empty(N, dtype=torch.int32, device=dev)
-    job = rafi.sl_job(f4, grid, endpoint, steps, reason, h, max_steps)
+    counters = torch.zeros(2, dtype=torch.int64, device=dev)
+    job = rafi.sl_job(f4, grid, endpoint, steps, reason, h, max_steps, args.steps_per_visit, counters)
     for _ in range(args.warmup):
         rafi.sl_trace_job(ctx, job, seeds)
     torch.cuda.synchronize()
+    counters.zero_()
     ctx.set_profiling(True)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -84,8 +90,11 @@ def streamline_job(args, dev):
     ms = t0.elapsed_time(t1) / args.steps
     prof = ctx.profile()
     rk4_steps = int(steps.sum().item())
+    cross = int(counters[0].item()) // args.steps
+    self_fwd = int(counters[1].item()) // args.steps
     ctx.set_profiling(False)
-    log(f"streamlines: {ms:.3f} ms/job, rounds {rounds}, forwarded {fwd}, rk4 steps {rk4_steps}")
+    log(f"streamlines: {ms:.3f} ms/job, rounds {rounds}, forward-step items {fwd} "
+        f"(seeds {N}, cross-brick {cross}, same-brick {self_fwd}), rk4 steps {rk4_steps}")
     per_job = 1.0 / args.steps
     dom_ms = prof["domain_ms"] * per_job
     split_ms = prof["split_ms"] * per_job
@@ -93,7 +102,8 @@ def streamline_job(args, dev):
     avg_launch_ms = dom_ms / max(launches, 1)
     flops_per_launch = rk4_steps * RK4_FLOPS_PER_STEP / max(launches, 1)
     achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
-    out = dict(ms=ms, rounds=rounds, forwarded=fwd, rk4_steps=rk4_steps, domain_ms=dom_ms, split_ms=split_ms,
+    out = dict(ms=ms, rounds=rounds, forwarded=N + cross, step_items=fwd, self_fwd=self_fwd, rk4_steps=rk4_steps,
+               domain_ms=dom_ms, split_ms=split_ms,
                launches=launches, avg_launch_ms=avg_launch_ms,
                roofline={"kernel": "advance_kernel (RK4 brick march)", "bound": "alu",
                          "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
@@ -199,7 +209,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-seeds", type=int, default=32768)
+    ap.add_argument("--cpu-seeds", type=int, default=262144)
+    ap.add_argument("--steps-per-visit", type=int, default=64,
+                    help="RK4 steps a particle takes per domain visit before it is forwarded to its own "
+                         "brick (0 = until it leaves); results do not depend on it")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -231,6 +244,8 @@ def main():
         "samples_per_s": sl["rk4_steps"] / (sl["ms"] * 1e-3),
         "samples_unit": "RK4 steps/s",
         "rounds": sl["rounds"], "forwarded_per_step": sl["forwarded"],
+        "forward_step_items_per_step": sl["step_items"], "same_brick_forwards_per_step": sl["self_fwd"],
+        "steps_per_visit": args.steps_per_visit,
         "time_split": {"domain_kernels_ms": round(sl["domain_ms"], 4), "forward_steps_ms": round(sl["split_ms"], 4)},
         "roofline": sl["roofline"],
         "cpu_baseline": cpu,

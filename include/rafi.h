@@ -267,10 +267,17 @@ typedef struct rafi_sl_job {
     float *endpoint;       /* device [n_seeds * 3] final position per particle id */
     int32_t *steps;        /* device [n_seeds] steps taken */
     int32_t *reason;       /* device [n_seeds] 1 stagnant, 2 exited, 3 max steps; optional */
+    unsigned long long *counters; /* device [2], optional, accumulated: forwards to another
+                                     brick, forwards to the same brick (step cap) */
     int32_t n;
     int32_t grid[3];
     float h;
     int32_t max_steps;
+    int32_t steps_per_visit; /* 0: integrate until the particle leaves its brick; k > 0: at
+                                most k steps per domain-kernel launch, then the particle is
+                                forwarded even to its own brick (k = 1 is the paper's one
+                                update per round). Results do not depend on k. */
+    int32_t pad;
 } rafi_sl_job;
 
 /* Item: position (3 x float32) and particle id; the step count lives in
@@ -288,9 +295,8 @@ int rafi_sl_pack(const float *field, int32_t n, float *field4, void *hip_stream)
 int rafi_sl_seed(rafi_ctx *ctx, const rafi_sl_job *job, const float *seeds, uint64_t n_seeds);
 
 /* One domain-kernel launch: every particle integrates until it leaves its
- * brick or finishes. With one_step != 0 it takes exactly one step and is
- * forwarded even to its own brick (the one-update-per-round form). */
-int rafi_sl_advance(rafi_ctx *ctx, const rafi_sl_job *job, int32_t one_step);
+ * brick, finishes, or has taken job->steps_per_visit steps in this launch. */
+int rafi_sl_advance(rafi_ctx *ctx, const rafi_sl_job *job);
 
 /* Whole trace: seed, then rafi_round / rafi_sl_advance until no particle is
  * left. *rounds receives the number of forward steps; *forwarded (optional)

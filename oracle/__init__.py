@@ -208,7 +208,9 @@ def _sl_params(n, grid, h, max_steps):
 
 
 def streamlines(field, grid, seeds, h=0.25, max_steps=2000, one_step=False, max_rounds=100000,
-                queue_cap=0, visit_stride=0, want_rounds=True):
+                queue_cap=0, visit_stride=0, want_rounds=True, steps_per_visit=0):
+    """Partitioned round loop (O2 + O4). steps_per_visit caps the RK4 steps a
+    particle takes per domain visit (0 = until it leaves; one_step means 1)."""
     f = np.ascontiguousarray(field, dtype=np.float32)
     n = f.shape[0]
     s = np.ascontiguousarray(seeds, dtype=np.float32)
@@ -222,7 +224,8 @@ def streamlines(field, grid, seeds, h=0.25, max_steps=2000, one_step=False, max_
     q = np.zeros(max(queue_cap, 1), dtype=np.int32) if queue_cap else None
     qlen = C.c_uint64(0)
     vis = np.zeros((N, visit_stride), dtype=np.int32) if visit_stride else None
-    rounds = lib().oracle_streamlines(_ptr(f), C.byref(P), _ptr(s), N, int(one_step), _ptr(ep),
+    cap = 1 if one_step else int(steps_per_visit)
+    rounds = lib().oracle_streamlines(_ptr(f), C.byref(P), _ptr(s), N, cap, _ptr(ep),
                                       _ptr(st), _ptr(why), max_rounds, _ptr(rc), _ptr(q), queue_cap,
                                       C.byref(qlen), _ptr(vis), visit_stride)
     if rounds < 0:

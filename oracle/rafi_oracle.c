@@ -581,13 +581,13 @@ typedef struct {
 } orc_particle;
 
 /* Advance one particle inside brick d. Returns its destination; on finish
- * sets *reason. With one_step set, at most one RK4 step is taken and a
- * particle that stays inside d is forwarded to d itself (the paper's
- * one-update-per-round form, Sec. 5.4). */
+ * sets *reason. With cap > 0, at most cap RK4 steps are taken and a particle
+ * still inside d is then forwarded to d itself; cap = 1 is the paper's one
+ * update per round (Sec. 5.4), cap = 0 integrates until the particle leaves. */
 static int32_t sl_advance(const float *field, const orc_sl_params *P, orc_particle *it,
-                          int32_t d, int one_step, int32_t *reason)
+                          int32_t d, int32_t cap, int32_t *reason)
 {
-    for (;;) {
+    for (int32_t taken = 1;; ++taken) {
         float pn[3];
         rk4_step(field, P->n, P->h, it->p, pn);
         it->steps++;
@@ -597,7 +597,7 @@ static int32_t sl_advance(const float *field, const orc_sl_params *P, orc_partic
         int32_t e = owner_of(pn, P->n, P->g);
         if (e < 0) { *reason = ORC_SL_EXITED; return ORC_DONE; }
         if (it->steps >= P->max_steps) { *reason = ORC_SL_MAXSTEPS; return ORC_DONE; }
-        if (e != d || one_step) return e;
+        if (e != d || (cap > 0 && taken >= cap)) return e;
     }
 }
 
@@ -608,7 +608,7 @@ static int32_t sl_advance(const float *field, const orc_sl_params *P, orc_partic
  * round_counts / queue_log (particle ids) / visit_log as in oracle_ea_render.
  */
 int oracle_streamlines(const float *field, const orc_sl_params *P, const float *seeds,
-                       int64_t n_seeds, int32_t one_step, float *endpoint, int32_t *steps,
+                       int64_t n_seeds, int32_t steps_per_visit, float *endpoint, int32_t *steps,
                        int32_t *reason, int32_t max_rounds, uint64_t *round_counts,
                        int32_t *queue_log, uint64_t queue_cap, uint64_t *queue_len,
                        int32_t *visit_log, int32_t visit_stride)
@@ -666,7 +666,7 @@ int oracle_streamlines(const float *field, const orc_sl_params *P, const float *
             for (uint64_t i = offs[d]; i < offs[d + 1]; ++i) {
                 orc_particle it = Q[i];
                 int32_t why = ORC_SL_LIVE;
-                int32_t e = sl_advance(field, P, &it, d, one_step, &why);
+                int32_t e = sl_advance(field, P, &it, d, steps_per_visit, &why);
                 O[n_out] = it;
                 odest[n_out] = e;
                 n_out++;

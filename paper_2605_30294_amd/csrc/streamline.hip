@@ -23,8 +23,16 @@ static_assert(sizeof(SLItem) == RAFI_SL_ITEM_BYTES, "item layout");
 
 __device__ inline float lerpf(float a, float b, float t) { return __fmaf_rn(t, b - a, a); }
 
-__device__ inline void field_at(const float4 *__restrict__ f, int32_t n, float qx, float qy, float qz,
-                                float &vx, float &vy, float &vz)
+// The 8 voxels around the last sample point, kept in registers: consecutive
+// RK4 stages and steps usually fall in the same cell (a step moves a particle
+// by a fraction of a voxel), and then no memory is touched. Reuse is exact.
+struct CellCache {
+    int64_t base = -1;  // linear index of corner (i0, j0, k0), -1 = empty
+    float4 c[8];
+};
+
+__device__ inline void field_at(const float4 *__restrict__ f, int32_t n, CellCache &cc, float qx, float qy,
+                                float qz, float &vx, float &vy, float &vz)
 {
     const float hi = (float)(n - 1);
     float u[3] = {qx - 0.5f, qy - 0.5f, qz - 0.5f};
@@ -37,13 +45,24 @@ __device__ inline void field_at(const float4 *__restrict__ f, int32_t n, float q
         i0[a] = i;
         w[a] = uc - (float)i;
     }
-    const size_t sy = (size_t)n, sz = (size_t)n * n;
-    const float4 *b = f + i0[0] + sy * i0[1] + sz * i0[2];
-    const float4 c000 = b[0], c100 = b[1], c010 = b[sy], c110 = b[sy + 1];
-    const float4 c001 = b[sz], c101 = b[sz + 1], c011 = b[sz + sy], c111 = b[sz + sy + 1];
-#define TRI(comp)                                                       \
-    lerpf(lerpf(lerpf(c000.comp, c100.comp, w[0]), lerpf(c010.comp, c110.comp, w[0]), w[1]), \
-          lerpf(lerpf(c001.comp, c101.comp, w[0]), lerpf(c011.comp, c111.comp, w[0]), w[1]), w[2])
+    const int64_t sy = n, sz = (int64_t)n * n;
+    const int64_t base = i0[0] + sy * i0[1] + sz * i0[2];
+    if (base != cc.base) {
+        const float4 *b = f + base;
+        cc.c[0] = b[0];
+        cc.c[1] = b[1];
+        cc.c[2] = b[sy];
+        cc.c[3] = b[sy + 1];
+        cc.c[4] = b[sz];
+        cc.c[5] = b[sz + 1];
+        cc.c[6] = b[sz + sy];
+        cc.c[7] = b[sz + sy + 1];
+        cc.base = base;
+    }
+    const float4 *c = cc.c;
+#define TRI(comp)                                                                                   \
+    lerpf(lerpf(lerpf(c[0].comp, c[1].comp, w[0]), lerpf(c[2].comp, c[3].comp, w[0]), w[1]),        \
+          lerpf(lerpf(c[4].comp, c[5].comp, w[0]), lerpf(c[6].comp, c[7].comp, w[0]), w[1]), w[2])
     vx = TRI(x);
     vy = TRI(y);
     vz = TRI(z);
@@ -106,8 +125,20 @@ __device__ inline int32_t find_domain(const uint64_t *__restrict__ off, int32_t 
     return lo;
 }
 
+__device__ inline void count_forwards(unsigned long long *counters, bool cross, bool self_fwd)
+{
+    // one atomic per wave and counter
+    const uint64_t mc = __ballot(cross), ms = __ballot(self_fwd);
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)__ballot(1)) - 1;
+    if (lane == leader) {
+        if (mc) atomicAdd(&counters[0], (unsigned long long)__popcll(mc));
+        if (ms) atomicAdd(&counters[1], (unsigned long long)__popcll(ms));
+    }
+}
+
 __global__ void __launch_bounds__(256)
-advance_kernel(rafi_device_view view, rafi_sl_job job, int32_t one_step, uint64_t n_ids)
+advance_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids)
 {
     const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (i >= view.n_in) return;
@@ -126,19 +157,22 @@ advance_kernel(rafi_device_view view, rafi_sl_job job, int32_t one_step, uint64_
     }
     int32_t steps = job.steps[it.id];
     const float h = job.h, hh = job.h * 0.5f, h6 = (float)((double)job.h / 6.0);
+    const int32_t cap = job.steps_per_visit > 0 ? job.steps_per_visit : 0x7fffffff;
     float x = it.x, y = it.y, z = it.z;
     int32_t dest = d, why = 0;
-    for (;;) {
+    CellCache cc;
+    for (int32_t taken = 0;;) {
         float k1x, k1y, k1z, k2x, k2y, k2z, k3x, k3y, k3z, k4x, k4y, k4z;
-        field_at(F, g.n, x, y, z, k1x, k1y, k1z);
-        field_at(F, g.n, __fmaf_rn(hh, k1x, x), __fmaf_rn(hh, k1y, y), __fmaf_rn(hh, k1z, z), k2x, k2y, k2z);
-        field_at(F, g.n, __fmaf_rn(hh, k2x, x), __fmaf_rn(hh, k2y, y), __fmaf_rn(hh, k2z, z), k3x, k3y, k3z);
-        field_at(F, g.n, __fmaf_rn(h, k3x, x), __fmaf_rn(h, k3y, y), __fmaf_rn(h, k3z, z), k4x, k4y, k4z);
+        field_at(F, g.n, cc, x, y, z, k1x, k1y, k1z);
+        field_at(F, g.n, cc, __fmaf_rn(hh, k1x, x), __fmaf_rn(hh, k1y, y), __fmaf_rn(hh, k1z, z), k2x, k2y, k2z);
+        field_at(F, g.n, cc, __fmaf_rn(hh, k2x, x), __fmaf_rn(hh, k2y, y), __fmaf_rn(hh, k2z, z), k3x, k3y, k3z);
+        field_at(F, g.n, cc, __fmaf_rn(h, k3x, x), __fmaf_rn(h, k3y, y), __fmaf_rn(h, k3z, z), k4x, k4y, k4z);
         const float sx = __fmaf_rn(2.0f, k3x, __fmaf_rn(2.0f, k2x, k1x)) + k4x;
         const float sy = __fmaf_rn(2.0f, k3y, __fmaf_rn(2.0f, k2y, k1y)) + k4y;
         const float sz = __fmaf_rn(2.0f, k3z, __fmaf_rn(2.0f, k2z, k1z)) + k4z;
         const float nx = __fmaf_rn(h6, sx, x), ny = __fmaf_rn(h6, sy, y), nz = __fmaf_rn(h6, sz, z);
         ++steps;
+        ++taken;
         const bool same = __float_as_uint(nx) == __float_as_uint(x) && __float_as_uint(ny) == __float_as_uint(y) &&
                           __float_as_uint(nz) == __float_as_uint(z);
         x = nx;
@@ -149,9 +183,10 @@ advance_kernel(rafi_device_view view, rafi_sl_job job, int32_t one_step, uint64_
         const int32_t e = inside ? d : owner_of(x, y, z, g);
         if (e < 0) { why = RAFI_SL_EXITED; break; }
         if (steps >= job.max_steps) { why = RAFI_SL_MAXSTEPS; break; }
-        if (e != d || one_step) { dest = e; break; }
+        if (e != d || taken >= cap) { dest = e; break; }
     }
     job.steps[it.id] = steps;
+    if (job.counters) count_forwards(job.counters, why == 0 && dest != d, why == 0 && dest == d);
     if (why) {
         job.endpoint[3 * (size_t)it.id] = x;
         job.endpoint[3 * (size_t)it.id + 1] = y;
@@ -169,7 +204,7 @@ advance_kernel(rafi_device_view view, rafi_sl_job job, int32_t one_step, uint64_
 bool job_ok(const rafi_ctx *c, const rafi_sl_job *j)
 {
     if (!c || !j || !j->field4 || !j->endpoint || !j->steps) return false;
-    if (j->n < 2 || j->max_steps < 1 || !(j->h > 0.0f)) return false;
+    if (j->n < 2 || j->max_steps < 1 || !(j->h > 0.0f) || j->steps_per_visit < 0) return false;
     for (int a = 0; a < 3; ++a)
         if (j->grid[a] < 1 || j->n % j->grid[a] != 0) return false;
     return c->D == j->grid[0] * j->grid[1] * j->grid[2] && c->S == RAFI_SL_ITEM_BYTES;
@@ -207,7 +242,7 @@ int rafi_sl_seed(rafi_ctx *c, const rafi_sl_job *job, const float *seeds, uint64
     return RAFI_OK;
 }
 
-int rafi_sl_advance(rafi_ctx *c, const rafi_sl_job *job, int32_t one_step)
+int rafi_sl_advance(rafi_ctx *c, const rafi_sl_job *job)
 {
     if (!job_ok(c, job)) return RAFI_ERR_ARG;
     rafi_device_view v;
@@ -215,7 +250,7 @@ int rafi_sl_advance(rafi_ctx *c, const rafi_sl_job *job, int32_t one_step)
     const int ph = prof_domain_begin(c);
     if (v.n_in)
         hipLaunchKernelGGL(advance_kernel, dim3((uint32_t)((v.n_in + 255) / 256)), dim3(256), 0, c->stream, v,
-                           *job, one_step, c->wave_slots);
+                           *job, c->wave_slots);
     prof_domain_end(c, ph);
     RAFI_LAUNCH_CHECK();
     return RAFI_OK;
@@ -237,7 +272,7 @@ int rafi_sl_trace(rafi_ctx *c, const rafi_sl_job *job, const float *seeds, uint6
         if (rc != RAFI_OK) break;
         if (total == 0) break;
         if (r >= max_rounds) { rc = RAFI_ERR_MAX_ROUNDS; break; }
-        rc = rafi_sl_advance(c, job, 0);
+        rc = rafi_sl_advance(c, job);
         if (rc != RAFI_OK) break;
     }
     if (rounds) *rounds = r;

@@ -63,7 +63,8 @@ class EAJob(C.Structure):
 
 class SLJob(C.Structure):
     _fields_ = [("field4", C.c_void_p), ("endpoint", C.c_void_p), ("steps", C.c_void_p), ("reason", C.c_void_p),
-                ("n", C.c_int32), ("grid", C.c_int32 * 3), ("h", C.c_float), ("max_steps", C.c_int32)]
+                ("counters", C.c_void_p), ("n", C.c_int32), ("grid", C.c_int32 * 3), ("h", C.c_float),
+                ("max_steps", C.c_int32), ("steps_per_visit", C.c_int32), ("pad", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -91,7 +92,7 @@ _SIGS = {
     "rafi_ea_render": ([_P, C.POINTER(EAJob), C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "rafi_sl_pack": ([_P, C.c_int32, _P, _P], C.c_int),
     "rafi_sl_seed": ([_P, C.POINTER(SLJob), _P, C.c_uint64], C.c_int),
-    "rafi_sl_advance": ([_P, C.POINTER(SLJob), C.c_int32], C.c_int),
+    "rafi_sl_advance": ([_P, C.POINTER(SLJob)], C.c_int),
     "rafi_sl_trace": ([_P, C.POINTER(SLJob), _P, C.c_uint64, C.c_int32, C.POINTER(C.c_int32), _U64P], C.c_int),
 }
 
@@ -302,17 +303,19 @@ def sl_pack(field: torch.Tensor) -> torch.Tensor:
     return f4
 
 
-def sl_job(field4: torch.Tensor, grid, endpoint, steps, reason=None, h=0.25, max_steps=2000) -> SLJob:
-    return SLJob(_dptr(field4), _dptr(endpoint), _dptr(steps), _dptr(reason), field4.shape[0],
-                 (C.c_int32 * 3)(*[int(g) for g in grid]), float(h), int(max_steps))
+def sl_job(field4: torch.Tensor, grid, endpoint, steps, reason=None, h=0.25, max_steps=2000,
+           steps_per_visit=0, counters=None) -> SLJob:
+    """counters: optional int64 device tensor [2] (cross-brick forwards, same-brick forwards)."""
+    return SLJob(_dptr(field4), _dptr(endpoint), _dptr(steps), _dptr(reason), _dptr(counters), field4.shape[0],
+                 (C.c_int32 * 3)(*[int(g) for g in grid]), float(h), int(max_steps), int(steps_per_visit), 0)
 
 
 def sl_seed(ctx: Context, job: SLJob, seeds: torch.Tensor):
     _check(lib().rafi_sl_seed(ctx.handle, C.byref(job), _dptr(seeds), seeds.shape[0]), "rafi_sl_seed")
 
 
-def sl_advance(ctx: Context, job: SLJob, one_step=False):
-    _check(lib().rafi_sl_advance(ctx.handle, C.byref(job), int(one_step)), "rafi_sl_advance")
+def sl_advance(ctx: Context, job: SLJob):
+    _check(lib().rafi_sl_advance(ctx.handle, C.byref(job)), "rafi_sl_advance")
 
 
 def sl_trace_job(ctx: Context, job: SLJob, seeds: torch.Tensor, max_rounds: int = 100000):
@@ -324,7 +327,7 @@ def sl_trace_job(ctx: Context, job: SLJob, seeds: torch.Tensor, max_rounds: int 
 
 
 def sl_trace(field4: torch.Tensor, grid, seeds: torch.Tensor, h=0.25, max_steps=2000, ctx: Context | None = None,
-             max_rounds: int = 100000):
+             max_rounds: int = 100000, steps_per_visit=0):
     dev = field4.device
     N = seeds.shape[0]
     if ctx is None:
@@ -332,6 +335,8 @@ def sl_trace(field4: torch.Tensor, grid, seeds: torch.Tensor, h=0.25, max_steps=
     endpoint = torch.empty((N, 3), dtype=torch.float32, device=dev)
     steps = torch.empty(N, dtype=torch.int32, device=dev)
     reason = torch.empty(N, dtype=torch.int32, device=dev)
-    job = sl_job(field4, grid, endpoint, steps, reason, h, max_steps)
+    counters = torch.zeros(2, dtype=torch.int64, device=dev)
+    job = sl_job(field4, grid, endpoint, steps, reason, h, max_steps, steps_per_visit, counters)
     rounds, fwd = sl_trace_job(ctx, job, seeds, max_rounds)
-    return dict(endpoint=endpoint, steps=steps, reason=reason, rounds=rounds, forwarded=fwd, ctx=ctx)
+    return dict(endpoint=endpoint, steps=steps, reason=reason, rounds=rounds, forwarded=fwd, ctx=ctx,
+                counters=counters)
