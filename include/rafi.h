@@ -224,12 +224,15 @@ typedef struct rafi_ea_job {
     float *tau;                     /* device, optional: final optical depth per ray */
     int32_t *klast;                 /* device, optional: one past the last inside sample */
     int32_t *kfirst;                /* device, optional: first inside sample (0 for misses) */
+    int32_t *visit_log;             /* device, optional [n_rays * visit_stride]: domains visited,
+                                       in order (forward) or as replayed (backward) */
+    int32_t *visit_count;           /* device [n_rays], required with visit_log; zeroed by raygen */
     int32_t n;
     int32_t grid[3];
     int32_t n_views, width, height;
     float dt;                       /* sample spacing along the ray */
     float c;                        /* extinction per unit density per sample (kappa * dt) */
-    int32_t pad;
+    int32_t visit_stride;
 } rafi_ea_job;
 
 /* Item size a context needs for the march (16 bytes: ray id, next sample,
@@ -249,6 +252,25 @@ int rafi_ea_march(rafi_ctx *ctx, const rafi_ea_job *job);
 /* Whole render: raygen, then rafi_round / rafi_ea_march until no item is
  * left. *rounds receives the number of forward steps taken. */
 int rafi_ea_render(rafi_ctx *ctx, const rafi_ea_job *job, int32_t max_rounds, int32_t *rounds);
+
+/*
+ * Adjoint of the march (reverse replay): accumulates dL/dV into grad_volume
+ * (device [n^3] float32, added to; the caller zeroes it) given
+ * grad_image = dL/dI per ray (device [n_rays]). job must be the forward job
+ * after rafi_ea_render with job->tau and job->klast recorded; job->visit_log,
+ * when set, receives the backward visit sequence (the forward one reversed).
+ *
+ * Each ray re-enters the domains in reverse order, starting at its last
+ * inside sample with the forward's final optical depth tau_N and B = 0, and
+ * walks its samples backwards. With T = exp(-tau_k), a = 1 - exp(-sigma_k):
+ *   dI/drho_k = T (a + c exp(-sigma_k) (rho_k - B)),   B <- a rho_k + (1 - a) B,
+ * B being the part of the integral behind sample k; dI/drho_k * dL/dI is
+ * scattered to the 8 voxels of sample k with their trilinear weights
+ * (float32 atomic adds, so the summation order is not fixed). The item is 16
+ * bytes (ray id, sample, tau, B); the context is the forward's.
+ */
+int rafi_ea_backward(rafi_ctx *ctx, const rafi_ea_job *job, const float *grad_image, float *grad_volume,
+                     int32_t max_rounds, int32_t *rounds);
 
 /* ------------------------------------------------------------------------
  * RK4 streamlines over bricked domains (particle tracing, Sec. 5.4).

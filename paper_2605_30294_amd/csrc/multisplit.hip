@@ -66,6 +66,15 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *lds, uint32_t *
     return res;
 }
 
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+// 16-byte streaming load (read once; not kept in the caches).
+__device__ inline uint4 load_nt4(const void *p)
+{
+    const u32x4_t v = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 __device__ inline uint32_t bucket_of(int32_t d, int32_t D)
 {
     if (d >= 0 && d < D) return (uint32_t)d;
@@ -83,16 +92,32 @@ hist_kernel(const int32_t *__restrict__ dest, uint64_t n, int32_t D, uint32_t T,
     __syncthreads();
     const uint64_t start = (uint64_t)blockIdx.x * T;
     const uint64_t end = min(start + T, n);
-    // T is a multiple of 1024 and dest is 16-byte aligned: whole int4 groups.
+    // T is a multiple of 1024 and dest is 16-byte aligned: whole int4 groups,
+    // loaded kU at a time before the LDS atomics so the loads overlap.
+    constexpr int kU = 8;
     const uint64_t vend = start + ((end - start) & ~(uint64_t)3);
-    for (uint64_t i = start + 4ull * threadIdx.x; i < vend; i += 4ull * blockDim.x) {
+    const uint64_t stride = 4ull * blockDim.x;
+    uint64_t i = start + 4ull * threadIdx.x;
+    for (; i + (kU - 1) * stride < vend; i += kU * stride) {
+        uint4 d4[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) d4[u] = load_nt4(dest + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            atomicAdd(&h[bucket_of((int32_t)d4[u].x, D)], 1u);
+            atomicAdd(&h[bucket_of((int32_t)d4[u].y, D)], 1u);
+            atomicAdd(&h[bucket_of((int32_t)d4[u].z, D)], 1u);
+            atomicAdd(&h[bucket_of((int32_t)d4[u].w, D)], 1u);
+        }
+    }
+    for (; i < vend; i += stride) {
         int4 d4 = *reinterpret_cast<const int4 *>(dest + i);
         atomicAdd(&h[bucket_of(d4.x, D)], 1u);
         atomicAdd(&h[bucket_of(d4.y, D)], 1u);
         atomicAdd(&h[bucket_of(d4.z, D)], 1u);
         atomicAdd(&h[bucket_of(d4.w, D)], 1u);
     }
-    for (uint64_t i = vend + threadIdx.x; i < end; i += blockDim.x) atomicAdd(&h[bucket_of(dest[i], D)], 1u);
+    for (uint64_t j = vend + threadIdx.x; j < end; j += blockDim.x) atomicAdd(&h[bucket_of(dest[j], D)], 1u);
     __syncthreads();
     for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x)
         table[(uint64_t)e * n_tiles + blockIdx.x] = h[e];
@@ -355,35 +380,41 @@ scatter_staged_kernel(const uint32_t *__restrict__ items, const int32_t *__restr
 
     for (int32_t e = tid; e < D; e += 256) run[e] = table[(uint64_t)e * n_tiles + blockIdx.x];
 
-    for (uint64_t cbase = tstart; cbase < tend; cbase += CH) {
-        // zero the per-wave counters
-        for (int k = tid; k < (W * D + 1) / 2; k += 256) cntw[k] = 0;
-        __syncthreads();
-
-        // rank: load destinations and items for this wave's quarter
-        uint32_t item[R][NW];
-        int32_t dd[R];
-        uint16_t rank[R];
+    uint32_t item[R][NW];
+    int32_t dd[R];
+    uint16_t rank[R];
+    // Load one chunk's destinations and items for this wave's quarter into
+    // registers (streamed: read once, not kept in cache).
+    auto load_chunk = [&](uint64_t cbase) {
         const uint64_t qbase = cbase + (uint64_t)w * SEG;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint64_t i = qbase + 64 * r + lane;
-            dd[r] = i < tend ? dest[i] : RAFI_DONE;
+            dd[r] = i < tend ? __builtin_nontemporal_load(dest + i) : RAFI_DONE;
             if (i < tend) {
                 const uint32_t *src = items + i * NW;
                 if constexpr (NW % 4 == 0) {
 #pragma unroll
                     for (int k = 0; k < NW / 4; ++k) {
-                        const uint4 q = reinterpret_cast<const uint4 *>(src)[k];
+                        const uint4 q = load_nt4(src + 4 * k);
                         item[r][4 * k] = q.x; item[r][4 * k + 1] = q.y;
                         item[r][4 * k + 2] = q.z; item[r][4 * k + 3] = q.w;
                     }
                 } else {
 #pragma unroll
-                    for (int k = 0; k < NW; ++k) item[r][k] = src[k];
+                    for (int k = 0; k < NW; ++k) item[r][k] = __builtin_nontemporal_load(src + k);
                 }
             }
         }
+    };
+    if (tstart < tend) load_chunk(tstart);
+
+    for (uint64_t cbase = tstart; cbase < tend; cbase += CH) {
+        // zero the per-wave counters
+        for (int k = tid; k < (W * D + 1) / 2; k += 256) cntw[k] = 0;
+        __syncthreads();
+
+        // rank
         uint16_t *mycnt = cnt + w * D;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -451,6 +482,10 @@ scatter_staged_kernel(const uint32_t *__restrict__ items, const int32_t *__restr
             }
         }
         __syncthreads();
+
+        // the registers are free again: start loading the next chunk so its
+        // latency overlaps the write phase
+        if (cbase + CH < tend) load_chunk(cbase + CH);
 
         // per destination: global slot of chunk-sorted slot j is dl[e] + j
         uint32_t *dl = cntw;

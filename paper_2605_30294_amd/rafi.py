@@ -56,9 +56,10 @@ class Profile(C.Structure):
 
 class EAJob(C.Structure):
     _fields_ = [("volume", C.c_void_p), ("views", C.c_void_p), ("image", C.c_void_p), ("tau", C.c_void_p),
-                ("klast", C.c_void_p), ("kfirst", C.c_void_p), ("n", C.c_int32), ("grid", C.c_int32 * 3), ("n_views", C.c_int32),
-                ("width", C.c_int32), ("height", C.c_int32), ("dt", C.c_float), ("c", C.c_float),
-                ("pad", C.c_int32)]
+                ("klast", C.c_void_p), ("kfirst", C.c_void_p), ("visit_log", C.c_void_p),
+                ("visit_count", C.c_void_p), ("n", C.c_int32), ("grid", C.c_int32 * 3),
+                ("n_views", C.c_int32), ("width", C.c_int32), ("height", C.c_int32), ("dt", C.c_float),
+                ("c", C.c_float), ("visit_stride", C.c_int32)]
 
 
 class SLJob(C.Structure):
@@ -90,6 +91,7 @@ _SIGS = {
     "rafi_ea_raygen": ([_P, C.POINTER(EAJob)], C.c_int),
     "rafi_ea_march": ([_P, C.POINTER(EAJob)], C.c_int),
     "rafi_ea_render": ([_P, C.POINTER(EAJob), C.c_int32, C.POINTER(C.c_int32)], C.c_int),
+    "rafi_ea_backward": ([_P, C.POINTER(EAJob), _P, _P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "rafi_sl_pack": ([_P, C.c_int32, _P, _P], C.c_int),
     "rafi_sl_seed": ([_P, C.POINTER(SLJob), _P, C.c_uint64], C.c_int),
     "rafi_sl_advance": ([_P, C.POINTER(SLJob)], C.c_int),
@@ -253,10 +255,13 @@ def multisplit(items: torch.Tensor, dest: torch.Tensor, n_domains: int, out=None
 # -------------------------------------------------------------- EA march ---
 
 def ea_job(volume: torch.Tensor, grid, views_dev: torch.Tensor, n_views: int, width: int, height: int,
-           image: torch.Tensor, tau=None, klast=None, dt=0.5, c=0.025, kfirst=None) -> EAJob:
+           image: torch.Tensor, tau=None, klast=None, dt=0.5, c=0.025, kfirst=None, visit_log=None,
+           visit_count=None) -> EAJob:
     n = volume.shape[0]
-    return EAJob(_dptr(volume), _dptr(views_dev), _dptr(image), _dptr(tau), _dptr(klast), _dptr(kfirst), n,
-                 (C.c_int32 * 3)(*[int(g) for g in grid]), n_views, width, height, float(dt), float(c), 0)
+    stride = 0 if visit_log is None else visit_log.shape[1]
+    return EAJob(_dptr(volume), _dptr(views_dev), _dptr(image), _dptr(tau), _dptr(klast), _dptr(kfirst),
+                 _dptr(visit_log), _dptr(visit_count), n, (C.c_int32 * 3)(*[int(g) for g in grid]), n_views,
+                 width, height, float(dt), float(c), stride)
 
 
 def ea_raygen(ctx: Context, job: EAJob):
@@ -270,6 +275,15 @@ def ea_march(ctx: Context, job: EAJob):
 def ea_render_job(ctx: Context, job: EAJob, max_rounds: int = 1024) -> int:
     r = C.c_int32(0)
     _check(lib().rafi_ea_render(ctx.handle, C.byref(job), max_rounds, C.byref(r)), "rafi_ea_render")
+    return r.value
+
+
+def ea_backward_job(ctx: Context, job: EAJob, grad_image: torch.Tensor, grad_volume: torch.Tensor,
+                    max_rounds: int = 1024) -> int:
+    """Accumulate dL/dV into grad_volume for dL/dI = grad_image (reverse replay)."""
+    r = C.c_int32(0)
+    _check(lib().rafi_ea_backward(ctx.handle, C.byref(job), _dptr(grad_image), _dptr(grad_volume), max_rounds,
+                                  C.byref(r)), "rafi_ea_backward")
     return r.value
 
 
@@ -340,3 +354,35 @@ def sl_trace(field4: torch.Tensor, grid, seeds: torch.Tensor, h=0.25, max_steps=
     rounds, fwd = sl_trace_job(ctx, job, seeds, max_rounds)
     return dict(endpoint=endpoint, steps=steps, reason=reason, rounds=rounds, forwarded=fwd, ctx=ctx,
                 counters=counters)
+
+
+class EARender(torch.autograd.Function):
+    """Emission-absorption render as a differentiable op of the volume.
+
+    forward: the bricked march-and-forward render (tau and the last sample
+    index are recorded per ray); backward: the reverse-replay adjoint kernel.
+    Both run in the library; this class only moves tensors."""
+
+    @staticmethod
+    def forward(fctx, volume, grid, views, dt, c, rafi_ctx):
+        out = ea_render(volume.contiguous(), grid, views, dt=dt, c=c, ctx=rafi_ctx, want_tau=True)
+        fctx.keep = (out["ctx"], out["job"], out["views_dev"], out["tau"], out["klast"], out["kfirst"],
+                     out["image"])
+        fctx.save_for_backward(volume)
+        return out["image"]
+
+    @staticmethod
+    def backward(fctx, grad_image):
+        (volume,) = fctx.saved_tensors
+        rctx, job, _views, _tau, _klast, _kfirst, _image = fctx.keep
+        grad = torch.zeros_like(volume)
+        ea_backward_job(rctx, job, grad_image.contiguous().to(torch.float32), grad)
+        return grad, None, None, None, None, None
+
+
+def ea_render_differentiable(volume: torch.Tensor, grid, views: np.ndarray, dt=0.5, c=0.025,
+                             rafi_ctx: Context | None = None) -> torch.Tensor:
+    if rafi_ctx is None:
+        n_rays = len(views) * int(views[0]["width"]) * int(views[0]["height"])
+        rafi_ctx = Context(int(np.prod(grid)), EA_ITEM_BYTES, max(n_rays, 1))
+    return EARender.apply(volume, tuple(grid), views, float(dt), float(c), rafi_ctx)
