@@ -1,0 +1,270 @@
+// Device building blocks of the stable multi-split, shared by the plain
+// forward step (multisplit.hip) and the segmented one of the batched form
+// (batched.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "rafi.h"
+
+namespace rafi {
+namespace dev {
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive block scan; lds needs NT/64 + 1 words. Returns the exclusive
+// prefix of v and the block total in *total.
+template <int NT>
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *lds, uint32_t *total)
+{
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    uint32_t incl = wave_incl_scan(v);
+    if (lane == 63) lds[wave] = incl;
+    __syncthreads();
+    if (tid < 64) {
+        uint32_t w = tid < NW ? lds[tid] : 0u;
+        uint32_t wi = wave_incl_scan(w);
+        if (tid < NW) lds[tid] = wi - w;
+        if (tid == NW - 1) lds[NW] = wi;
+    }
+    __syncthreads();
+    uint32_t res = lds[wave] + incl - v;
+    *total = lds[NW];
+    __syncthreads();
+    return res;
+}
+
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+// 16-byte streaming load (read once; not kept in the caches).
+__device__ inline uint4 load_nt4(const void *p)
+{
+    const u32x4_t v = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+__device__ inline uint32_t bucket_of(int32_t d, int32_t D)
+{
+    if (d >= 0 && d < D) return (uint32_t)d;
+    return d == RAFI_DONE ? (uint32_t)D : (uint32_t)D + 1u;
+}
+
+// Lanes of this wave whose key equals mine (only lanes with ok set take part).
+__device__ inline uint64_t match_peers(uint32_t key, bool ok, int nbits)
+{
+    uint64_t peers = __ballot(ok);
+    for (int b = 0; b < nbits; ++b) {
+        const bool bit = (key >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    return peers;
+}
+
+// ------------------------------------------------ staged stable scatter ---
+// A tile of slots [tstart, tend) is processed in chunks of CH = 4 waves x R
+// rounds x 64 slots. Per chunk:
+//   rank   each wave owns a contiguous quarter; round r, lane l takes slot
+//          quarter_base + 64 r + l, so slot order = (round, lane) order. A
+//          ballot match gives the lane's rank among same-destination lanes,
+//          and a per-wave LDS counter carries it across rounds.
+//   scan   chunk-local offsets over destinations (block scan), turned into
+//          per-wave bases.
+//   place  items move from registers into LDS at their chunk-sorted slot.
+//   write  consecutive threads write consecutive 16-byte pieces of the
+//          sorted chunk, so every destination run goes out as whole lines.
+// The next chunk's loads are issued before the write phase.
+constexpr int kStagedMaxD = 1024;
+constexpr size_t kStagedLds = 80 * 1024;  // two workgroups per CU
+
+template <int NW>
+constexpr int staged_rounds()
+{
+    return NW <= 3 ? 16 : (56 / NW > 0 ? 56 / NW : 0);
+}
+
+template <int NW>
+inline size_t staged_lds_bytes(int32_t D)
+{
+    constexpr int R = staged_rounds<NW>();
+    constexpr int CH = 4 * 64 * R;
+    return sizeof(uint32_t) * ((size_t)CH * NW + D + (4 * (size_t)D + 1) / 2) + sizeof(uint16_t) * CH;
+}
+
+// Destination of slot i is dest[i] - dbase, valid when in [0, D). run_base(e)
+// gives the output slot of the tile's first item bound for e. Output slots
+// >= out_cap are never written (they cannot occur for a consistent table).
+template <int NW, int R, typename RunBase>
+__device__ inline void staged_scatter_tile(const uint32_t *__restrict__ items, const int32_t *__restrict__ dest,
+                                           uint64_t tstart, uint64_t tend, int32_t D, int32_t dbase, int nbits,
+                                           RunBase run_base, uint32_t *__restrict__ out, uint64_t out_cap,
+                                           uint32_t *lds)
+{
+    constexpr int W = 4, SEG = 64 * R, CH = W * SEG;
+    constexpr int PIECE = (NW % 4 == 0) ? 4 : ((NW % 2 == 0) ? 2 : 1);  // words per store
+    constexpr int PPI = NW / PIECE;                                    // pieces per item
+    constexpr int EPT = (kStagedMaxD + 255) / 256;                     // max destinations per thread
+    uint32_t *stage = lds;                                             // [CH * NW]
+    uint32_t *run = stage + CH * NW;                                   // [D] next output slot per dest
+    uint32_t *cntw = run + D;                                          // [W * D / 2] (u16) / dl [D] (u32)
+    uint16_t *cnt = reinterpret_cast<uint16_t *>(cntw);
+    uint16_t *bkt = reinterpret_cast<uint16_t *>(cntw + (W * D + 1) / 2);  // [CH]
+    __shared__ uint32_t scan_lds[256 / 64 + 1];
+
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const int per = (D + 255) / 256;  // destinations per thread in the scans
+    const int e0 = tid * per;
+
+    for (int32_t e = tid; e < D; e += 256) run[e] = run_base(e);
+
+    uint32_t item[R][NW];
+    int32_t dd[R];
+    uint16_t rank[R];
+    auto load_chunk = [&](uint64_t cbase) {
+        const uint64_t qbase = cbase + (uint64_t)w * SEG;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t i = qbase + 64 * r + lane;
+            dd[r] = i < tend ? __builtin_nontemporal_load(dest + i) - dbase : -1;
+            if (i < tend) {
+                const uint32_t *src = items + i * NW;
+                if constexpr (NW % 4 == 0) {
+#pragma unroll
+                    for (int k = 0; k < NW / 4; ++k) {
+                        const uint4 q = load_nt4(src + 4 * k);
+                        item[r][4 * k] = q.x; item[r][4 * k + 1] = q.y;
+                        item[r][4 * k + 2] = q.z; item[r][4 * k + 3] = q.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < NW; ++k) item[r][k] = __builtin_nontemporal_load(src + k);
+                }
+            }
+        }
+    };
+    if (tstart < tend) load_chunk(tstart);
+
+    for (uint64_t cbase = tstart; cbase < tend; cbase += CH) {
+        for (int k = tid; k < (W * D + 1) / 2; k += 256) cntw[k] = 0;
+        __syncthreads();
+
+        // rank
+        uint16_t *mycnt = cnt + w * D;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int32_t d = dd[r];
+            const bool ok = d >= 0 && d < D;
+            const uint64_t peers = match_peers((uint32_t)d, ok, nbits);
+            uint16_t before = 0;
+            if (ok) before = mycnt[d];
+            __builtin_amdgcn_wave_barrier();
+            rank[r] = (uint16_t)(before + __popcll(peers & lt));
+            if (ok && (peers & lt) == 0ull) mycnt[d] = (uint16_t)(before + __popcll(peers));
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+
+        // scan: chunk totals per destination -> chunk offsets -> per-wave bases
+        uint32_t tot_e[EPT], excl_e[EPT];
+        uint32_t local = 0;
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int32_t e = e0 + k;
+            uint32_t t = 0;
+            if (k < per && e < D)
+#pragma unroll
+                for (int ww = 0; ww < W; ++ww) t += cnt[ww * D + e];
+            tot_e[k] = t;
+            local += t;
+        }
+        uint32_t chunk_total;
+        uint32_t base = block_excl_scan<256>(local, scan_lds, &chunk_total);
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int32_t e = e0 + k;
+            excl_e[k] = base;
+            if (k < per && e < D) {
+                uint32_t b = base;
+#pragma unroll
+                for (int ww = 0; ww < W; ++ww) {
+                    const uint32_t c = cnt[ww * D + e];
+                    cnt[ww * D + e] = (uint16_t)b;
+                    b += c;
+                }
+            }
+            base += tot_e[k];
+        }
+        __syncthreads();
+
+        // place: items go to their chunk-sorted slot in LDS
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int32_t d = dd[r];
+            if (d >= 0 && d < D) {
+                const uint32_t pos = (uint32_t)cnt[w * D + d] + rank[r];
+                uint32_t *dst = stage + pos * NW;
+                if constexpr (NW % 4 == 0) {
+#pragma unroll
+                    for (int k = 0; k < NW / 4; ++k)
+                        reinterpret_cast<uint4 *>(dst)[k] =
+                            make_uint4(item[r][4 * k], item[r][4 * k + 1], item[r][4 * k + 2], item[r][4 * k + 3]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < NW; ++k) dst[k] = item[r][k];
+                }
+                bkt[pos] = (uint16_t)d;
+            }
+        }
+        __syncthreads();
+
+        // the registers are free again: start loading the next chunk so its
+        // latency overlaps the write phase
+        if (cbase + CH < tend) load_chunk(cbase + CH);
+
+        // per destination: output slot of chunk-sorted slot j is dl[e] + j
+        uint32_t *dl = cntw;
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int32_t e = e0 + k;
+            if (k < per && e < D) {
+                dl[e] = run[e] - excl_e[k];
+                run[e] += tot_e[k];
+            }
+        }
+        __syncthreads();
+
+        // write: whole destination runs, consecutive lanes on consecutive pieces
+        const uint32_t n_pieces = chunk_total * PPI;
+        for (uint32_t q = tid; q < n_pieces; q += 256) {
+            const uint32_t j = q / PPI, part = q - j * PPI;
+            const uint32_t g = dl[bkt[j]] + j;
+            if (g < out_cap) {
+                const uint32_t *src = stage + j * NW + part * PIECE;
+                uint32_t *dst = out + (uint64_t)g * NW + part * PIECE;
+                if constexpr (PIECE == 4)
+                    *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
+                else if constexpr (PIECE == 2)
+                    *reinterpret_cast<uint2 *>(dst) = *reinterpret_cast<const uint2 *>(src);
+                else
+                    *dst = *src;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace dev
+}  // namespace rafi
