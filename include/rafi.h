@@ -273,6 +273,52 @@ int rafi_ea_backward(rafi_ctx *ctx, const rafi_ea_job *job, const float *grad_im
                      int32_t max_rounds, int32_t *rounds);
 
 /* ------------------------------------------------------------------------
+ * Batched form: many independent scenes advance together, one launch per
+ * kernel per round for all of them (an extension; not in the paper).
+ *
+ * Scene s has its own volume (n_s^3 float32 at volume_offset in one device
+ * buffer), domain grid and view; its domains get global ids
+ * dom_base_s + local and its rays global ids ray_base_s + local (both filled
+ * in by rafi_batch_create, in scene order). Items never change scene, so the
+ * forward step is a segmented split: tiles never straddle a scene, each has
+ * at most the scene's domain count of destinations, and the result equals the
+ * stable split over all global domains. Every size the kernels need lives on
+ * the device, so a round is captured once in a hipGraph and replayed.
+ * ------------------------------------------------------------------------ */
+typedef struct rafi_ea_scene {
+    uint64_t volume_offset;   /* first float of the scene's volume in the volume buffer */
+    rafi_ortho_view view;     /* the scene's view: width * height rays */
+    int32_t n;
+    int32_t grid[3];
+    uint32_t ray_base;        /* set by rafi_batch_create */
+    int32_t dom_base;         /* set by rafi_batch_create */
+} rafi_ea_scene; /* 96 bytes */
+
+typedef struct rafi_batch rafi_batch;
+
+typedef struct rafi_batch_tuning {
+    uint32_t split_tile;      /* slots per split tile, multiple of 256, >= 1024 (default 4096) */
+    uint32_t march_block;     /* threads per march workgroup: 64, 128, 256 or 512 (default 256) */
+    uint32_t march_grid;      /* persistent march workgroups (default 2048) */
+    int32_t use_graph;        /* 1: rounds replayed from a captured hipGraph (default 1) */
+    int32_t rounds_per_sync;  /* rounds launched between host checks of the total (default 4) */
+} rafi_batch_tuning;
+
+/* Create a batch over n_scenes scenes (host array; copied, bases filled in
+ * the copy and in `scenes` itself). n_s >= 2, n_s % grid_a == 0, at most 64
+ * domains per scene, total rays < 2^31. dt, c as for rafi_ea_job. */
+int rafi_batch_create(rafi_ea_scene *scenes, int32_t n_scenes, float dt, float c, rafi_batch **out);
+void rafi_batch_destroy(rafi_batch *b);
+int rafi_batch_set_stream(rafi_batch *b, void *hip_stream);
+int rafi_batch_set_tuning(rafi_batch *b, const rafi_batch_tuning *t);
+/* Total rays and global domains of the batch. */
+int rafi_batch_info(const rafi_batch *b, uint64_t *n_rays, int32_t *n_domains);
+/* Render every scene: volumes device (the buffer the scenes' offsets index),
+ * image device [n_rays] (ray r of scene s at ray_base_s + r). *rounds gets the
+ * number of forward steps until no item was left. */
+int rafi_batch_render(rafi_batch *b, const float *volumes, float *image, int32_t max_rounds, int32_t *rounds);
+
+/* ------------------------------------------------------------------------
  * RK4 streamlines over bricked domains (particle tracing, Sec. 5.4).
  *
  * Field: n^3 float32 velocity triples at voxel centres, x fastest, in voxels

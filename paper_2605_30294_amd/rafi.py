@@ -68,6 +68,23 @@ class SLJob(C.Structure):
                 ("max_steps", C.c_int32), ("steps_per_visit", C.c_int32), ("pad", C.c_int32)]
 
 
+class ViewRec(C.Structure):
+    _fields_ = [("org0", C.c_float * 3), ("du", C.c_float * 3), ("dv", C.c_float * 3), ("dir", C.c_float * 3),
+                ("width", C.c_int32), ("height", C.c_int32), ("n_samples", C.c_int32), ("pad", C.c_int32)]
+
+
+class SceneRec(C.Structure):
+    _fields_ = [("volume_offset", C.c_uint64), ("view", ViewRec), ("n", C.c_int32), ("grid", C.c_int32 * 3),
+                ("ray_base", C.c_uint32), ("dom_base", C.c_int32)]
+
+
+class BatchTuning(C.Structure):
+    _fields_ = [("split_tile", C.c_uint32), ("march_block", C.c_uint32), ("march_grid", C.c_uint32),
+                ("use_graph", C.c_int32), ("rounds_per_sync", C.c_int32)]
+
+
+assert C.sizeof(ViewRec) == 64 and C.sizeof(SceneRec) == 96
+
 _P = C.c_void_p
 _U64P = C.POINTER(C.c_uint64)
 _SIGS = {
@@ -92,6 +109,12 @@ _SIGS = {
     "rafi_ea_march": ([_P, C.POINTER(EAJob)], C.c_int),
     "rafi_ea_render": ([_P, C.POINTER(EAJob), C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "rafi_ea_backward": ([_P, C.POINTER(EAJob), _P, _P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
+    "rafi_batch_create": ([C.POINTER(SceneRec), C.c_int32, C.c_float, C.c_float, C.POINTER(C.c_void_p)], C.c_int),
+    "rafi_batch_destroy": ([_P], None),
+    "rafi_batch_set_stream": ([_P, _P], C.c_int),
+    "rafi_batch_set_tuning": ([_P, C.POINTER(BatchTuning)], C.c_int),
+    "rafi_batch_info": ([_P, _U64P, C.POINTER(C.c_int32)], C.c_int),
+    "rafi_batch_render": ([_P, _P, _P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "rafi_sl_pack": ([_P, C.c_int32, _P, _P], C.c_int),
     "rafi_sl_seed": ([_P, C.POINTER(SLJob), _P, C.c_uint64], C.c_int),
     "rafi_sl_advance": ([_P, C.POINTER(SLJob)], C.c_int),
@@ -386,3 +409,70 @@ def ea_render_differentiable(volume: torch.Tensor, grid, views: np.ndarray, dt=0
         n_rays = len(views) * int(views[0]["width"]) * int(views[0]["height"])
         rafi_ctx = Context(int(np.prod(grid)), EA_ITEM_BYTES, max(n_rays, 1))
     return EARender.apply(volume, tuple(grid), views, float(dt), float(c), rafi_ctx)
+
+
+# ---------------------------------------------------------------- batched ---
+
+def view_rec(v) -> ViewRec:
+    r = ViewRec()
+    for k in ("org0", "du", "dv", "dir"):
+        getattr(r, k)[:] = [float(x) for x in np.asarray(v[k], dtype=np.float32)]
+    r.width, r.height, r.n_samples = int(v["width"]), int(v["height"]), int(v["n_samples"])
+    return r
+
+
+class Batch:
+    """Many independent scenes rendered together (rafi_batch_*).
+
+    scenes: list of (n, grid, view record, volume_offset in floats)."""
+
+    def __init__(self, scenes, dt=0.5, c=0.025, stream=None):
+        arr = (SceneRec * len(scenes))()
+        for i, (n, grid, view, off) in enumerate(scenes):
+            arr[i].volume_offset = int(off)
+            arr[i].view = view_rec(view)
+            arr[i].n = int(n)
+            arr[i].grid[:] = [int(g) for g in grid]
+        h = C.c_void_p()
+        _check(lib().rafi_batch_create(arr, len(scenes), float(dt), float(c), C.byref(h)), "rafi_batch_create")
+        self._h = h
+        self.scenes = arr
+        nr, nd = C.c_uint64(0), C.c_int32(0)
+        _check(lib().rafi_batch_info(self._h, C.byref(nr), C.byref(nd)), "rafi_batch_info")
+        self.n_rays, self.n_domains = nr.value, nd.value
+        _check(lib().rafi_batch_set_stream(self._h, _stream(stream)), "rafi_batch_set_stream")
+
+    def close(self):
+        if self._h:
+            lib().rafi_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tuning(self, split_tile=4096, march_block=256, march_grid=2048, use_graph=True, rounds_per_sync=4):
+        t = BatchTuning(split_tile, march_block, march_grid, int(use_graph), rounds_per_sync)
+        _check(lib().rafi_batch_set_tuning(self._h, C.byref(t)), "rafi_batch_set_tuning")
+
+    def render(self, volumes: torch.Tensor, image: torch.Tensor, max_rounds: int = 1024) -> int:
+        r = C.c_int32(0)
+        _check(lib().rafi_batch_render(self._h, _dptr(volumes), _dptr(image), max_rounds, C.byref(r)),
+               "rafi_batch_render")
+        return r.value
+
+
+def build_batch_inputs(specs, device, views=None):
+    """Concatenated device volume buffer and Batch scene tuples for
+    workloads.SceneSpec specs (blob volumes, +z views unless given)."""
+    offs, vols, scenes = [], [], []
+    off = 0
+    for i, sp in enumerate(specs):
+        v = W.blob_volume(sp.n, sp.volume_seed, device=device).reshape(-1)
+        vols.append(v)
+        view = W.plusz_view(sp.n, sp.rays_side, sp.rays_side)[0] if views is None else views[i]
+        scenes.append((sp.n, sp.grid, view, off))
+        off += v.numel()
+    return torch.cat(vols), scenes
