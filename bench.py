@@ -202,6 +202,96 @@ def ea_forward(dev, reps):
     return out
 
 
+def ea_adjoint(dev, reps):
+    """128^3 / 64 bricks / 64 views x 256^2: forward render, then the
+    reverse-replay backward of the L2 image loss against a second volume."""
+    import numpy as np
+    import torch
+
+    from paper_2605_30294_amd import rafi
+    from paper_2605_30294_amd import workloads as W
+
+    n, grid = 128, (4, 4, 4)
+    c = float(np.float32(0.025))
+    vol = W.blob_volume(n, W.SEED_ADJ_VOLUME, device=dev)
+    tgt = W.blob_volume(n, W.SEED_ADJ_TARGET, device=dev)
+    views = W.random_views(64, n, 256, 256)
+    target = rafi.ea_render(tgt, grid, views, c=c)["image"]
+    r = rafi.ea_render(vol, grid, views, c=c, want_tau=True)
+    ctx, job = r["ctx"], r["job"]
+    grad_image = 2.0 * (r["image"] - target)
+    grad = torch.zeros_like(vol)
+    rafi.ea_backward_job(ctx, job, grad_image, grad)      # warm-up
+    torch.cuda.synchronize()
+    samples = int((r["klast"] - r["kfirst"]).clamp(min=0).sum().item())
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    for _ in range(reps):
+        rafi.ea_render_job(ctx, job)
+    ev[1].record()
+    ev[2].record()
+    for _ in range(reps):
+        grad.zero_()
+        rafi.ea_backward_job(ctx, job, grad_image, grad)
+    ev[3].record()
+    torch.cuda.synchronize()
+    fwd = ev[0].elapsed_time(ev[1]) / reps
+    bwd = ev[2].elapsed_time(ev[3]) / reps
+    ctx.close()
+    out = {"workload": "128^3, 4x4x4 bricks, 64 views x 256^2, L2 loss vs second volume",
+           "forward_ms": round(fwd, 4), "backward_ms": round(bwd, 4), "backward_over_forward": round(bwd / fwd, 3),
+           "samples": samples, "forward_samples_per_s": samples / (fwd * 1e-3),
+           "backward_samples_per_s": samples / (bwd * 1e-3)}
+    log(f"adjoint: forward {fwd:.3f} ms, backward {bwd:.3f} ms ({bwd / fwd:.2f}x)")
+    return out
+
+
+def batched(dev, reps):
+    """256 uneven scenes: one batched render (autotuned, graph-replayed rounds)
+    against rendering the scenes one at a time with the plain path."""
+    import numpy as np
+    import torch
+
+    from paper_2605_30294_amd import autotune, rafi
+    from paper_2605_30294_amd import workloads as W
+
+    c = float(np.float32(0.025))
+    specs = W.draw_scenes(256)
+    vols, scenes = rafi.build_batch_inputs(specs, dev)
+    b = rafi.Batch(scenes, c=c)
+    image = torch.empty(b.n_rays, dtype=torch.float32, device=dev)
+    best, _, _ = autotune.tune_batch(b, vols, image, reps=1)
+    ms_b = autotune.time_render(b, vols, image, reps=reps)
+    # plain, one scene at a time (contexts and jobs prepared outside the timing)
+    plain = []
+    samples = 0
+    for n, grid, view, off in scenes:
+        v = vols[off:off + n ** 3].reshape(n, n, n)
+        r = rafi.ea_render(v, grid, np.array([view]), c=c, want_tau=True)
+        samples += int((r["klast"] - r["kfirst"]).clamp(min=0).sum().item())
+        plain.append(r)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        for r in plain:
+            rafi.ea_render_job(r["ctx"], r["job"])
+    t1.record()
+    torch.cuda.synchronize()
+    ms_p = t0.elapsed_time(t1) / reps
+    same = bool(torch.equal(image, torch.cat([r["image"] for r in plain])))
+    for r in plain:
+        r["ctx"].close()
+    b.close()
+    out = {"workload": "256 scenes: edges 32-256 log-uniform, 1-64 domains, 1K-1M rays (+z)",
+           "rays": b.n_rays, "samples": samples, "batched_ms": round(ms_b, 3), "sequential_plain_ms": round(ms_p, 3),
+           "speedup": round(ms_p / ms_b, 3), "batched_samples_per_s": samples / (ms_b * 1e-3),
+           "tuning": best, "bit_identical_to_plain": same}
+    log(f"batched: {ms_b:.2f} ms vs sequential plain {ms_p:.2f} ms ({ms_p / ms_b:.2f}x), identical={same}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +320,8 @@ def main():
     if not args.no_extras:
         extras["multisplit_64M_x32B_1024dest"] = split_microbench(dev, reps=20)
         extras["ea_forward"] = ea_forward(dev, reps=5)
+        extras["adjoint_vs_forward"] = ea_adjoint(dev, reps=3)
+        extras["batched_vs_plain"] = batched(dev, reps=2)
     cpu = None if args.no_cpu else cpu_baseline(seeds_np, args.cpu_seeds)
 
     value = sl["forwarded"] / (sl["ms"] * 1e-3)
