@@ -292,6 +292,26 @@ def batched(dev, reps):
     return out
 
 
+def plain_copy(dev, reps):
+    """A device-to-device copy of exactly 2 GiB per launch: the reference for
+    scaling the HBM traffic counters."""
+    import torch
+
+    nbytes = 2 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    dst.copy_(src)
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "ms": ms, "GBps": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -300,6 +320,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seeds", type=int, default=262144)
+    ap.add_argument("--only", default=None,
+                    choices=["streamlines", "split", "ea", "adjoint", "batched", "copy"],
+                    help="run one leg alone (for profilers) and print its result")
     ap.add_argument("--steps-per-visit", type=int, default=64,
                     help="RK4 steps a particle takes per domain visit before it is forwarded to its own "
                          "brick (0 = until it leaves); results do not depend on it")
@@ -314,6 +337,22 @@ def main():
     import torch
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+
+    if args.only is not None:
+        if args.only == "streamlines":
+            res = streamline_job(args, dev)[0]
+        elif args.only == "split":
+            res = split_microbench(dev, reps=args.steps)
+        elif args.only == "ea":
+            res = ea_forward(dev, reps=args.steps)
+        elif args.only == "adjoint":
+            res = ea_adjoint(dev, reps=args.steps)
+        elif args.only == "batched":
+            res = batched(dev, reps=args.steps)
+        else:
+            res = plain_copy(dev, reps=args.steps)
+        print(json.dumps({"only": args.only, "result": res}, default=str), flush=True)
+        return
 
     sl, seeds_np = streamline_job(args, dev)
     extras = {}
