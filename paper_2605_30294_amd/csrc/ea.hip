@@ -4,6 +4,8 @@
 // each forwarded ray carries its partial integration state), and the adjoint
 // that replays every ray backwards through the same bricks. The per-sample
 // arithmetic is in ea_device.h.
+#include <algorithm>
+
 #include "ea_device.h"
 #include "internal.h"
 #include "rafi_device.h"
@@ -179,6 +181,120 @@ bwd_march_kernel(rafi_device_view view, rafi_ea_job job, const float *__restrict
     else rafi_done(view, i);
 }
 
+// LDS-privatised backward: one workgroup per domain-pure tile of the input
+// queue. The workgroup accumulates dL/dV for the voxels its brick's samples
+// touch -- the brick plus a one-voxel rim, (b+2)^3 floats -- in LDS, and each
+// lane first sums its ray's contributions in registers while consecutive
+// samples stay in the same trilinear cell. At the end the non-zero LDS
+// entries are added to the global gradient.
+constexpr int kBwdThreads = 512;
+
+__global__ void __launch_bounds__(kBwdThreads)
+bwd_march_lds_kernel(rafi_device_view view, rafi_ea_job job, const float *__restrict__ grad_image,
+                     float *__restrict__ grad, uint32_t n_rays)
+{
+    extern __shared__ float gl[];
+    uint64_t tb, te;
+    const int32_t d = rafi_tile(view, blockIdx.x, &tb, &te);
+    const Geo g = job_geo(job);
+    const Box box = ea::box_of(d, g);
+    const int32_t ox = (int32_t)box.lo0 - 1, oy = (int32_t)box.lo1 - 1, oz = (int32_t)box.lo2 - 1;
+    const int32_t ex = g.b0 + 2, ey = g.b1 + 2, ez = g.b2 + 2;
+    const int32_t nl = ex * ey * ez, sxy = ex * ey;
+    for (int32_t k = threadIdx.x; k < nl; k += blockDim.x) gl[k] = 0.0f;
+    __syncthreads();
+
+    const float c = job.c;
+    for (uint64_t i = tb + threadIdx.x; i < te; i += blockDim.x) {
+        Item it = static_cast<const Item *>(view.in_items)[i];
+        if ((uint32_t)it.ray >= n_rays) {
+            rafi_forward_t(view, i, it, RAFI_POISON);
+            continue;
+        }
+        log_visit(job, it.ray, d);
+        float org[3], dir[3];
+        int32_t K;
+        job_ray(job, it.ray, org, dir, &K);
+        const float gI = grad_image[it.ray];
+        float tau = it.tau, ctau = 0.0f, B = it.I;
+        int32_t k = it.k;
+        int32_t dest = RAFI_DONE;
+        int32_t cell = -1;
+        float acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = 0.0f;
+        auto flush = [&]() {
+            if (cell < 0) return;
+            const int32_t o[8] = {0, 1, ex, ex + 1, sxy, sxy + 1, sxy + ex, sxy + ex + 1};
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (acc[q] != 0.0f) atomicAdd(&gl[cell + o[q]], acc[q]);
+        };
+        for (; k >= 0; --k) {
+            float p[3];
+            ea::sample_pos(org, dir, job.dt, k, p);
+            if (!box.contains(p)) {
+                dest = ea::owner_of(p, g);
+                break;
+            }
+            const Tri t = ea::tri_setup(g.n, p);
+            const float rho = ea::density(job.volume, g.n, t);
+            const float sigma = c * rho;
+            const float yt = -sigma - ctau;
+            const float tt = tau + yt;
+            ctau = (tt - tau) - yt;
+            tau = tt;
+            const float T = expf(-tau);
+            const float a = -expm1f(-sigma);
+            const float dIdrho = T * __fmaf_rn(c * (1.0f - a), rho - B, a);
+            B = __fmaf_rn(a, rho - B, B);
+            if (gI == 0.0f) continue;
+            // local cell of corner (i0, j0, k0)
+            const int64_t nn = (int64_t)g.n * g.n;
+            const int32_t iz = (int32_t)(t.base / nn), rem = (int32_t)(t.base - (int64_t)iz * nn);
+            const int32_t iy = rem / g.n, ix = rem - iy * g.n;
+            const int32_t lc = (ix - ox) + ex * ((iy - oy) + ey * (iz - oz));
+            if (lc != cell) {
+                flush();
+                cell = lc;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) acc[q] = 0.0f;
+            }
+            const float s = gI * dIdrho;
+            const float gx0 = 1.0f - t.f0, gy0 = 1.0f - t.f1, gz0 = 1.0f - t.f2;
+            const float a00 = s * gz0 * gy0, a01 = s * gz0 * t.f1, a10 = s * t.f2 * gy0, a11 = s * t.f2 * t.f1;
+            acc[0] += a00 * gx0;
+            acc[1] += a00 * t.f0;
+            acc[2] += a01 * gx0;
+            acc[3] += a01 * t.f0;
+            acc[4] += a10 * gx0;
+            acc[5] += a10 * t.f0;
+            acc[6] += a11 * gx0;
+            acc[7] += a11 * t.f0;
+        }
+        flush();
+        it.k = k;
+        it.tau = tau - ctau;
+        it.I = B;
+        if (k >= 0 && dest >= 0) rafi_forward_t(view, i, it, dest);
+        else rafi_done(view, i);
+    }
+    __syncthreads();
+    for (int32_t k = threadIdx.x; k < nl; k += blockDim.x) {
+        const float v = gl[k];
+        if (v != 0.0f) {
+            const int32_t lz = k / sxy, ly = (k - lz * sxy) / ex, lx = k - lz * sxy - ly * ex;
+            const int64_t idx = (ox + lx) + (int64_t)g.n * ((oy + ly) + (int64_t)g.n * (oz + lz));
+            unsafeAtomicAdd(&grad[idx], v);
+        }
+    }
+}
+
+size_t bwd_lds_bytes(const rafi_ea_job *j)
+{
+    return sizeof(float) * (size_t)(j->n / j->grid[0] + 2) * (j->n / j->grid[1] + 2) * (j->n / j->grid[2] + 2);
+}
+
 bool job_ok(const rafi_ctx *c, const rafi_ea_job *j)
 {
     if (!c || !j || !j->volume || !j->views || !j->image) return false;
@@ -263,8 +379,17 @@ int rafi_ea_backward(rafi_ctx *c, const rafi_ea_job *job, const float *grad_imag
         hipLaunchKernelGGL(bwd_seed_kernel, dim3((uint32_t)((rays + 255) / 256)), dim3(256), 0, c->stream, v,
                            *job, rays);
     RAFI_LAUNCH_CHECK();
+    // LDS privatisation when the brick's region fits a workgroup's LDS
+    int dev = 0, max_lds = 0;
+    RAFI_HIP_CHECK(hipGetDevice(&dev));
+    RAFI_HIP_CHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t lds = bwd_lds_bytes(job);
+    const bool use_lds = lds <= (size_t)max_lds;
+    const uint32_t saved_tile = c->tile_items;
     int32_t r = 0;
     for (;;) {
+        // tiles sized so a round has a few hundred workgroups
+        if (use_lds) c->tile_items = (uint32_t)std::min<uint64_t>(4096, std::max<uint64_t>(256, c->n_slots / 512));
         uint64_t total = 0;
         rc = rafi_round(c, nullptr, &total);
         ++r;
@@ -273,11 +398,17 @@ int rafi_ea_backward(rafi_ctx *c, const rafi_ea_job *job, const float *grad_imag
         if (r >= max_rounds) { rc = RAFI_ERR_MAX_ROUNDS; break; }
         rafi_view(c, &v);
         const int ph = prof_domain_begin(c);
-        hipLaunchKernelGGL(bwd_march_kernel, dim3((uint32_t)((v.n_in + 255) / 256)), dim3(256), 0, c->stream, v,
-                           *job, grad_image, grad_volume, (uint32_t)rays);
+        if (use_lds)
+            hipLaunchKernelGGL(bwd_march_lds_kernel, dim3(v.n_tiles), dim3(kBwdThreads), lds, c->stream, v, *job,
+                               grad_image, grad_volume, (uint32_t)rays);
+        else
+            hipLaunchKernelGGL(bwd_march_kernel, dim3((uint32_t)((v.n_in + 255) / 256)), dim3(256), 0, c->stream,
+                               v, *job, grad_image, grad_volume, (uint32_t)rays);
         prof_domain_end(c, ph);
-        RAFI_LAUNCH_CHECK();
+        rc = hipGetLastError() == hipSuccess ? RAFI_OK : RAFI_ERR_HIP;
+        if (rc != RAFI_OK) break;
     }
+    c->tile_items = saved_tile;
     if (rounds) *rounds = r;
     return rc;
 }
