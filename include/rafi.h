@@ -345,7 +345,8 @@ typedef struct rafi_sl_job {
                                 most k steps per domain-kernel launch, then the particle is
                                 forwarded even to its own brick (k = 1 is the paper's one
                                 update per round). Results do not depend on k. */
-    int32_t pad;
+    uint32_t tail_items;     /* the cap is not applied in launches whose input queue holds at
+                                most this many particles (0: always applied) */
 } rafi_sl_job;
 
 /* Item: position (3 x float32) and particle id; the step count lives in
@@ -355,7 +356,7 @@ typedef struct rafi_sl_job {
 #define RAFI_SL_EXITED 2
 #define RAFI_SL_MAXSTEPS 3
 
-/* Repack field [n^3 * 3] (device) into field4 [n^3 * 4] (device). */
+/* Repack field [n^3 * 3] (device) into field4 [n^3 * 4] (device); n^3 < 2^31. */
 int rafi_sl_pack(const float *field, int32_t n, float *field4, void *hip_stream);
 
 /* Round 0: opens one slot per seed and emits seed i (id i, position

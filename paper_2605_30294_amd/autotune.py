@@ -75,3 +75,42 @@ def tune_batch(batch, volumes, image, space=None, reps=2, use_cache=True):
         with open(path, "w") as f:
             json.dump(cache, f, indent=1)
     return best, best_ms, results
+
+
+STREAMLINE_SPACE = [(c, t) for c in (32, 64, 128, 256) for t in (0, 16384, 65536)]
+
+
+def tune_streamlines(ctx, job, seeds, space=None, reps=1, use_cache=True):
+    """Picks (steps_per_visit, tail_items) for a streamline job by timing whole
+    traces; results do not depend on the choice. Returns (best, ms, results)."""
+    from . import rafi
+
+    path = cache_path()
+    dev = torch.cuda.get_device_name(torch.cuda.current_device())
+    key = f"{dev}|streamlines|n={job.n}|grid={list(job.grid)}|seeds={seeds.shape[0]}|max_steps={job.max_steps}"
+    cache = _load(path) if use_cache else {}
+    if use_cache and key in cache:
+        job.steps_per_visit, job.tail_items = cache[key]["tuning"]
+        return tuple(cache[key]["tuning"]), cache[key]["ms"], []
+    results = []
+    for cap, tail in (space or STREAMLINE_SPACE):
+        job.steps_per_visit, job.tail_items = cap, tail
+        rafi.sl_trace_job(ctx, job, seeds)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(reps):
+            rafi.sl_trace_job(ctx, job, seeds)
+        t1.record()
+        torch.cuda.synchronize()
+        results.append((t0.elapsed_time(t1) / reps, (cap, tail)))
+    results.sort(key=lambda r: r[0])
+    best_ms, best = results[0]
+    job.steps_per_visit, job.tail_items = best
+    if use_cache:
+        cache[key] = {"tuning": list(best), "ms": best_ms}
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(cache, f, indent=1)
+    return best, best_ms, results

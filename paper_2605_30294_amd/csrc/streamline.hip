@@ -27,7 +27,7 @@ __device__ inline float lerpf(float a, float b, float t) { return __fmaf_rn(t, b
 // RK4 stages and steps usually fall in the same cell (a step moves a particle
 // by a fraction of a voxel), and then no memory is touched. Reuse is exact.
 struct CellCache {
-    int64_t base = -1;  // linear index of corner (i0, j0, k0), -1 = empty
+    int32_t base = -1;  // linear index of corner (i0, j0, k0), -1 = empty
     float4 c[8];
 };
 
@@ -45,8 +45,8 @@ __device__ inline void field_at(const float4 *__restrict__ f, int32_t n, CellCac
         i0[a] = i;
         w[a] = uc - (float)i;
     }
-    const int64_t sy = n, sz = (int64_t)n * n;
-    const int64_t base = i0[0] + sy * i0[1] + sz * i0[2];
+    const int32_t sy = n, sz = n * n;  // n^3 < 2^31 (checked by the entry points)
+    const int32_t base = i0[0] + sy * i0[1] + sz * i0[2];
     if (base != cc.base) {
         const float4 *b = f + base;
         cc.c[0] = b[0];
@@ -157,7 +157,8 @@ advance_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids)
     }
     int32_t steps = job.steps[it.id];
     const float h = job.h, hh = job.h * 0.5f, h6 = (float)((double)job.h / 6.0);
-    const int32_t cap = job.steps_per_visit > 0 ? job.steps_per_visit : 0x7fffffff;
+    const bool capped = job.steps_per_visit > 0 && view.n_in > job.tail_items;
+    const int32_t cap = capped ? job.steps_per_visit : 0x7fffffff;
     float x = it.x, y = it.y, z = it.z;
     int32_t dest = d, why = 0;
     CellCache cc;
@@ -204,7 +205,7 @@ advance_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids)
 bool job_ok(const rafi_ctx *c, const rafi_sl_job *j)
 {
     if (!c || !j || !j->field4 || !j->endpoint || !j->steps) return false;
-    if (j->n < 2 || j->max_steps < 1 || !(j->h > 0.0f) || j->steps_per_visit < 0) return false;
+    if (j->n < 2 || j->n > 1290 || j->max_steps < 1 || !(j->h > 0.0f) || j->steps_per_visit < 0) return false;
     for (int a = 0; a < 3; ++a)
         if (j->grid[a] < 1 || j->n % j->grid[a] != 0) return false;
     return c->D == j->grid[0] * j->grid[1] * j->grid[2] && c->S == RAFI_SL_ITEM_BYTES;
@@ -219,7 +220,7 @@ extern "C" {
 
 int rafi_sl_pack(const float *field, int32_t n, float *field4, void *hip_stream)
 {
-    if (!field || !field4 || n < 2) return RAFI_ERR_ARG;
+    if (!field || !field4 || n < 2 || n > 1290) return RAFI_ERR_ARG;
     const uint64_t nvox = (uint64_t)n * n * n;
     const uint32_t blocks = (uint32_t)std::min<uint64_t>((nvox + 255) / 256, 65536);
     hipLaunchKernelGGL(pack_kernel, dim3(blocks), dim3(256), 0, static_cast<hipStream_t>(hip_stream), field, nvox,

@@ -106,6 +106,9 @@ def test_full_cfg1_sampled(orc):
     assert torch.equal(r["endpoint"], r2["endpoint"]) and torch.equal(r["steps"], r2["steps"])
     assert int(r2["counters"][0]) == r["forwarded"] - N == int(r["counters"][0])
     assert int(r["counters"][1]) == 0 and r2["forwarded"] == N + int(r2["counters"].sum())
+    r3 = rafi.sl_trace(f4, (4, 4, 4), torch.from_numpy(seeds).to(dev), steps_per_visit=32, tail_items=30000)
+    assert torch.equal(r["endpoint"], r3["endpoint"]) and torch.equal(r["steps"], r3["steps"])
+    assert int(r3["counters"][0]) == int(r["counters"][0])
     ids = np.sort(np.random.default_rng(2).choice(N, 4096, replace=False))
     o = orc.streamlines_brute(field, (4, 4, 4), seeds[ids])
     assert np.array_equal(ep[ids].view(np.uint32), o["endpoint"].view(np.uint32))
