@@ -348,6 +348,9 @@ def main():
     import torch
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    props = torch.cuda.get_device_properties(dev)
+    log(f"device {props.name}, {props.multi_processor_count} CUs, "
+        f"LDS per workgroup {getattr(props, 'shared_memory_per_block', 'n/a')} B")
 
     if args.only is not None:
         if args.only == "streamlines":

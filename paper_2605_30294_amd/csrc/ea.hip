@@ -87,6 +87,44 @@ march_kernel(rafi_device_view view, rafi_ea_job job, uint32_t n_rays)
     }
 }
 
+// LDS-staged march: one workgroup per domain-pure tile of the input queue
+// stages its brick's densities (plus a one-voxel rim) in LDS once and marches
+// all the tile's rays against it.
+constexpr int kMarchLdsThreads = 512;
+
+__global__ void __launch_bounds__(kMarchLdsThreads)
+march_lds_kernel(rafi_device_view view, rafi_ea_job job, uint32_t n_rays)
+{
+    extern __shared__ float vl[];
+    uint64_t tb, te;
+    const int32_t d = rafi_tile(view, blockIdx.x, &tb, &te);
+    const Geo g = job_geo(job);
+    const Box box = ea::box_of(d, g);
+    const ea::Region reg = ea::region_of(box, g);
+    ea::load_region(vl, job.volume, g.n, reg);
+    __syncthreads();
+    for (uint64_t i = tb + threadIdx.x; i < te; i += blockDim.x) {
+        Item it = static_cast<const Item *>(view.in_items)[i];
+        if ((uint32_t)it.ray >= n_rays) {
+            rafi_forward_t(view, i, it, RAFI_POISON);
+            continue;
+        }
+        log_visit(job, it.ray, d);
+        float org[3], dir[3];
+        int32_t K;
+        job_ray(job, it.ray, org, dir, &K);
+        const int32_t dest = ea::march_through_lds(vl, reg, g, box, org, dir, K, job.dt, job.c, it);
+        if (dest >= 0) {
+            rafi_forward_t(view, i, it, dest);
+        } else {
+            job.image[it.ray] = it.I;
+            if (job.tau) job.tau[it.ray] = it.tau;
+            if (job.klast) job.klast[it.ray] = it.k;
+            rafi_done(view, i);
+        }
+    }
+}
+
 // ----------------------------------------------------------- adjoint ----
 // Round 0 of the backward pass: every ray that sampled the volume starts at
 // its last inside sample, in that sample's brick, with tau = tau_N, B = 0.
@@ -290,9 +328,25 @@ bwd_march_lds_kernel(rafi_device_view view, rafi_ea_job job, const float *__rest
     }
 }
 
-size_t bwd_lds_bytes(const rafi_ea_job *j)
+// Bytes of a brick region (brick + one-voxel rim) in LDS.
+size_t region_bytes(const rafi_ea_job *j)
 {
     return sizeof(float) * (size_t)(j->n / j->grid[0] + 2) * (j->n / j->grid[1] + 2) * (j->n / j->grid[2] + 2);
+}
+
+size_t max_lds_bytes()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 0;
+    return (size_t)v;
+}
+
+// Tile size for LDS-staged launches: a few hundred workgroups per round.
+uint32_t staged_tile(uint64_t n_slots)
+{
+    return (uint32_t)std::min<uint64_t>(4096, std::max<uint64_t>(512, n_slots / 512));
 }
 
 bool job_ok(const rafi_ctx *c, const rafi_ea_job *j)
@@ -336,10 +390,19 @@ int rafi_ea_march(rafi_ctx *c, const rafi_ea_job *job)
     if (!job_ok(c, job)) return RAFI_ERR_ARG;
     rafi_device_view v;
     rafi_view(c, &v);
+    // The LDS-staged kernel pays one brick load per workgroup, so it is used
+    // when the tile table was built with large tiles and the brick fits.
+    const size_t lds = region_bytes(job);
+    const bool staged = v.tile_items >= 512 && lds <= max_lds_bytes();
     const int ph = prof_domain_begin(c);
-    if (v.n_in)
-        hipLaunchKernelGGL(march_kernel, dim3((uint32_t)((v.n_in + 255) / 256)), dim3(256), 0, c->stream, v,
-                           *job, n_rays_of(job));
+    if (v.n_in) {
+        if (staged)
+            hipLaunchKernelGGL(march_lds_kernel, dim3(v.n_tiles), dim3(kMarchLdsThreads), lds, c->stream, v, *job,
+                               n_rays_of(job));
+        else
+            hipLaunchKernelGGL(march_kernel, dim3((uint32_t)((v.n_in + 255) / 256)), dim3(256), 0, c->stream, v,
+                               *job, n_rays_of(job));
+    }
     prof_domain_end(c, ph);
     RAFI_LAUNCH_CHECK();
     return RAFI_OK;
@@ -350,8 +413,11 @@ int rafi_ea_render(rafi_ctx *c, const rafi_ea_job *job, int32_t max_rounds, int3
     if (!job_ok(c, job) || max_rounds < 1) return RAFI_ERR_ARG;
     int rc = rafi_ea_raygen(c, job);
     if (rc != RAFI_OK) return rc;
+    const bool staged = region_bytes(job) <= max_lds_bytes();
+    const uint32_t saved_tile = c->tile_items;
     int32_t r = 0;
     for (;;) {
+        if (staged) c->tile_items = staged_tile(c->n_slots);
         uint64_t total = 0;
         rc = rafi_round(c, nullptr, &total);
         ++r;
@@ -361,6 +427,7 @@ int rafi_ea_render(rafi_ctx *c, const rafi_ea_job *job, int32_t max_rounds, int3
         rc = rafi_ea_march(c, job);
         if (rc != RAFI_OK) break;
     }
+    c->tile_items = saved_tile;
     if (rounds) *rounds = r;
     return rc;
 }
@@ -380,16 +447,13 @@ int rafi_ea_backward(rafi_ctx *c, const rafi_ea_job *job, const float *grad_imag
                            *job, rays);
     RAFI_LAUNCH_CHECK();
     // LDS privatisation when the brick's region fits a workgroup's LDS
-    int dev = 0, max_lds = 0;
-    RAFI_HIP_CHECK(hipGetDevice(&dev));
-    RAFI_HIP_CHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const size_t lds = bwd_lds_bytes(job);
-    const bool use_lds = lds <= (size_t)max_lds;
+    const size_t lds = region_bytes(job);
+    const bool use_lds = lds <= max_lds_bytes();
     const uint32_t saved_tile = c->tile_items;
     int32_t r = 0;
     for (;;) {
         // tiles sized so a round has a few hundred workgroups
-        if (use_lds) c->tile_items = (uint32_t)std::min<uint64_t>(4096, std::max<uint64_t>(256, c->n_slots / 512));
+        if (use_lds) c->tile_items = staged_tile(c->n_slots);
         uint64_t total = 0;
         rc = rafi_round(c, nullptr, &total);
         ++r;

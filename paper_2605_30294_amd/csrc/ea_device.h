@@ -210,6 +210,89 @@ __device__ inline int32_t march_through(const float *__restrict__ vol, const Geo
     return dest;
 }
 
+// A brick's voxels plus a one-voxel rim, staged in LDS: region origin
+// o = lo - 1 per axis, extent e = b + 2. Samples inside the brick only touch
+// voxels [max(lo-1, 0), min(hi, n-1)], all inside the region.
+struct Region {
+    int32_t ox, oy, oz, ex, ey, ez;
+};
+
+__device__ inline Region region_of(const Box &box, const Geo &g)
+{
+    return Region{(int32_t)box.lo0 - 1, (int32_t)box.lo1 - 1, (int32_t)box.lo2 - 1, g.b0 + 2, g.b1 + 2, g.b2 + 2};
+}
+
+// Global corner index -> region index.
+__device__ inline int32_t region_index(const Region &r, int32_t n, int64_t base)
+{
+    const int32_t nn = n * n;
+    const int32_t iz = (int32_t)(base / nn), rem = (int32_t)(base - (int64_t)iz * nn);
+    const int32_t iy = rem / n, ix = rem - iy * n;
+    return (ix - r.ox) + r.ex * ((iy - r.oy) + r.ey * (iz - r.oz));
+}
+
+// Load the region of `vol` into lds (voxels outside the volume are never read).
+__device__ inline void load_region(float *lds, const float *__restrict__ vol, int32_t n, const Region &r)
+{
+    const int32_t total = r.ex * r.ey * r.ez, sxy = r.ex * r.ey;
+    for (int32_t k = threadIdx.x; k < total; k += blockDim.x) {
+        const int32_t lz = k / sxy, ly = (k - lz * sxy) / r.ex, lx = k - lz * sxy - ly * r.ex;
+        const int32_t x = r.ox + lx, y = r.oy + ly, z = r.oz + lz;
+        float v = 0.0f;
+        if (x >= 0 && x < n && y >= 0 && y < n && z >= 0 && z < n) v = vol[x + (int64_t)n * (y + (int64_t)n * z)];
+        lds[k] = v;
+    }
+}
+
+// Trilinear density from a staged region: the same values and operations as
+// density(), so the result is bit-identical.
+__device__ inline float density_lds(const float *lds, const Region &r, int32_t li, const Tri &t)
+{
+    const int32_t sy = r.ex, sz = r.ex * r.ey;
+    const float *b = lds + li;
+    const float x00 = lerpf(b[0], b[1], t.f0);
+    const float x10 = lerpf(b[sy], b[sy + 1], t.f0);
+    const float x01 = lerpf(b[sz], b[sz + 1], t.f0);
+    const float x11 = lerpf(b[sz + sy], b[sz + sy + 1], t.f0);
+    const float y0 = lerpf(x00, x10, t.f1);
+    const float y1 = lerpf(x01, x11, t.f1);
+    return lerpf(y0, y1, t.f2);
+}
+
+// march_through with the brick's densities read from a staged region.
+__device__ inline int32_t march_through_lds(const float *lds, const Region &reg, const Geo &g, const Box &box,
+                                            const float org[3], const float dir[3], int32_t K, float dt, float c,
+                                            Item &it)
+{
+    float tau = it.tau, I = it.I, ctau = 0.0f, cI = 0.0f;
+    int32_t k = it.k;
+    int32_t dest = -1;
+    for (; k < K; ++k) {
+        float p[3];
+        sample_pos(org, dir, dt, k, p);
+        if (!box.contains(p)) {
+            dest = owner_of(p, g);
+            break;
+        }
+        const Tri t = tri_setup(g.n, p);
+        const float rho = density_lds(lds, reg, region_index(reg, g.n, t.base), t);
+        const float sigma = c * rho;
+        const float w = expf(-tau) * -expm1f(-sigma);
+        const float yI = w * rho - cI;
+        const float tI = I + yI;
+        cI = (tI - I) - yI;
+        I = tI;
+        const float yt = sigma - ctau;
+        const float tt = tau + yt;
+        ctau = (tt - tau) - yt;
+        tau = tt;
+    }
+    it.k = k;
+    it.tau = tau - ctau;
+    it.I = I - cI;
+    return dest;
+}
+
 __device__ inline int32_t find_domain(const uint64_t *__restrict__ off, int32_t D, uint64_t i)
 {
     int32_t lo = 0, hi = D;  // last d with off[d] <= i
