@@ -90,7 +90,7 @@ march_kernel(rafi_device_view view, rafi_ea_job job, uint32_t n_rays)
 // LDS-staged march: one workgroup per domain-pure tile of the input queue
 // stages its brick's densities (plus a one-voxel rim) in LDS once and marches
 // all the tile's rays against it.
-constexpr int kMarchLdsThreads = 512;
+constexpr int kMarchLdsThreads = 1024;
 
 __global__ void __launch_bounds__(kMarchLdsThreads)
 march_lds_kernel(rafi_device_view view, rafi_ea_job job, uint32_t n_rays)
@@ -225,7 +225,7 @@ bwd_march_kernel(rafi_device_view view, rafi_ea_job job, const float *__restrict
 // lane first sums its ray's contributions in registers while consecutive
 // samples stay in the same trilinear cell. At the end the non-zero LDS
 // entries are added to the global gradient.
-constexpr int kBwdThreads = 512;
+constexpr int kBwdThreads = 1024;
 
 __global__ void __launch_bounds__(kBwdThreads)
 bwd_march_lds_kernel(rafi_device_view view, rafi_ea_job job, const float *__restrict__ grad_image,
@@ -288,10 +288,7 @@ bwd_march_lds_kernel(rafi_device_view view, rafi_ea_job job, const float *__rest
             B = __fmaf_rn(a, rho - B, B);
             if (gI == 0.0f) continue;
             // local cell of corner (i0, j0, k0)
-            const int64_t nn = (int64_t)g.n * g.n;
-            const int32_t iz = (int32_t)(t.base / nn), rem = (int32_t)(t.base - (int64_t)iz * nn);
-            const int32_t iy = rem / g.n, ix = rem - iy * g.n;
-            const int32_t lc = (ix - ox) + ex * ((iy - oy) + ey * (iz - oz));
+            const int32_t lc = (t.x - ox) + ex * ((t.y - oy) + ey * (t.z - oz));
             if (lc != cell) {
                 flush();
                 cell = lc;

@@ -92,9 +92,11 @@ __device__ inline void sample_pos(const float org[3], const float dir[3], float 
 
 __device__ inline float lerpf(float a, float b, float t) { return __fmaf_rn(t, b - a, a); }
 
-// Trilinear setup at p: corner (i0, j0, k0) and fractional weights.
+// Trilinear setup at p: corner (i0, j0, k0), its linear index and the
+// fractional weights.
 struct Tri {
     int64_t base;
+    int32_t x, y, z;
     float f0, f1, f2;
 };
 
@@ -110,7 +112,7 @@ __device__ inline Tri tri_setup(int32_t n, const float p[3])
         i0[a] = i;
         f[a] = u - (float)i;
     }
-    return Tri{i0[0] + (int64_t)n * (i0[1] + (int64_t)n * i0[2]), f[0], f[1], f[2]};
+    return Tri{i0[0] + (int64_t)n * (i0[1] + (int64_t)n * i0[2]), i0[0], i0[1], i0[2], f[0], f[1], f[2]};
 }
 
 // Trilinear density from the volume (voxel centres at i + 0.5).
@@ -222,13 +224,10 @@ __device__ inline Region region_of(const Box &box, const Geo &g)
     return Region{(int32_t)box.lo0 - 1, (int32_t)box.lo1 - 1, (int32_t)box.lo2 - 1, g.b0 + 2, g.b1 + 2, g.b2 + 2};
 }
 
-// Global corner index -> region index.
-__device__ inline int32_t region_index(const Region &r, int32_t n, int64_t base)
+// Corner (i0, j0, k0) of a trilinear setup -> region index.
+__device__ inline int32_t region_index(const Region &r, const Tri &t)
 {
-    const int32_t nn = n * n;
-    const int32_t iz = (int32_t)(base / nn), rem = (int32_t)(base - (int64_t)iz * nn);
-    const int32_t iy = rem / n, ix = rem - iy * n;
-    return (ix - r.ox) + r.ex * ((iy - r.oy) + r.ey * (iz - r.oz));
+    return (t.x - r.ox) + r.ex * ((t.y - r.oy) + r.ey * (t.z - r.oz));
 }
 
 // Load the region of `vol` into lds (voxels outside the volume are never read).
@@ -275,7 +274,7 @@ __device__ inline int32_t march_through_lds(const float *lds, const Region &reg,
             break;
         }
         const Tri t = tri_setup(g.n, p);
-        const float rho = density_lds(lds, reg, region_index(reg, g.n, t.base), t);
+        const float rho = density_lds(lds, reg, region_index(reg, t), t);
         const float sigma = c * rho;
         const float w = expf(-tau) * -expm1f(-sigma);
         const float yI = w * rho - cI;
