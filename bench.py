@@ -151,23 +151,37 @@ def split_microbench(dev, reps):
     items = torch.from_numpy(W.split_items(N).view(np.int32)).to(dev)
     res = {}
     ctx = rafi.Context(D, S, N)
+
+    def timed(reps_):
+        ctx.round(counts=False)                      # warm-up; slots are left intact
+        ctx.set_profiling(True)
+        for _ in range(reps_):
+            ctx.round(counts=False)
+        p = ctx.profile()
+        ctx.set_profiling(False)
+        return p["split_ms"] / p["split_calls"], p["scatter_ms"] / p["scatter_calls"]
+
     for dist in ("uniform", "zipf"):
         dest = torch.from_numpy(W.split_dest(N, D, dist)).to(dev)
         ctx.begin(N)
         ctx.emit_bulk(items, dest)
-        ctx.round(counts=False)                      # warm-up; slots are left intact
-        ctx.set_profiling(True)
-        for _ in range(reps):
-            ctx.round(counts=False)
-        p = ctx.profile()
-        ctx.set_profiling(False)
-        split_ms = p["split_ms"] / p["split_calls"]
-        scat_ms = p["scatter_ms"] / p["scatter_calls"]
+        # workgroup shape of the scatter: every shape gives the same bytes
+        shapes = {}
+        for v in (1, 2, 3, 4):
+            rafi.split_set_variant(v)
+            shapes[v] = timed(3)[0]
+        best = min(shapes, key=shapes.get)
+        rafi.split_set_variant(best)
+        split_ms, scat_ms = timed(reps)
+        rafi.split_set_variant(0)
         alg = split_bytes_per_item(S) * N
         res[dist] = {"split_ms": round(split_ms, 4), "scatter_ms": round(scat_ms, 4),
                      "items_per_s": N / (split_ms * 1e-3), "GBps": alg / (split_ms * 1e-3) / 1e9,
-                     "frac_hbm": alg / (split_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
-        log(f"split {dist}: {split_ms:.3f} ms ({res[dist]['GBps']:.0f} GB/s algorithmic), scatter {scat_ms:.3f} ms")
+                     "frac_hbm": alg / (split_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "scatter_GBps": alg / (scat_ms * 1e-3) / 1e9, "shape": best,
+                     "shape_ms": {k: round(v, 4) for k, v in shapes.items()}}
+        log(f"split {dist}: {split_ms:.3f} ms ({res[dist]['GBps']:.0f} GB/s algorithmic), scatter {scat_ms:.3f} ms, "
+            f"shapes {res[dist]['shape_ms']}")
         del dest
     ctx.close()
     del items

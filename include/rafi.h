@@ -192,6 +192,12 @@ const char *rafi_strerror(int code);
  */
 int rafi_multisplit_workspace(uint64_t n, int32_t n_domains, uint32_t item_bytes,
                               uint64_t *bytes);
+
+/* Process-wide choice of the scatter pass's workgroup shape (chunk size,
+ * waves per workgroup, workgroups per CU): 0 = automatic, 1..4 = fixed
+ * shapes, for tuning. Every shape gives the same bytes. Not synchronised:
+ * set it while no split is being launched. */
+int rafi_split_set_variant(int32_t variant);
 int rafi_multisplit(const void *items, const int32_t *dest, uint64_t n, uint32_t item_bytes,
                     int32_t n_domains, void *out, uint64_t *offsets, uint64_t *summary,
                     void *workspace, uint64_t workspace_bytes, void *hip_stream);

@@ -295,9 +295,9 @@ batch_finalize_kernel(BatchDev b)
 
 // ------------------------------------------------------------ scatter ---
 constexpr int kNW = RAFI_EA_ITEM_BYTES / 4;
-constexpr int kR = dev::staged_rounds<kNW>();
+constexpr int kR = 12, kW = 4;  // 3072-slot chunks, two workgroups per CU
 
-__global__ void __launch_bounds__(256, 2)
+__global__ void __launch_bounds__(64 * kW, 2)
 batch_scatter_kernel(BatchDev b, uint64_t cap)
 {
     extern __shared__ __align__(16) uint32_t lds[];
@@ -311,7 +311,7 @@ batch_scatter_kernel(BatchDev b, uint64_t cap)
     const uint64_t tb = b.seg_table[tr.s];
     const uint32_t *table = b.table;
     const uint64_t tcap = b.table_cap;
-    dev::staged_scatter_tile<kNW, kR>(
+    dev::staged_scatter_tile<kNW, kR, kW>(
         static_cast<const uint32_t *>(b.items_out), b.dest, tr.begin, tr.end, D, dbase, nbits,
         [&](int32_t e) {
             const uint64_t idx = tb + (uint64_t)e * tr.ntiles + tr.local;
@@ -467,8 +467,8 @@ int launch_round(rafi_batch *b, const float *volumes, float *image, hipStream_t 
     hipLaunchKernelGGL(batch_scan_partials_kernel, dim3(1), dim3(1024), 0, st, d);
     hipLaunchKernelGGL(batch_scan_apply_kernel, dim3(scan_blocks), dim3(256), 0, st, d);
     hipLaunchKernelGGL(batch_finalize_kernel, dim3(1), dim3(1024), 0, st, d);
-    const size_t lds = dev::staged_lds_bytes<kNW>(kMaxSceneDomains);
-    hipLaunchKernelGGL(batch_scatter_kernel, dim3(tiles), dim3(256), lds, st, d, (uint64_t)b->n_rays);
+    const size_t lds = dev::staged_lds_bytes<kNW, kR, kW>(kMaxSceneDomains);
+    hipLaunchKernelGGL(batch_scatter_kernel, dim3(tiles), dim3(64 * kW), lds, st, d, (uint64_t)b->n_rays);
     hipLaunchKernelGGL(batch_march_kernel, dim3(b->tune.march_grid), dim3(b->tune.march_block), 0, st, d, volumes,
                        image, (uint32_t)b->n_rays);
     RAFI_LAUNCH_CHECK();

@@ -383,6 +383,8 @@ int rafi_get_stats(const rafi_ctx *c, rafi_stats *out)
     return RAFI_OK;
 }
 
+int rafi_split_set_variant(int32_t variant) { return split_set_variant(variant); }
+
 int rafi_multisplit_workspace(uint64_t n, int32_t n_domains, uint32_t item_bytes, uint64_t *bytes)
 {
     if (!bytes || !valid_shape(n_domains, item_bytes) || n >= (1ull << 32)) return RAFI_ERR_ARG;

@@ -46,6 +46,8 @@ struct SplitPlan {
 };
 
 SplitPlan split_plan(uint64_t n, int32_t D, uint32_t S);
+// Select the staged scatter shape (0 = automatic, 1..4 = fixed shapes).
+int split_set_variant(int v);
 // A plan whose workspace covers every n <= cap.
 SplitPlan split_plan_bound(uint64_t cap, int32_t D, uint32_t S);
 

@@ -279,8 +279,8 @@ scatter_kernel(const uint32_t *__restrict__ items, const int32_t *__restrict__ d
 }
 
 // ------------------------------------------------------- pass 3, staged ---
-template <int NW, int R>
-__global__ void __launch_bounds__(256, 2)
+template <int NW, int R, int W, int OCC>
+__global__ void __launch_bounds__(64 * W, OCC)
 scatter_staged_kernel(const uint32_t *__restrict__ items, const int32_t *__restrict__ dest, uint64_t n,
                       int32_t D, int nbits, uint32_t T, uint32_t n_tiles, const uint32_t *__restrict__ table,
                       uint32_t *__restrict__ out)
@@ -289,27 +289,53 @@ scatter_staged_kernel(const uint32_t *__restrict__ items, const int32_t *__restr
     const uint64_t tstart = (uint64_t)blockIdx.x * T;
     const uint64_t tend = min(tstart + T, n);
     const uint32_t tile = blockIdx.x;
-    dev::staged_scatter_tile<NW, R>(
+    dev::staged_scatter_tile<NW, R, W>(
         items, dest, tstart, tend, D, 0, nbits,
         [&](int32_t e) { return table[(uint64_t)e * n_tiles + tile]; }, out, n, lds);
 }
+
+// One (rounds, waves, workgroups per CU) shape of the staged scatter; it is
+// launched only if its LDS fits that many workgroups per CU.
+template <int NW, int R, int W, int BPC>
+bool try_staged(const SplitPlan &p, const uint32_t *items, const int32_t *dest, const uint32_t *table,
+                uint32_t *out, hipStream_t s)
+{
+    const size_t lds = dev::staged_lds_bytes<NW, R, W>(p.D) + 64;
+    if (p.D > dev::kStagedMaxD || lds * BPC > dev::kStagedLdsPerCu) return false;
+    int nbits = 1;
+    while ((1 << nbits) < p.D) ++nbits;
+    constexpr int OCC = (W * BPC + 3) / 4;  // waves per SIMD
+    hipLaunchKernelGGL((scatter_staged_kernel<NW, R, W, OCC>), dim3(p.n_tiles), dim3(64 * W), lds, s, items, dest,
+                       p.n, p.D, nbits, p.tile, p.n_tiles, table, out);
+    return true;
+}
+
+// Process-wide choice among the staged shapes (0 = first that fits).
+int g_split_variant = 0;
 
 template <int NW>
 bool launch_staged(const SplitPlan &p, const uint32_t *items, const int32_t *dest, const uint32_t *table,
                    uint32_t *out, hipStream_t s)
 {
-    constexpr int R = dev::staged_rounds<NW>();
-    if constexpr (R == 0) {
+    const int v = g_split_variant;
+    if constexpr (NW == 8) {
+        if ((v == 0 || v == 1) && try_staged<8, 7, 4, 2>(p, items, dest, table, out, s)) return true;
+        if ((v == 0 || v == 2) && try_staged<8, 4, 4, 3>(p, items, dest, table, out, s)) return true;
+        if ((v == 0 || v == 3) && try_staged<8, 3, 8, 2>(p, items, dest, table, out, s)) return true;
+        if ((v == 0 || v == 4) && try_staged<8, 2, 4, 4>(p, items, dest, table, out, s)) return true;
         return false;
+    } else if constexpr (NW == 4) {
+        if ((v == 0 || v == 1) && try_staged<4, 12, 4, 2>(p, items, dest, table, out, s)) return true;
+        if ((v == 0 || v == 2) && try_staged<4, 8, 4, 3>(p, items, dest, table, out, s)) return true;
+        if ((v == 0 || v == 3) && try_staged<4, 5, 8, 2>(p, items, dest, table, out, s)) return true;
+        if ((v == 0 || v == 4) && try_staged<4, 4, 4, 4>(p, items, dest, table, out, s)) return true;
+        return false;
+    } else if constexpr (NW <= 3) {
+        return try_staged<NW, 16, 4, 2>(p, items, dest, table, out, s);
+    } else if constexpr (56 / NW > 0) {
+        return try_staged<NW, 56 / NW, 4, 2>(p, items, dest, table, out, s);
     } else {
-        if (p.D > dev::kStagedMaxD) return false;
-        const size_t lds = dev::staged_lds_bytes<NW>(p.D);
-        if (lds + 64 > dev::kStagedLds) return false;
-        int nbits = 1;
-        while ((1 << nbits) < p.D) ++nbits;
-        hipLaunchKernelGGL((scatter_staged_kernel<NW, R>), dim3(p.n_tiles), dim3(256), lds, s, items, dest, p.n,
-                           p.D, nbits, p.tile, p.n_tiles, table, out);
-        return true;
+        return false;
     }
 }
 
@@ -349,6 +375,13 @@ void finish_plan(SplitPlan &p)
     p.bytes = p.off_part + ((uint64_t)std::max<uint32_t>(p.scan_blocks, 1) * 4 + 255) / 256 * 256;
 }
 }  // namespace
+
+int split_set_variant(int v)
+{
+    if (v < 0 || v > 4) return RAFI_ERR_ARG;
+    g_split_variant = v;
+    return RAFI_OK;
+}
 
 SplitPlan split_plan(uint64_t n, int32_t D, uint32_t S)
 {

@@ -74,61 +74,60 @@ __device__ inline uint64_t match_peers(uint32_t key, bool ok, int nbits)
 }
 
 // ------------------------------------------------ staged stable scatter ---
-// A tile of slots [tstart, tend) is processed in chunks of CH = 4 waves x R
+// A tile of slots [tstart, tend) is processed in chunks of CH = W waves x R
 // rounds x 64 slots. Per chunk:
-//   rank   each wave owns a contiguous quarter; round r, lane l takes slot
-//          quarter_base + 64 r + l, so slot order = (round, lane) order. A
+//   rank   each wave owns a contiguous 1/W of the chunk; round r, lane l takes
+//          slot wave_base + 64 r + l, so slot order = (round, lane) order. A
 //          ballot match gives the lane's rank among same-destination lanes,
 //          and a per-wave LDS counter carries it across rounds.
 //   scan   chunk-local offsets over destinations (block scan), turned into
 //          per-wave bases.
-//   place  items move from registers into LDS at their chunk-sorted slot.
+//   place  items move from registers into LDS at their chunk-sorted slot,
+//          together with that slot's output position.
 //   write  consecutive threads write consecutive 16-byte pieces of the
 //          sorted chunk, so every destination run goes out as whole lines.
 // The next chunk's loads are issued before the write phase.
 constexpr int kStagedMaxD = 1024;
-constexpr size_t kStagedLds = 80 * 1024;  // two workgroups per CU
+constexpr size_t kStagedLdsPerCu = 160 * 1024;
 
-template <int NW>
-constexpr int staged_rounds()
+template <int NW, int R, int W>
+constexpr size_t staged_lds_bytes_c(int32_t D)
 {
-    return NW <= 3 ? 16 : (56 / NW > 0 ? 56 / NW : 0);
+    constexpr int CH = W * 64 * R;
+    return sizeof(uint32_t) * ((size_t)CH * NW + D + CH) + sizeof(uint16_t) * ((size_t)W * D + 1);
 }
 
-template <int NW>
+template <int NW, int R, int W>
 inline size_t staged_lds_bytes(int32_t D)
 {
-    constexpr int R = staged_rounds<NW>();
-    constexpr int CH = 4 * 64 * R;
-    return sizeof(uint32_t) * ((size_t)CH * NW + D + (4 * (size_t)D + 1) / 2) + sizeof(uint16_t) * CH;
+    return staged_lds_bytes_c<NW, R, W>(D);
 }
 
 // Destination of slot i is dest[i] - dbase, valid when in [0, D). run_base(e)
 // gives the output slot of the tile's first item bound for e. Output slots
 // >= out_cap are never written (they cannot occur for a consistent table).
-template <int NW, int R, typename RunBase>
+template <int NW, int R, int W, typename RunBase>
 __device__ inline void staged_scatter_tile(const uint32_t *__restrict__ items, const int32_t *__restrict__ dest,
                                            uint64_t tstart, uint64_t tend, int32_t D, int32_t dbase, int nbits,
                                            RunBase run_base, uint32_t *__restrict__ out, uint64_t out_cap,
                                            uint32_t *lds)
 {
-    constexpr int W = 4, SEG = 64 * R, CH = W * SEG;
+    constexpr int NT = 64 * W, SEG = 64 * R, CH = W * SEG;
     constexpr int PIECE = (NW % 4 == 0) ? 4 : ((NW % 2 == 0) ? 2 : 1);  // words per store
     constexpr int PPI = NW / PIECE;                                    // pieces per item
-    constexpr int EPT = (kStagedMaxD + 255) / 256;                     // max destinations per thread
+    constexpr int EPT = (kStagedMaxD + NT - 1) / NT;                   // max destinations per thread
     uint32_t *stage = lds;                                             // [CH * NW]
     uint32_t *run = stage + CH * NW;                                   // [D] next output slot per dest
-    uint32_t *cntw = run + D;                                          // [W * D / 2] (u16) / dl [D] (u32)
-    uint16_t *cnt = reinterpret_cast<uint16_t *>(cntw);
-    uint16_t *bkt = reinterpret_cast<uint16_t *>(cntw + (W * D + 1) / 2);  // [CH]
-    __shared__ uint32_t scan_lds[256 / 64 + 1];
+    uint32_t *gpos = run + D;                                          // [CH] output slot of sorted slot j
+    uint16_t *cnt = reinterpret_cast<uint16_t *>(gpos + CH);           // [W * D]
+    __shared__ uint32_t scan_lds[NT / 64 + 1];
 
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const uint64_t lt = (1ull << lane) - 1ull;
-    const int per = (D + 255) / 256;  // destinations per thread in the scans
+    const int per = (D + NT - 1) / NT;  // destinations per thread in the scans
     const int e0 = tid * per;
 
-    for (int32_t e = tid; e < D; e += 256) run[e] = run_base(e);
+    for (int32_t e = tid; e < D; e += NT) run[e] = run_base(e);
 
     uint32_t item[R][NW];
     int32_t dd[R];
@@ -158,7 +157,7 @@ __device__ inline void staged_scatter_tile(const uint32_t *__restrict__ items, c
     if (tstart < tend) load_chunk(tstart);
 
     for (uint64_t cbase = tstart; cbase < tend; cbase += CH) {
-        for (int k = tid; k < (W * D + 1) / 2; k += 256) cntw[k] = 0;
+        for (int k = tid; k < (W * D + 1) / 2; k += NT) reinterpret_cast<uint32_t *>(cnt)[k] = 0;
         __syncthreads();
 
         // rank
@@ -177,8 +176,10 @@ __device__ inline void staged_scatter_tile(const uint32_t *__restrict__ items, c
         }
         __syncthreads();
 
-        // scan: chunk totals per destination -> chunk offsets -> per-wave bases
-        uint32_t tot_e[EPT], excl_e[EPT];
+        // scan: chunk totals per destination -> chunk offsets -> per-wave
+        // bases; the wave-0 base is the chunk offset excl[e], and the output
+        // slot of chunk-sorted slot j bound for e is run[e] - excl[e] + j
+        uint32_t tot_e[EPT];
         uint32_t local = 0;
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
@@ -191,11 +192,10 @@ __device__ inline void staged_scatter_tile(const uint32_t *__restrict__ items, c
             local += t;
         }
         uint32_t chunk_total;
-        uint32_t base = block_excl_scan<256>(local, scan_lds, &chunk_total);
+        uint32_t base = block_excl_scan<NT>(local, scan_lds, &chunk_total);
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
             const int32_t e = e0 + k;
-            excl_e[k] = base;
             if (k < per && e < D) {
                 uint32_t b = base;
 #pragma unroll
@@ -225,7 +225,7 @@ __device__ inline void staged_scatter_tile(const uint32_t *__restrict__ items, c
 #pragma unroll
                     for (int k = 0; k < NW; ++k) dst[k] = item[r][k];
                 }
-                bkt[pos] = (uint16_t)d;
+                gpos[pos] = run[d] - (uint32_t)cnt[d] + pos;
             }
         }
         __syncthreads();
@@ -234,23 +234,18 @@ __device__ inline void staged_scatter_tile(const uint32_t *__restrict__ items, c
         // latency overlaps the write phase
         if (cbase + CH < tend) load_chunk(cbase + CH);
 
-        // per destination: output slot of chunk-sorted slot j is dl[e] + j
-        uint32_t *dl = cntw;
+        // advance the per-destination output slots past this chunk
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
             const int32_t e = e0 + k;
-            if (k < per && e < D) {
-                dl[e] = run[e] - excl_e[k];
-                run[e] += tot_e[k];
-            }
+            if (k < per && e < D) run[e] += tot_e[k];
         }
-        __syncthreads();
 
         // write: whole destination runs, consecutive lanes on consecutive pieces
         const uint32_t n_pieces = chunk_total * PPI;
-        for (uint32_t q = tid; q < n_pieces; q += 256) {
+        for (uint32_t q = tid; q < n_pieces; q += NT) {
             const uint32_t j = q / PPI, part = q - j * PPI;
-            const uint32_t g = dl[bkt[j]] + j;
+            const uint32_t g = gpos[j];
             if (g < out_cap) {
                 const uint32_t *src = stage + j * NW + part * PIECE;
                 uint32_t *dst = out + (uint64_t)g * NW + part * PIECE;

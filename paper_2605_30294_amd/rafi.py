@@ -104,6 +104,7 @@ _SIGS = {
     "rafi_get_profile": ([_P, C.POINTER(Profile)], C.c_int),
     "rafi_strerror": ([C.c_int], C.c_char_p),
     "rafi_multisplit_workspace": ([C.c_uint64, C.c_int32, C.c_uint32, _U64P], C.c_int),
+    "rafi_split_set_variant": ([C.c_int32], C.c_int),
     "rafi_multisplit": ([_P, _P, C.c_uint64, C.c_uint32, C.c_int32, _P, _P, _P, _P, C.c_uint64, _P], C.c_int),
     "rafi_ea_raygen": ([_P, C.POINTER(EAJob)], C.c_int),
     "rafi_ea_march": ([_P, C.POINTER(EAJob)], C.c_int),
@@ -246,6 +247,10 @@ class Context:
 
 
 # ----------------------------------------------------------- multisplit ---
+
+def split_set_variant(v: int):
+    _check(lib().rafi_split_set_variant(v), "rafi_split_set_variant")
+
 
 def multisplit_workspace(n: int, n_domains: int, item_bytes: int) -> int:
     b = C.c_uint64(0)

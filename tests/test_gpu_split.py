@@ -88,3 +88,14 @@ def test_context_round_and_error_paths(orc):
     st = ctx.stats()
     assert st["bad_dest"] == 1000 and st["done"] == e_done and st["rounds"] == 1
     ctx.close()
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+@pytest.mark.parametrize("n,D,words", [(300_001, 1024, 8), (200_003, 64, 4), (77_777, 1000, 8), (150_000, 7, 4)])
+def test_split_shapes_identical(orc, variant, n, D, words):
+    """Every workgroup shape of the staged scatter gives the oracle's bytes."""
+    try:
+        rafi.split_set_variant(variant)
+        _run_split(orc, n, D, words, seed=variant * 1000 + n)
+    finally:
+        rafi.split_set_variant(0)
