@@ -167,7 +167,7 @@ def split_microbench(dev, reps):
         ctx.emit_bulk(items, dest)
         # workgroup shape of the scatter: every shape gives the same bytes
         shapes = {}
-        for v in (1, 2, 3, 4):
+        for v in (1, 2, 3, 4, 5, 6, 7):
             rafi.split_set_variant(v)
             shapes[v] = timed(3)[0]
         best = min(shapes, key=shapes.get)

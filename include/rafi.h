@@ -194,8 +194,9 @@ int rafi_multisplit_workspace(uint64_t n, int32_t n_domains, uint32_t item_bytes
                               uint64_t *bytes);
 
 /* Process-wide choice of the scatter pass's workgroup shape (chunk size,
- * waves per workgroup, workgroups per CU): 0 = automatic, 1..4 = fixed
- * shapes, for tuning. Every shape gives the same bytes. Not synchronised:
+ * waves per workgroup, workgroups per CU): 0 = automatic; 1..4 stage items
+ * in LDS; 5..7 stage only indices and read items in sorted order. For
+ * tuning. Every shape gives the same bytes. Not synchronised:
  * set it while no split is being launched. */
 int rafi_split_set_variant(int32_t variant);
 int rafi_multisplit(const void *items, const int32_t *dest, uint64_t n, uint32_t item_bytes,

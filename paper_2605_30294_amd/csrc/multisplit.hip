@@ -310,7 +310,36 @@ bool try_staged(const SplitPlan &p, const uint32_t *items, const int32_t *dest, 
     return true;
 }
 
-// Process-wide choice among the staged shapes (0 = first that fits).
+template <int NW, int R, int W, int OCC>
+__global__ void __launch_bounds__(64 * W, OCC)
+scatter_gather_kernel(const uint32_t *__restrict__ items, const int32_t *__restrict__ dest, uint64_t n,
+                      int32_t D, int nbits, uint32_t T, uint32_t n_tiles, const uint32_t *__restrict__ table,
+                      uint32_t *__restrict__ out)
+{
+    extern __shared__ __align__(16) uint32_t lds[];
+    const uint64_t tstart = (uint64_t)blockIdx.x * T;
+    const uint64_t tend = min(tstart + T, n);
+    const uint32_t tile = blockIdx.x;
+    dev::gather_scatter_tile<NW, R, W>(
+        items, dest, tstart, tend, D, 0, nbits,
+        [&](int32_t e) { return table[(uint64_t)e * n_tiles + tile]; }, out, n, lds);
+}
+
+template <int NW, int R, int W, int BPC>
+bool try_gather(const SplitPlan &p, const uint32_t *items, const int32_t *dest, const uint32_t *table,
+                uint32_t *out, hipStream_t s)
+{
+    const size_t lds = dev::gather_lds_bytes<R, W>(p.D) + 64;
+    if (p.D > dev::kStagedMaxD || lds * BPC > dev::kStagedLdsPerCu) return false;
+    int nbits = 1;
+    while ((1 << nbits) < p.D) ++nbits;
+    constexpr int OCC = (W * BPC + 3) / 4;
+    hipLaunchKernelGGL((scatter_gather_kernel<NW, R, W, OCC>), dim3(p.n_tiles), dim3(64 * W), lds, s, items, dest,
+                       p.n, p.D, nbits, p.tile, p.n_tiles, table, out);
+    return true;
+}
+
+// Process-wide choice among the scatter shapes (0 = automatic).
 int g_split_variant = 0;
 
 template <int NW>
@@ -318,6 +347,12 @@ bool launch_staged(const SplitPlan &p, const uint32_t *items, const int32_t *des
                    uint32_t *out, hipStream_t s)
 {
     const int v = g_split_variant;
+    if (v >= 5) {
+        if (v == 5) return try_gather<NW, 16, 4, 4>(p, items, dest, table, out, s);  // 4096-slot chunks
+        if (v == 6) return try_gather<NW, 32, 4, 2>(p, items, dest, table, out, s);  // 8192-slot chunks
+        if (v == 7) return try_gather<NW, 16, 8, 2>(p, items, dest, table, out, s);  // 8192, 8 waves
+        return false;
+    }
     if constexpr (NW == 8) {
         if ((v == 0 || v == 1) && try_staged<8, 7, 4, 2>(p, items, dest, table, out, s)) return true;
         if ((v == 0 || v == 2) && try_staged<8, 4, 4, 3>(p, items, dest, table, out, s)) return true;
@@ -378,7 +413,7 @@ void finish_plan(SplitPlan &p)
 
 int split_set_variant(int v)
 {
-    if (v < 0 || v > 4) return RAFI_ERR_ARG;
+    if (v < 0 || v > 7) return RAFI_ERR_ARG;
     g_split_variant = v;
     return RAFI_OK;
 }

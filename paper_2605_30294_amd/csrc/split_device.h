@@ -261,5 +261,166 @@ __device__ inline void staged_scatter_tile(const uint32_t *__restrict__ items, c
     }
 }
 
+// ------------------------------------- gather-read, coalesced-write scatter ---
+// Same ranking as staged_scatter_tile, but LDS keeps only, per chunk-sorted
+// slot, the chunk-local source index and the output slot (6 bytes instead of
+// the item), so a chunk can hold many more slots and every destination run
+// of a chunk is long. The write phase reads each item from global memory in
+// sorted order (the chunk's lines come from HBM once and are then served by
+// L2) and writes consecutive pieces of the sorted chunk with consecutive
+// lanes.
+template <int R, int W>
+inline size_t gather_lds_bytes(int32_t D)
+{
+    constexpr int CH = W * 64 * R;
+    return sizeof(uint32_t) * ((size_t)D + CH) + sizeof(uint16_t) * ((size_t)CH + (size_t)W * D + 1);
+}
+
+template <int NW, int R, int W, typename RunBase>
+__device__ inline void gather_scatter_tile(const uint32_t *__restrict__ items, const int32_t *__restrict__ dest,
+                                           uint64_t tstart, uint64_t tend, int32_t D, int32_t dbase, int nbits,
+                                           RunBase run_base, uint32_t *__restrict__ out, uint64_t out_cap,
+                                           uint32_t *lds)
+{
+    constexpr int NT = 64 * W, SEG = 64 * R, CH = W * SEG;
+    constexpr int PIECE = (NW % 4 == 0) ? 4 : ((NW % 2 == 0) ? 2 : 1);
+    constexpr int PPI = NW / PIECE;
+    constexpr int EPT = (kStagedMaxD + NT - 1) / NT;
+    constexpr int UNROLL = 8;
+    static_assert(CH <= 65536, "chunk-local indices are 16-bit");
+    uint32_t *run = lds;                                               // [D]
+    uint32_t *gpos = run + D;                                          // [CH]
+    uint16_t *src = reinterpret_cast<uint16_t *>(gpos + CH);           // [CH]
+    uint16_t *cnt = src + CH;                                          // [W * D]
+    __shared__ uint32_t scan_lds[NT / 64 + 1];
+
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const int per = (D + NT - 1) / NT;
+    const int e0 = tid * per;
+
+    for (int32_t e = tid; e < D; e += NT) run[e] = run_base(e);
+
+    int32_t dd[R];
+    uint16_t rank[R];
+    auto load_dest = [&](uint64_t cbase) {
+        const uint64_t qbase = cbase + (uint64_t)w * SEG;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t i = qbase + 64 * r + lane;
+            dd[r] = i < tend ? __builtin_nontemporal_load(dest + i) - dbase : -1;
+        }
+    };
+    if (tstart < tend) load_dest(tstart);
+
+    for (uint64_t cbase = tstart; cbase < tend; cbase += CH) {
+        for (int k = tid; k < (W * D + 1) / 2; k += NT) reinterpret_cast<uint32_t *>(cnt)[k] = 0;
+        __syncthreads();
+
+        uint16_t *mycnt = cnt + w * D;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int32_t d = dd[r];
+            const bool ok = d >= 0 && d < D;
+            const uint64_t peers = match_peers((uint32_t)d, ok, nbits);
+            uint16_t before = 0;
+            if (ok) before = mycnt[d];
+            __builtin_amdgcn_wave_barrier();
+            rank[r] = (uint16_t)(before + __popcll(peers & lt));
+            if (ok && (peers & lt) == 0ull) mycnt[d] = (uint16_t)(before + __popcll(peers));
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+
+        uint32_t tot_e[EPT];
+        uint32_t local = 0;
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int32_t e = e0 + k;
+            uint32_t t = 0;
+            if (k < per && e < D)
+#pragma unroll
+                for (int ww = 0; ww < W; ++ww) t += cnt[ww * D + e];
+            tot_e[k] = t;
+            local += t;
+        }
+        uint32_t chunk_total;
+        uint32_t base = block_excl_scan<NT>(local, scan_lds, &chunk_total);
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int32_t e = e0 + k;
+            if (k < per && e < D) {
+                uint32_t b = base;
+#pragma unroll
+                for (int ww = 0; ww < W; ++ww) {
+                    const uint32_t c = cnt[ww * D + e];
+                    cnt[ww * D + e] = (uint16_t)b;
+                    b += c;
+                }
+            }
+            base += tot_e[k];
+        }
+        __syncthreads();
+
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int32_t d = dd[r];
+            if (d >= 0 && d < D) {
+                const uint32_t pos = (uint32_t)cnt[w * D + d] + rank[r];
+                src[pos] = (uint16_t)(w * SEG + 64 * r + lane);
+                gpos[pos] = run[d] - (uint32_t)cnt[d] + pos;
+            }
+        }
+        __syncthreads();
+
+        if (cbase + CH < tend) load_dest(cbase + CH);
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int32_t e = e0 + k;
+            if (k < per && e < D) run[e] += tot_e[k];
+        }
+
+        // write: UNROLL pieces per thread in flight (loads first, then stores)
+        const uint32_t n_pieces = chunk_total * PPI;
+        for (uint32_t q0 = 0; q0 < n_pieces; q0 += NT * UNROLL) {
+            uint32_t v[UNROLL][PIECE];
+            uint32_t g[UNROLL], part[UNROLL];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                const uint32_t q = q0 + u * NT + tid;
+                g[u] = 0xffffffffu;
+                if (q < n_pieces) {
+                    const uint32_t j = q / PPI;
+                    part[u] = q - j * PPI;
+                    g[u] = gpos[j];
+                    const uint32_t *s = items + (cbase + src[j]) * NW + part[u] * PIECE;
+                    if constexpr (PIECE == 4) {
+                        const uint4 x = *reinterpret_cast<const uint4 *>(s);
+                        v[u][0] = x.x; v[u][1] = x.y; v[u][2] = x.z; v[u][3] = x.w;
+                    } else if constexpr (PIECE == 2) {
+                        const uint2 x = *reinterpret_cast<const uint2 *>(s);
+                        v[u][0] = x.x; v[u][1] = x.y;
+                    } else {
+                        v[u][0] = *s;
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                if (g[u] < out_cap) {
+                    uint32_t *dst = out + (uint64_t)g[u] * NW + part[u] * PIECE;
+                    if constexpr (PIECE == 4)
+                        *reinterpret_cast<uint4 *>(dst) = make_uint4(v[u][0], v[u][1], v[u][2], v[u][3]);
+                    else if constexpr (PIECE == 2)
+                        *reinterpret_cast<uint2 *>(dst) = make_uint2(v[u][0], v[u][1]);
+                    else
+                        *dst = v[u][0];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace dev
 }  // namespace rafi
