@@ -189,6 +189,47 @@ def split_microbench(dev, reps):
     return res
 
 
+def split_domain_sweep(dev, reps, domains=(16, 64, 256, 1024, 4096)):
+    """The same 64M x 32-byte split over a range of destination counts
+    (uniform), best scatter shape each: how the time depends on the number of
+    output regions written at once."""
+    import numpy as np
+    import torch
+
+    from paper_2605_30294_amd import rafi
+    from paper_2605_30294_amd import workloads as W
+
+    N, S = 1 << 26, 32
+    items = torch.from_numpy(W.split_items(N).view(np.int32)).to(dev)
+    out = {}
+    for D in domains:
+        dest = torch.from_numpy(W.split_dest(N, D, "uniform")).to(dev)
+        ctx = rafi.Context(D, S, N)
+        ctx.begin(N)
+        ctx.emit_bulk(items, dest)
+        best = None
+        for v in (0, 1, 3, 7):
+            try:
+                rafi.split_set_variant(v)
+                ctx.round(counts=False)
+                ctx.set_profiling(True)
+                for _ in range(reps):
+                    ctx.round(counts=False)
+                p = ctx.profile()
+                ctx.set_profiling(False)
+                ms = p["split_ms"] / p["split_calls"]
+                if best is None or ms < best[0]:
+                    best = (ms, v, p["scatter_ms"] / p["scatter_calls"])
+            finally:
+                rafi.split_set_variant(0)
+        ctx.close()
+        del dest
+        out[D] = {"split_ms": round(best[0], 4), "scatter_ms": round(best[2], 4), "shape": best[1],
+                  "GBps": split_bytes_per_item(S) * N / (best[0] * 1e-3) / 1e9}
+        log(f"split D={D}: {best[0]:.3f} ms (scatter {best[2]:.3f}), {out[D]['GBps']:.0f} GB/s")
+    return out
+
+
 def ea_forward(dev, reps):
     import numpy as np
     import torch
@@ -343,7 +384,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seeds", type=int, default=262144)
     ap.add_argument("--only", default=None,
-                    choices=["streamlines", "split", "ea", "adjoint", "batched", "copy"],
+                    choices=["streamlines", "split", "split-domains", "ea", "adjoint", "batched", "copy"],
                     help="run one leg alone (for profilers) and print its result")
     ap.add_argument("--tail-items", type=int, default=0,
                     help="launches with at most this many particles integrate uncapped")
@@ -371,6 +412,8 @@ def main():
             res = streamline_job(args, dev)[0]
         elif args.only == "split":
             res = split_microbench(dev, reps=args.steps)
+        elif args.only == "split-domains":
+            res = split_domain_sweep(dev, reps=args.steps)
         elif args.only == "ea":
             res = ea_forward(dev, reps=args.steps)
         elif args.only == "adjoint":
