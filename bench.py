@@ -74,12 +74,12 @@ def streamline_job(args, dev):
     reason = torch.empty(N, dtype=torch.int32, device=dev)
     counters = torch.zeros(2, dtype=torch.int64, device=dev)
     job = rafi.sl_job(f4, grid, endpoint, steps, reason, h, max_steps, args.steps_per_visit, counters,
-                      args.tail_items)
+                      args.tail_items, args.refill_lanes)
     tuned = None
     if args.steps_per_visit < 0:      # autotune the schedule (results do not depend on it)
         from paper_2605_30294_amd import autotune
         tuned, _, sweep = autotune.tune_streamlines(ctx, job, seeds)
-        log("streamline schedule sweep (ms, (steps_per_visit, tail_items)): "
+        log("streamline schedule sweep (ms, (steps_per_visit, tail_items, refill_lanes)): "
             + ", ".join(f"{m:.2f} {t}" for m, t in sweep))
     for _ in range(args.warmup):
         rafi.sl_trace_job(ctx, job, seeds)
@@ -110,10 +110,11 @@ def streamline_job(args, dev):
     flops_per_launch = rk4_steps * RK4_FLOPS_PER_STEP / max(launches, 1)
     achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
     out = dict(ms=ms, rounds=rounds, forwarded=N + cross, step_items=fwd, self_fwd=self_fwd, rk4_steps=rk4_steps,
-               schedule=(job.steps_per_visit, job.tail_items),
+               schedule=(job.steps_per_visit, job.tail_items, job.refill_lanes),
                domain_ms=dom_ms, split_ms=split_ms,
                launches=launches, avg_launch_ms=avg_launch_ms,
-               roofline={"kernel": "advance_kernel (RK4 brick march)", "bound": "alu",
+               roofline={"kernel": ("advance_persistent_kernel" if job.refill_lanes else "advance_kernel")
+                         + " (RK4 brick march)", "bound": "alu",
                          "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
                          "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None,
                          "per_launch_flops": flops_per_launch, "avg_launch_ms": round(avg_launch_ms, 4)})
@@ -388,6 +389,9 @@ def main():
                     help="run one leg alone (for profilers) and print its result")
     ap.add_argument("--tail-items", type=int, default=0,
                     help="launches with at most this many particles integrate uncapped")
+    ap.add_argument("--refill-lanes", type=int, default=0,
+                    help="persistent RK4 waves refill when this many lanes are idle (0: one thread per "
+                         "particle); ignored when the schedule is autotuned")
     ap.add_argument("--steps-per-visit", type=int, default=-1,
                     help="RK4 steps a particle takes per domain visit before it is forwarded to its own "
                          "brick (0 = until it leaves, -1 = autotune with the tail threshold); results do "
@@ -447,7 +451,8 @@ def main():
         "samples_unit": "RK4 steps/s",
         "rounds": sl["rounds"], "forwarded_per_step": sl["forwarded"],
         "forward_step_items_per_step": sl["step_items"], "same_brick_forwards_per_step": sl["self_fwd"],
-        "schedule": {"steps_per_visit": sl["schedule"][0], "tail_items": sl["schedule"][1]},
+        "schedule": {"steps_per_visit": sl["schedule"][0], "tail_items": sl["schedule"][1],
+                     "refill_lanes": sl["schedule"][2]},
         "time_split": {"domain_kernels_ms": round(sl["domain_ms"], 4), "forward_steps_ms": round(sl["split_ms"], 4)},
         "roofline": sl["roofline"],
         "cpu_baseline": cpu,

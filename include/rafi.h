@@ -354,6 +354,11 @@ typedef struct rafi_sl_job {
                                 update per round). Results do not depend on k. */
     uint32_t tail_items;     /* the cap is not applied in launches whose input queue holds at
                                 most this many particles (0: always applied) */
+    int32_t refill_lanes;    /* 0: one thread per queued particle; 1..64: persistent waves,
+                                each taking new particles from the queue whenever at least
+                                this many of its 64 lanes are idle (lanes stay busy while
+                                their neighbours cross the brick). Results do not depend on
+                                it. Outside 0..64: RAFI_ERR_ARG. */
 } rafi_sl_job;
 
 /* Item: position (3 x float32) and particle id; the step count lives in

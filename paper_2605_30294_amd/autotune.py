@@ -77,24 +77,31 @@ def tune_batch(batch, volumes, image, space=None, reps=2, use_cache=True):
     return best, best_ms, results
 
 
-STREAMLINE_SPACE = [(c, t) for c in (32, 64, 128, 256) for t in (0, 16384, 65536)]
+# (steps_per_visit, tail_items, refill_lanes)
+STREAMLINE_SPACE = [(c, t, r) for c in (32, 64, 128, 256, 512) for t in (0, 65536) for r in (0, 8, 16, 32)]
+
+
+def _set_schedule(job, tuning):
+    job.steps_per_visit, job.tail_items, job.refill_lanes = (int(v) for v in tuning)
 
 
 def tune_streamlines(ctx, job, seeds, space=None, reps=1, use_cache=True):
-    """Picks (steps_per_visit, tail_items) for a streamline job by timing whole
-    traces; results do not depend on the choice. Returns (best, ms, results)."""
+    """Picks (steps_per_visit, tail_items, refill_lanes) for a streamline job by
+    timing whole traces; results do not depend on the choice.
+    Returns (best, ms, results)."""
     from . import rafi
 
     path = cache_path()
     dev = torch.cuda.get_device_name(torch.cuda.current_device())
-    key = f"{dev}|streamlines|n={job.n}|grid={list(job.grid)}|seeds={seeds.shape[0]}|max_steps={job.max_steps}"
+    key = (f"{dev}|streamlines|n={job.n}|grid={list(job.grid)}|seeds={seeds.shape[0]}|max_steps={job.max_steps}"
+           f"|schedule=cap,tail,refill")
     cache = _load(path) if use_cache else {}
-    if use_cache and key in cache:
-        job.steps_per_visit, job.tail_items = cache[key]["tuning"]
+    if use_cache and key in cache and len(cache[key]["tuning"]) == 3:
+        _set_schedule(job, cache[key]["tuning"])
         return tuple(cache[key]["tuning"]), cache[key]["ms"], []
     results = []
-    for cap, tail in (space or STREAMLINE_SPACE):
-        job.steps_per_visit, job.tail_items = cap, tail
+    for tuning in (space or STREAMLINE_SPACE):
+        _set_schedule(job, tuning)
         rafi.sl_trace_job(ctx, job, seeds)
         torch.cuda.synchronize()
         t0 = torch.cuda.Event(enable_timing=True)
@@ -104,10 +111,10 @@ def tune_streamlines(ctx, job, seeds, space=None, reps=1, use_cache=True):
             rafi.sl_trace_job(ctx, job, seeds)
         t1.record()
         torch.cuda.synchronize()
-        results.append((t0.elapsed_time(t1) / reps, (cap, tail)))
+        results.append((t0.elapsed_time(t1) / reps, tuple(tuning)))
     results.sort(key=lambda r: r[0])
     best_ms, best = results[0]
-    job.steps_per_visit, job.tail_items = best
+    _set_schedule(job, best)
     if use_cache:
         cache[key] = {"tuning": list(best), "ms": best_ms}
         os.makedirs(os.path.dirname(path), exist_ok=True)

@@ -181,6 +181,8 @@ int rafi_create(int32_t n_domains, uint32_t item_bytes, uint64_t capacity, rafi_
          hipMalloc(reinterpret_cast<void **>(&c->tile_offsets), sizeof(uint32_t) * (n_domains + 1)) != hipSuccess ||
          hipMalloc(reinterpret_cast<void **>(&c->summary), sizeof(uint64_t) * 4) != hipSuccess ||
          hipMalloc(reinterpret_cast<void **>(&c->dropped), sizeof(unsigned long long)) != hipSuccess ||
+         hipMalloc(reinterpret_cast<void **>(&c->work), 2 * sizeof(unsigned long long)) != hipSuccess ||
+         hipMemset(c->work, 0, 2 * sizeof(unsigned long long)) != hipSuccess ||
          hipHostMalloc(reinterpret_cast<void **>(&c->host_summary), sizeof(uint64_t) * 8, hipHostMallocDefault) != hipSuccess))
         rc = RAFI_ERR_OOM;
     if (rc == RAFI_OK) rc = empty_queue(c);
@@ -203,6 +205,7 @@ void rafi_destroy(rafi_ctx *c)
     if (c->tile_offsets) (void)hipFree(c->tile_offsets);
     if (c->summary) (void)hipFree(c->summary);
     if (c->dropped) (void)hipFree(c->dropped);
+    if (c->work) (void)hipFree(c->work);
     if (c->host_summary) (void)hipHostFree(c->host_summary);
     for (int i = 0; i < c->n_pending; ++i)
         for (int k = 0; k < (c->pending[i].kind == 0 ? 3 : 2); ++k)

@@ -410,11 +410,11 @@ int rafi_ea_render(rafi_ctx *c, const rafi_ea_job *job, int32_t max_rounds, int3
     if (!job_ok(c, job) || max_rounds < 1) return RAFI_ERR_ARG;
     int rc = rafi_ea_raygen(c, job);
     if (rc != RAFI_OK) return rc;
-    const bool staged = region_bytes(job) <= max_lds_bytes();
-    const uint32_t saved_tile = c->tile_items;
+    // The march kernel is chosen by the context's tile size (see rafi_ea_march);
+    // the default tiles select the gather kernel, which measured faster than
+    // the LDS-staged one on coherent view batches.
     int32_t r = 0;
     for (;;) {
-        if (staged) c->tile_items = staged_tile(c->n_slots);
         uint64_t total = 0;
         rc = rafi_round(c, nullptr, &total);
         ++r;
@@ -424,7 +424,6 @@ int rafi_ea_render(rafi_ctx *c, const rafi_ea_job *job, int32_t max_rounds, int3
         rc = rafi_ea_march(c, job);
         if (rc != RAFI_OK) break;
     }
-    c->tile_items = saved_tile;
     if (rounds) *rounds = r;
     return rc;
 }

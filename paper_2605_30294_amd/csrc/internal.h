@@ -79,6 +79,9 @@ struct rafi_ctx {
     uint32_t *tile_offsets = nullptr;   // [D+1]
     uint64_t *summary = nullptr;        // [4] device
     unsigned long long *dropped = nullptr;  // device counter
+    // Persistent domain kernels: [0] next queue index to hand out, [1] waves
+    // that have exited. Zero between launches: the last wave to exit resets both.
+    unsigned long long *work = nullptr;
     uint64_t *host_summary = nullptr;   // pinned [8]
     void *ws = nullptr;
     uint64_t ws_bytes = 0;

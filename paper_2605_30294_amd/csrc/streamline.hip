@@ -69,6 +69,23 @@ __device__ inline void field_at(const float4 *__restrict__ f, int32_t n, CellCac
 #undef TRI
 }
 
+// One classical RK4 step from (x, y, z), with the operation order fixed above.
+__device__ inline void rk4_step(const float4 *__restrict__ F, int32_t n, CellCache &cc, float h, float hh, float h6,
+                                float x, float y, float z, float &nx, float &ny, float &nz)
+{
+    float k1x, k1y, k1z, k2x, k2y, k2z, k3x, k3y, k3z, k4x, k4y, k4z;
+    field_at(F, n, cc, x, y, z, k1x, k1y, k1z);
+    field_at(F, n, cc, __fmaf_rn(hh, k1x, x), __fmaf_rn(hh, k1y, y), __fmaf_rn(hh, k1z, z), k2x, k2y, k2z);
+    field_at(F, n, cc, __fmaf_rn(hh, k2x, x), __fmaf_rn(hh, k2y, y), __fmaf_rn(hh, k2z, z), k3x, k3y, k3z);
+    field_at(F, n, cc, __fmaf_rn(h, k3x, x), __fmaf_rn(h, k3y, y), __fmaf_rn(h, k3z, z), k4x, k4y, k4z);
+    const float sx = __fmaf_rn(2.0f, k3x, __fmaf_rn(2.0f, k2x, k1x)) + k4x;
+    const float sy = __fmaf_rn(2.0f, k3y, __fmaf_rn(2.0f, k2y, k1y)) + k4y;
+    const float sz = __fmaf_rn(2.0f, k3z, __fmaf_rn(2.0f, k2z, k1z)) + k4z;
+    nx = __fmaf_rn(h6, sx, x);
+    ny = __fmaf_rn(h6, sy, y);
+    nz = __fmaf_rn(h6, sz, z);
+}
+
 struct Geo {
     int32_t n, g0, g1, g2, b0, b1, b2;
 };
@@ -163,15 +180,8 @@ advance_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids)
     int32_t dest = d, why = 0;
     CellCache cc;
     for (int32_t taken = 0;;) {
-        float k1x, k1y, k1z, k2x, k2y, k2z, k3x, k3y, k3z, k4x, k4y, k4z;
-        field_at(F, g.n, cc, x, y, z, k1x, k1y, k1z);
-        field_at(F, g.n, cc, __fmaf_rn(hh, k1x, x), __fmaf_rn(hh, k1y, y), __fmaf_rn(hh, k1z, z), k2x, k2y, k2z);
-        field_at(F, g.n, cc, __fmaf_rn(hh, k2x, x), __fmaf_rn(hh, k2y, y), __fmaf_rn(hh, k2z, z), k3x, k3y, k3z);
-        field_at(F, g.n, cc, __fmaf_rn(h, k3x, x), __fmaf_rn(h, k3y, y), __fmaf_rn(h, k3z, z), k4x, k4y, k4z);
-        const float sx = __fmaf_rn(2.0f, k3x, __fmaf_rn(2.0f, k2x, k1x)) + k4x;
-        const float sy = __fmaf_rn(2.0f, k3y, __fmaf_rn(2.0f, k2y, k1y)) + k4y;
-        const float sz = __fmaf_rn(2.0f, k3z, __fmaf_rn(2.0f, k2z, k1z)) + k4z;
-        const float nx = __fmaf_rn(h6, sx, x), ny = __fmaf_rn(h6, sy, y), nz = __fmaf_rn(h6, sz, z);
+        float nx, ny, nz;
+        rk4_step(F, g.n, cc, h, hh, h6, x, y, z, nx, ny, nz);
         ++steps;
         ++taken;
         const bool same = __float_as_uint(nx) == __float_as_uint(x) && __float_as_uint(ny) == __float_as_uint(y) &&
@@ -202,10 +212,156 @@ advance_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids)
     }
 }
 
+constexpr int kSLThreads = 256;
+
+// Persistent form of advance_kernel. Each wave keeps 64 particles in flight:
+// whenever at least job.refill_lanes lanes are idle, lane 0 takes that many
+// queue indices from work[0] and the idle lanes load them. A particle is
+// integrated exactly as in advance_kernel and written to its own slot, so
+// results and routing are the same; only the assignment of particles to lanes
+// changes. Every wave exits once the queue is handed out and its lanes are
+// idle; each particle needs at most max_steps steps, so every wave ends.
+// The last wave to exit (work[1] reaching n_waves - 1) resets both counters.
+__global__ void __launch_bounds__(kSLThreads)
+advance_persistent_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids, unsigned long long *work,
+                          uint32_t n_waves)
+{
+    const Geo g = make_geo(job);
+    const float4 *__restrict__ F = reinterpret_cast<const float4 *>(job.field4);
+    const uint64_t n = view.n_in;
+    const int lane = threadIdx.x & 63;
+    const uint64_t lanes_below = (1ull << lane) - 1;
+    const float h = job.h, hh = job.h * 0.5f, h6 = (float)((double)job.h / 6.0);
+    const bool capped = job.steps_per_visit > 0 && n > job.tail_items;
+    const int32_t cap = capped ? job.steps_per_visit : 0x7fffffff;
+    const int refill = job.refill_lanes;
+
+    bool has = false, exhausted = false;
+    uint64_t i = 0;
+    SLItem it{};
+    int32_t d = 0, steps = 0, taken = 0;
+    float lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0, lo2 = 0, hi2 = 0;
+    uint32_t n_cross = 0, n_self = 0;
+    CellCache cc;
+    for (;;) {
+        uint64_t idle = __ballot(!has);
+        if (!exhausted && __popcll(idle) >= refill) {
+            const uint32_t grab = (uint32_t)__popcll(idle);
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(&work[0], (unsigned long long)grab);
+            base = __shfl(base, 0);
+            if (base + grab >= n) exhausted = true;
+            if (!has) {
+                const uint64_t j = base + (uint64_t)__popcll(idle & lanes_below);
+                if (j < n) {
+                    i = j;
+                    it = static_cast<const SLItem *>(view.in_items)[j];
+                    if ((uint64_t)(uint32_t)it.id >= n_ids) {  // never true for items this library emitted
+                        rafi_forward_t(view, j, it, RAFI_POISON);
+                    } else {
+                        d = find_domain(view.in_offsets, view.n_domains, j);
+                        const int32_t bx = d % g.g0, by = (d / g.g0) % g.g1, bz = d / (g.g0 * g.g1);
+                        lo0 = (float)(bx * g.b0);
+                        hi0 = (float)((bx + 1) * g.b0);
+                        lo1 = (float)(by * g.b1);
+                        hi1 = (float)((by + 1) * g.b1);
+                        lo2 = (float)(bz * g.b2);
+                        hi2 = (float)((bz + 1) * g.b2);
+                        steps = job.steps[it.id];
+                        taken = 0;
+                        has = true;
+                    }
+                }
+            }
+            idle = __ballot(!has);
+        }
+        if (idle == ~0ull) {
+            if (exhausted) break;
+            continue;
+        }
+        if (has) {
+            float nx, ny, nz;
+            rk4_step(F, g.n, cc, h, hh, h6, it.x, it.y, it.z, nx, ny, nz);
+            ++steps;
+            ++taken;
+            const bool same = __float_as_uint(nx) == __float_as_uint(it.x) &&
+                              __float_as_uint(ny) == __float_as_uint(it.y) &&
+                              __float_as_uint(nz) == __float_as_uint(it.z);
+            it.x = nx;
+            it.y = ny;
+            it.z = nz;
+            int32_t why = 0, dest = -1;
+            if (same) {
+                why = RAFI_SL_STAGNANT;
+            } else {
+                const bool inside = nx >= lo0 && nx < hi0 && ny >= lo1 && ny < hi1 && nz >= lo2 && nz < hi2;
+                const int32_t e = inside ? d : owner_of(nx, ny, nz, g);
+                if (e < 0) why = RAFI_SL_EXITED;
+                else if (steps >= job.max_steps) why = RAFI_SL_MAXSTEPS;
+                else if (e != d || taken >= cap) dest = e;
+            }
+            if (why || dest >= 0) {
+                job.steps[it.id] = steps;
+                if (why) {
+                    job.endpoint[3 * (size_t)it.id] = nx;
+                    job.endpoint[3 * (size_t)it.id + 1] = ny;
+                    job.endpoint[3 * (size_t)it.id + 2] = nz;
+                    if (job.reason) job.reason[it.id] = why;
+                    rafi_done(view, i);
+                } else {
+                    n_cross += dest != d;
+                    n_self += dest == d;
+                    rafi_forward_t(view, i, it, dest);
+                }
+                has = false;
+            }
+        }
+    }
+    // all lanes are converged here (the exit test is wave-uniform)
+    if (job.counters) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            n_cross += __shfl_xor(n_cross, o);
+            n_self += __shfl_xor(n_self, o);
+        }
+        if (lane == 0) {
+            if (n_cross) atomicAdd(&job.counters[0], (unsigned long long)n_cross);
+            if (n_self) atomicAdd(&job.counters[1], (unsigned long long)n_self);
+        }
+    }
+    if (lane == 0) {
+        const unsigned long long done = atomicAdd(&work[1], 1ull);
+        if (done == n_waves - 1) {
+            atomicExch(&work[0], 0ull);
+            atomicExch(&work[1], 0ull);
+        }
+    }
+}
+
+// Workgroups of the persistent kernel that fit on the device at once.
+uint32_t persistent_blocks()
+{
+    static int cached_dev = -1;
+    static uint32_t cached = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (dev != cached_dev) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, advance_persistent_kernel, kSLThreads, 0) !=
+                hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        cached = (uint32_t)std::max(1, per_cu) * (uint32_t)std::max(1, cus);
+        cached_dev = dev;
+    }
+    return cached;
+}
+
 bool job_ok(const rafi_ctx *c, const rafi_sl_job *j)
 {
     if (!c || !j || !j->field4 || !j->endpoint || !j->steps) return false;
     if (j->n < 2 || j->n > 1290 || j->max_steps < 1 || !(j->h > 0.0f) || j->steps_per_visit < 0) return false;
+    if (j->refill_lanes < 0 || j->refill_lanes > 64) return false;
     for (int a = 0; a < 3; ++a)
         if (j->grid[a] < 1 || j->n % j->grid[a] != 0) return false;
     return c->D == j->grid[0] * j->grid[1] * j->grid[2] && c->S == RAFI_SL_ITEM_BYTES;
@@ -248,10 +404,18 @@ int rafi_sl_advance(rafi_ctx *c, const rafi_sl_job *job)
     if (!job_ok(c, job)) return RAFI_ERR_ARG;
     rafi_device_view v;
     rafi_view(c, &v);
+    const uint64_t one_per_item = (v.n_in + kSLThreads - 1) / kSLThreads;
+    const uint32_t resident = job->refill_lanes > 0 ? persistent_blocks() : 1;
+    if (!resident) return RAFI_ERR_HIP;
     const int ph = prof_domain_begin(c);
-    if (v.n_in)
-        hipLaunchKernelGGL(advance_kernel, dim3((uint32_t)((v.n_in + 255) / 256)), dim3(256), 0, c->stream, v,
-                           *job, c->wave_slots);
+    if (v.n_in && job->refill_lanes > 0) {
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>(one_per_item, resident);
+        hipLaunchKernelGGL(advance_persistent_kernel, dim3(blocks), dim3(kSLThreads), 0, c->stream, v, *job,
+                           c->wave_slots, c->work, blocks * (kSLThreads / 64));
+    } else if (v.n_in) {
+        hipLaunchKernelGGL(advance_kernel, dim3((uint32_t)one_per_item), dim3(kSLThreads), 0, c->stream, v, *job,
+                           c->wave_slots);
+    }
     prof_domain_end(c, ph);
     RAFI_LAUNCH_CHECK();
     return RAFI_OK;

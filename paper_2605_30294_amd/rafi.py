@@ -65,7 +65,8 @@ class EAJob(C.Structure):
 class SLJob(C.Structure):
     _fields_ = [("field4", C.c_void_p), ("endpoint", C.c_void_p), ("steps", C.c_void_p), ("reason", C.c_void_p),
                 ("counters", C.c_void_p), ("n", C.c_int32), ("grid", C.c_int32 * 3), ("h", C.c_float),
-                ("max_steps", C.c_int32), ("steps_per_visit", C.c_int32), ("tail_items", C.c_uint32)]
+                ("max_steps", C.c_int32), ("steps_per_visit", C.c_int32), ("tail_items", C.c_uint32),
+                ("refill_lanes", C.c_int32)]
 
 
 class ViewRec(C.Structure):
@@ -346,11 +347,11 @@ def sl_pack(field: torch.Tensor) -> torch.Tensor:
 
 
 def sl_job(field4: torch.Tensor, grid, endpoint, steps, reason=None, h=0.25, max_steps=2000,
-           steps_per_visit=0, counters=None, tail_items=0) -> SLJob:
+           steps_per_visit=0, counters=None, tail_items=0, refill_lanes=0) -> SLJob:
     """counters: optional int64 device tensor [2] (cross-brick forwards, same-brick forwards)."""
     return SLJob(_dptr(field4), _dptr(endpoint), _dptr(steps), _dptr(reason), _dptr(counters), field4.shape[0],
                  (C.c_int32 * 3)(*[int(g) for g in grid]), float(h), int(max_steps), int(steps_per_visit),
-                 int(tail_items))
+                 int(tail_items), int(refill_lanes))
 
 
 def sl_seed(ctx: Context, job: SLJob, seeds: torch.Tensor):
@@ -370,7 +371,7 @@ def sl_trace_job(ctx: Context, job: SLJob, seeds: torch.Tensor, max_rounds: int 
 
 
 def sl_trace(field4: torch.Tensor, grid, seeds: torch.Tensor, h=0.25, max_steps=2000, ctx: Context | None = None,
-             max_rounds: int = 100000, steps_per_visit=0, tail_items=0):
+             max_rounds: int = 100000, steps_per_visit=0, tail_items=0, refill_lanes=0):
     dev = field4.device
     N = seeds.shape[0]
     if ctx is None:
@@ -379,7 +380,8 @@ def sl_trace(field4: torch.Tensor, grid, seeds: torch.Tensor, h=0.25, max_steps=
     steps = torch.empty(N, dtype=torch.int32, device=dev)
     reason = torch.empty(N, dtype=torch.int32, device=dev)
     counters = torch.zeros(2, dtype=torch.int64, device=dev)
-    job = sl_job(field4, grid, endpoint, steps, reason, h, max_steps, steps_per_visit, counters, tail_items)
+    job = sl_job(field4, grid, endpoint, steps, reason, h, max_steps, steps_per_visit, counters, tail_items,
+                 refill_lanes)
     rounds, fwd = sl_trace_job(ctx, job, seeds, max_rounds)
     return dict(endpoint=endpoint, steps=steps, reason=reason, rounds=rounds, forwarded=fwd, ctx=ctx,
                 counters=counters)

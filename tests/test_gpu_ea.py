@@ -23,8 +23,9 @@ RTOL = 1e-5
 ATOL = 1e-35
 
 
-def _stepwise(vol_t, grid, views, dt=0.5, c=C32):
-    """Run the rounds one at a time, snapshotting every queue."""
+def _stepwise(vol_t, grid, views, dt=0.5, c=C32, tile_items=None):
+    """Run the rounds one at a time, snapshotting every queue.  Tiles of 512
+    items or more select the LDS-staged march kernel when the brick fits."""
     dev = vol_t.device
     nv, w, h = len(views), int(views[0]["width"]), int(views[0]["height"])
     n_rays = nv * w * h
@@ -35,6 +36,8 @@ def _stepwise(vol_t, grid, views, dt=0.5, c=C32):
     klast = torch.zeros(n_rays, dtype=torch.int32, device=dev)
     job = rafi.ea_job(vol_t, grid, vdev, nv, w, h, image, tau, klast, dt, c)
     rafi.ea_raygen(ctx, job)
+    if tile_items:
+        ctx.set_tile_items(tile_items)
     counts, queues = [], []
     while True:
         cnt, total, rc = ctx.round()
@@ -63,13 +66,14 @@ def _compare(g, o):
     assert g["stats"]["bad_dest"] == 0 and g["stats"]["dropped"] == 0
 
 
-def test_cfg0_plusz_64cube(orc):
+@pytest.mark.parametrize("tile_items", [None, 2048])
+def test_cfg0_plusz_64cube(orc, tile_items):
     """64^3 blobs, 2x2x2 domains, 128x128 rays along +z."""
     dev = device()
     vol = W.blob_volume(64, W.SEED_CFG0_VOLUME)
     views = W.plusz_view(64, 128, 128)
-    announce("ea cfg0")
-    g = _stepwise(torch.from_numpy(vol).to(dev), (2, 2, 2), views)
+    announce(f"ea cfg0 tile_items={tile_items}")
+    g = _stepwise(torch.from_numpy(vol).to(dev), (2, 2, 2), views, tile_items=tile_items)
     o = orc.ea_render(vol, (2, 2, 2), views, c=C32, queue_cap=1 << 20)
     assert len(g["counts"]) == 3
     _compare(g, o)
@@ -79,12 +83,13 @@ def test_cfg0_plusz_64cube(orc):
     (32, (4, 4, 4), 3, 20, 20, 1), (32, (2, 1, 4), 2, 33, 17, 2), (48, (3, 2, 1), 2, 40, 40, 3),
     (16, (1, 1, 1), 1, 7, 9, 4), (64, (4, 2, 2), 4, 64, 64, 5),
 ])
-def test_rotated_views(orc, n, grid, nv, w, h, seed):
+@pytest.mark.parametrize("tile_items", [None, 512])
+def test_rotated_views(orc, n, grid, nv, w, h, seed, tile_items):
     dev = device()
     vol = W.blob_volume(n, 100 + seed)
     views = W.random_views(nv, n, w, h, seed=200 + seed)
-    announce(f"ea rotated n={n} grid={grid}")
-    g = _stepwise(torch.from_numpy(vol).to(dev), grid, views)
+    announce(f"ea rotated n={n} grid={grid} tile_items={tile_items}")
+    g = _stepwise(torch.from_numpy(vol).to(dev), grid, views, tile_items=tile_items)
     o = orc.ea_render(vol, grid, views, c=C32, queue_cap=1 << 22)
     _compare(g, o)
 

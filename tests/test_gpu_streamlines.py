@@ -14,7 +14,7 @@ from paper_2605_30294_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def _stepwise(field, grid, seeds, h=0.25, max_steps=2000, steps_per_visit=0):
+def _stepwise(field, grid, seeds, h=0.25, max_steps=2000, steps_per_visit=0, refill_lanes=0):
     dev = device()
     N = len(seeds)
     f4 = rafi.sl_pack(torch.from_numpy(np.ascontiguousarray(field)).to(dev))
@@ -22,7 +22,7 @@ def _stepwise(field, grid, seeds, h=0.25, max_steps=2000, steps_per_visit=0):
     ep = torch.zeros((N, 3), dtype=torch.float32, device=dev)
     st = torch.zeros(N, dtype=torch.int32, device=dev)
     why = torch.zeros(N, dtype=torch.int32, device=dev)
-    job = rafi.sl_job(f4, grid, ep, st, why, h, max_steps, steps_per_visit)
+    job = rafi.sl_job(f4, grid, ep, st, why, h, max_steps, steps_per_visit, refill_lanes=refill_lanes)
     rafi.sl_seed(ctx, job, torch.from_numpy(seeds).to(dev))
     counts, queues = [], []
     while True:
@@ -49,25 +49,29 @@ def _compare(g, o):
     assert g["stats"]["bad_dest"] == 0 and g["stats"]["dropped"] == 0
 
 
+# refill_lanes 0: one thread per particle; 1..64: persistent waves that take new
+# particles whenever that many lanes are idle (1 and 64 are the extremes)
+@pytest.mark.parametrize("refill", [0, 1, 16, 64])
 @pytest.mark.parametrize("n,grid,N,max_steps", [(64, (4, 4, 4), 4096, 2000), (64, (2, 1, 4), 3001, 500),
                                                 (32, (1, 1, 1), 100, 300), (96, (3, 4, 2), 2000, 800)])
-def test_abc_matches_oracle(orc, n, grid, N, max_steps):
+def test_abc_matches_oracle(orc, n, grid, N, max_steps, refill):
     field = W.abc_field(n)
     seeds = W.streamline_seeds(N, n, seed=N + n)
-    announce(f"sl abc n={n} grid={grid} N={N}")
-    g = _stepwise(field, grid, seeds, max_steps=max_steps)
+    announce(f"sl abc n={n} grid={grid} N={N} refill={refill}")
+    g = _stepwise(field, grid, seeds, max_steps=max_steps, refill_lanes=refill)
     o = orc.streamlines(field, grid, seeds, max_steps=max_steps, queue_cap=1 << 24)
     _compare(g, o)
 
 
+@pytest.mark.parametrize("refill", [0, 8])
 @pytest.mark.parametrize("cap", [1, 7, 64])
-def test_steps_per_visit_cap(orc, cap):
+def test_steps_per_visit_cap(orc, cap, refill):
     """At most `cap` steps per domain visit (cap 1 = the paper's one update per
     round): per-round queues follow the capped schedule, results do not move."""
     field = W.abc_field(32)
     seeds = W.streamline_seeds(256, 32, seed=5)
-    announce(f"sl steps_per_visit={cap}")
-    g = _stepwise(field, (2, 2, 2), seeds, max_steps=120, steps_per_visit=cap)
+    announce(f"sl steps_per_visit={cap} refill={refill}")
+    g = _stepwise(field, (2, 2, 2), seeds, max_steps=120, steps_per_visit=cap, refill_lanes=refill)
     o = orc.streamlines(field, (2, 2, 2), seeds, max_steps=120, steps_per_visit=cap, max_rounds=1000,
                         queue_cap=1 << 22)
     _compare(g, o)
@@ -109,6 +113,14 @@ def test_full_cfg1_sampled(orc):
     r3 = rafi.sl_trace(f4, (4, 4, 4), torch.from_numpy(seeds).to(dev), steps_per_visit=32, tail_items=30000)
     assert torch.equal(r["endpoint"], r3["endpoint"]) and torch.equal(r["steps"], r3["steps"])
     assert int(r3["counters"][0]) == int(r["counters"][0])
+    # persistent waves with lane refill: same particles, same forward counts;
+    # run twice so the second launch sees the work counter reset by the first
+    for _ in range(2):
+        r4 = rafi.sl_trace(f4, (4, 4, 4), torch.from_numpy(seeds).to(dev), steps_per_visit=128, refill_lanes=16)
+        assert torch.equal(r["endpoint"], r4["endpoint"]) and torch.equal(r["steps"], r4["steps"])
+        assert torch.equal(r["reason"], r4["reason"])
+        assert int(r4["counters"][0]) == int(r["counters"][0])
+        assert r4["forwarded"] == N + int(r4["counters"].sum())
     ids = np.sort(np.random.default_rng(2).choice(N, 4096, replace=False))
     o = orc.streamlines_brute(field, (4, 4, 4), seeds[ids])
     assert np.array_equal(ep[ids].view(np.uint32), o["endpoint"].view(np.uint32))
