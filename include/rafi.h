@@ -195,9 +195,12 @@ int rafi_multisplit_workspace(uint64_t n, int32_t n_domains, uint32_t item_bytes
 
 /* Process-wide choice of the scatter pass's workgroup shape (chunk size,
  * waves per workgroup, workgroups per CU): 0 = automatic; 1..4 stage items
- * in LDS; 5..7 stage only indices and read items in sorted order. For
- * tuning. Every shape gives the same bytes. Not synchronised:
- * set it while no split is being launched. */
+ * in LDS; 5..7 stage only indices and read items in sorted order; 8..11 are
+ * shapes 1..4 with the next chunk's loads issued before the current chunk is
+ * ranked; 12..13 use one workgroup per CU with 4096-slot chunks (32-byte
+ * items), 13 with the next chunk's loads issued early. For tuning. Every
+ * shape gives the same bytes. Not synchronised: set it while no split is
+ * being launched. Outside 0..13: RAFI_ERR_ARG. */
 int rafi_split_set_variant(int32_t variant);
 int rafi_multisplit(const void *items, const int32_t *dest, uint64_t n, uint32_t item_bytes,
                     int32_t n_domains, void *out, uint64_t *offsets, uint64_t *summary,

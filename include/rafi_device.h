@@ -89,4 +89,17 @@ __device__ inline int32_t rafi_tile(const rafi_device_view &v, uint32_t tile, ui
     return lo;
 }
 
+/* Launch helper for domain kernels (not part of the paper's interface).
+ * The GPU deals workgroups to its 8 XCDs round-robin (workgroup b to XCD
+ * b % 8), and each XCD has its own L2. Numbering workgroups with
+ * rafi_xcd_block(blockIdx.x, gridDim.x) instead gives each XCD a contiguous
+ * range of logical workgroups, so the workgroups resident on one XCD read
+ * neighbouring parts of the domain-sorted input queue, and therefore the same
+ * few bricks. It is a bijection on [0, nb) for any nb. */
+__device__ inline uint32_t rafi_xcd_block(uint32_t b, uint32_t nb)
+{
+    const uint32_t per = nb / 8u, rem = nb % 8u, x = b % 8u;
+    return x * per + (x < rem ? x : rem) + b / 8u;
+}
+
 #endif /* RAFI_DEVICE_H */

@@ -63,7 +63,7 @@ raygen_kernel(rafi_device_view view, rafi_ea_job job, uint64_t n_rays)
 __global__ void __launch_bounds__(256)
 march_kernel(rafi_device_view view, rafi_ea_job job, uint32_t n_rays)
 {
-    const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    const uint64_t i = rafi_xcd_block(blockIdx.x, gridDim.x) * (uint64_t)blockDim.x + threadIdx.x;
     if (i >= view.n_in) return;
     const Geo g = job_geo(job);
     const int32_t d = ea::find_domain(view.in_offsets, view.n_domains, i);

@@ -42,7 +42,8 @@ struct SplitPlan {
     uint64_t rows = 0;       // D + 2 (domains, done, bad)
     uint64_t M = 0;          // rows * n_tiles table entries
     uint32_t scan_blocks = 0;
-    uint64_t off_table = 0, off_part = 0, bytes = 0;  // workspace layout
+    uint64_t off_table = 0, off_part = 0, off_dummy = 0, bytes = 0;  // workspace layout
+                                       // (off_dummy: 16 bytes any scatter lane may overwrite)
 };
 
 SplitPlan split_plan(uint64_t n, int32_t D, uint32_t S);

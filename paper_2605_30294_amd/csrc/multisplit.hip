@@ -279,7 +279,7 @@ scatter_kernel(const uint32_t *__restrict__ items, const int32_t *__restrict__ d
 }
 
 // ------------------------------------------------------- pass 3, staged ---
-template <int NW, int R, int W, int OCC>
+template <int NW, int R, int W, int OCC, bool DB>
 __global__ void __launch_bounds__(64 * W, OCC)
 scatter_staged_kernel(const uint32_t *__restrict__ items, const int32_t *__restrict__ dest, uint64_t n,
                       int32_t D, int nbits, uint32_t T, uint32_t n_tiles, const uint32_t *__restrict__ table,
@@ -289,14 +289,14 @@ scatter_staged_kernel(const uint32_t *__restrict__ items, const int32_t *__restr
     const uint64_t tstart = (uint64_t)blockIdx.x * T;
     const uint64_t tend = min(tstart + T, n);
     const uint32_t tile = blockIdx.x;
-    dev::staged_scatter_tile<NW, R, W>(
+    dev::staged_scatter_tile<NW, R, W, DB>(
         items, dest, tstart, tend, D, 0, nbits,
         [&](int32_t e) { return table[(uint64_t)e * n_tiles + tile]; }, out, n, lds);
 }
 
 // One (rounds, waves, workgroups per CU) shape of the staged scatter; it is
 // launched only if its LDS fits that many workgroups per CU.
-template <int NW, int R, int W, int BPC>
+template <int NW, int R, int W, int BPC, bool DB = false>
 bool try_staged(const SplitPlan &p, const uint32_t *items, const int32_t *dest, const uint32_t *table,
                 uint32_t *out, hipStream_t s)
 {
@@ -305,7 +305,7 @@ bool try_staged(const SplitPlan &p, const uint32_t *items, const int32_t *dest, 
     int nbits = 1;
     while ((1 << nbits) < p.D) ++nbits;
     constexpr int OCC = (W * BPC + 3) / 4;  // waves per SIMD
-    hipLaunchKernelGGL((scatter_staged_kernel<NW, R, W, OCC>), dim3(p.n_tiles), dim3(64 * W), lds, s, items, dest,
+    hipLaunchKernelGGL((scatter_staged_kernel<NW, R, W, OCC, DB>), dim3(p.n_tiles), dim3(64 * W), lds, s, items, dest,
                        p.n, p.D, nbits, p.tile, p.n_tiles, table, out);
     return true;
 }
@@ -339,14 +339,67 @@ bool try_gather(const SplitPlan &p, const uint32_t *items, const int32_t *dest, 
     return true;
 }
 
+template <int NW, int R, int W, bool DB>
+__global__ void __launch_bounds__(64 * W, (W + 3) / 4)
+scatter_wide_kernel(const uint32_t *__restrict__ items, const int32_t *__restrict__ dest, uint64_t n,
+                    int32_t D, int nbits, uint32_t T, uint32_t n_tiles, const uint32_t *__restrict__ table,
+                    uint32_t *__restrict__ out, uint32_t *__restrict__ dummy)
+{
+    extern __shared__ __align__(16) uint32_t lds[];
+    const uint64_t tstart = (uint64_t)blockIdx.x * T;
+    const uint64_t tend = min(tstart + T, n);
+    const uint32_t tile = blockIdx.x;
+    dev::wide_scatter_tile<NW, R, W, DB>(
+        items, dest, tstart, tend, D, 0, nbits,
+        [&](int32_t e) { return table[(uint64_t)e * n_tiles + tile]; }, out, n, dummy, lds);
+}
+
+// The wide shape: one workgroup per CU with a chunk as large as LDS allows.
+template <int NW, int R, int W, bool DB>
+bool try_wide(const SplitPlan &p, const uint32_t *items, const int32_t *dest, const uint32_t *table,
+              uint32_t *out, uint32_t *dummy, hipStream_t s)
+{
+    const size_t lds = dev::wide_lds_bytes_c<NW, R, W>(p.D) + 64;
+    if (p.D > dev::kStagedMaxD || lds > dev::kStagedLdsPerCu) return false;
+    int nbits = 1;
+    while ((1 << nbits) < p.D) ++nbits;
+    hipLaunchKernelGGL((scatter_wide_kernel<NW, R, W, DB>), dim3(p.n_tiles), dim3(64 * W), lds, s, items, dest,
+                       p.n, p.D, nbits, p.tile, p.n_tiles, table, out, dummy);
+    return true;
+}
+
 // Process-wide choice among the scatter shapes (0 = automatic).
 int g_split_variant = 0;
 
 template <int NW>
 bool launch_staged(const SplitPlan &p, const uint32_t *items, const int32_t *dest, const uint32_t *table,
-                   uint32_t *out, hipStream_t s)
+                   uint32_t *out, uint32_t *dummy, hipStream_t s)
 {
     const int v = g_split_variant;
+    if (v >= 12) {  // one workgroup per CU, 4096-slot (32-byte) or 6144-slot (16-byte) chunks
+        if constexpr (NW == 8) {
+            if (v == 12) return try_wide<8, 8, 8, false>(p, items, dest, table, out, dummy, s);
+            if (v == 13) return try_wide<8, 8, 8, true>(p, items, dest, table, out, dummy, s);
+        } else if constexpr (NW == 4) {
+            if (v == 12) return try_wide<4, 12, 8, false>(p, items, dest, table, out, dummy, s);
+            if (v == 13) return try_wide<4, 12, 8, true>(p, items, dest, table, out, dummy, s);
+        }
+        return false;
+    }
+    if (v >= 8) {  // shapes 1-4 with double-buffered chunk loads
+        if constexpr (NW == 8) {
+            if (v == 8) return try_staged<8, 7, 4, 2, true>(p, items, dest, table, out, s);
+            if (v == 9) return try_staged<8, 4, 4, 3, true>(p, items, dest, table, out, s);
+            if (v == 10) return try_staged<8, 3, 8, 2, true>(p, items, dest, table, out, s);
+            if (v == 11) return try_staged<8, 2, 4, 4, true>(p, items, dest, table, out, s);
+        } else if constexpr (NW == 4) {
+            if (v == 8) return try_staged<4, 12, 4, 2, true>(p, items, dest, table, out, s);
+            if (v == 9) return try_staged<4, 8, 4, 3, true>(p, items, dest, table, out, s);
+            if (v == 10) return try_staged<4, 5, 8, 2, true>(p, items, dest, table, out, s);
+            if (v == 11) return try_staged<4, 4, 4, 4, true>(p, items, dest, table, out, s);
+        }
+        return false;
+    }
     if (v >= 5) {
         if (v == 5) return try_gather<NW, 16, 4, 4>(p, items, dest, table, out, s);  // 4096-slot chunks
         if (v == 6) return try_gather<NW, 32, 4, 2>(p, items, dest, table, out, s);  // 8192-slot chunks
@@ -376,10 +429,10 @@ bool launch_staged(const SplitPlan &p, const uint32_t *items, const int32_t *des
 
 template <int NW>
 void launch_scatter(const SplitPlan &p, const uint32_t *items, const int32_t *dest,
-                    const uint32_t *table, uint32_t *out, hipStream_t s)
+                    const uint32_t *table, uint32_t *out, uint32_t *dummy, hipStream_t s)
 {
     if constexpr (NW > 0) {
-        if (launch_staged<NW>(p, items, dest, table, out, s)) return;
+        if (launch_staged<NW>(p, items, dest, table, out, dummy, s)) return;
     }
     int nbits = 1;
     while ((1 << nbits) < p.D) ++nbits;
@@ -407,13 +460,14 @@ void finish_plan(SplitPlan &p)
     p.scan_blocks = (uint32_t)((p.M + kScanChunk - 1) / kScanChunk);
     p.off_table = 0;
     p.off_part = (p.M * 4 + 255) / 256 * 256;
-    p.bytes = p.off_part + ((uint64_t)std::max<uint32_t>(p.scan_blocks, 1) * 4 + 255) / 256 * 256;
+    p.off_dummy = p.off_part + ((uint64_t)std::max<uint32_t>(p.scan_blocks, 1) * 4 + 255) / 256 * 256;
+    p.bytes = p.off_dummy + 256;
 }
 }  // namespace
 
 int split_set_variant(int v)
 {
-    if (v < 0 || v > 7) return RAFI_ERR_ARG;
+    if (v < 0 || v > 13) return RAFI_ERR_ARG;
     g_split_variant = v;
     return RAFI_OK;
 }
@@ -453,6 +507,7 @@ int split_run(const SplitPlan &p, const void *items, const int32_t *dest, void *
     if (ev) RAFI_HIP_CHECK(hipEventRecord(ev->begin, s));
     uint32_t *table = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + p.off_table);
     uint32_t *part = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + p.off_part);
+    uint32_t *dummy = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + p.off_dummy);
     if (p.n_tiles > 0) {
         hipLaunchKernelGGL(hist_kernel, dim3(p.n_tiles), dim3(256), sizeof(uint32_t) * p.rows, s,
                            dest, p.n, p.D, p.tile, p.n_tiles, table);
@@ -476,16 +531,16 @@ int split_run(const SplitPlan &p, const void *items, const int32_t *dest, void *
     const uint32_t *it = static_cast<const uint32_t *>(items);
     uint32_t *o = static_cast<uint32_t *>(out);
     switch (p.S / 4) {
-    case 1: launch_scatter<1>(p, it, dest, table, o, s); break;
-    case 2: launch_scatter<2>(p, it, dest, table, o, s); break;
-    case 3: launch_scatter<3>(p, it, dest, table, o, s); break;
-    case 4: launch_scatter<4>(p, it, dest, table, o, s); break;
-    case 6: launch_scatter<6>(p, it, dest, table, o, s); break;
-    case 8: launch_scatter<8>(p, it, dest, table, o, s); break;
-    case 11: launch_scatter<11>(p, it, dest, table, o, s); break;
-    case 12: launch_scatter<12>(p, it, dest, table, o, s); break;
-    case 16: launch_scatter<16>(p, it, dest, table, o, s); break;
-    default: launch_scatter<0>(p, it, dest, table, o, s); break;
+    case 1: launch_scatter<1>(p, it, dest, table, o, dummy, s); break;
+    case 2: launch_scatter<2>(p, it, dest, table, o, dummy, s); break;
+    case 3: launch_scatter<3>(p, it, dest, table, o, dummy, s); break;
+    case 4: launch_scatter<4>(p, it, dest, table, o, dummy, s); break;
+    case 6: launch_scatter<6>(p, it, dest, table, o, dummy, s); break;
+    case 8: launch_scatter<8>(p, it, dest, table, o, dummy, s); break;
+    case 11: launch_scatter<11>(p, it, dest, table, o, dummy, s); break;
+    case 12: launch_scatter<12>(p, it, dest, table, o, dummy, s); break;
+    case 16: launch_scatter<16>(p, it, dest, table, o, dummy, s); break;
+    default: launch_scatter<0>(p, it, dest, table, o, dummy, s); break;
     }
     RAFI_LAUNCH_CHECK();
     if (ev) RAFI_HIP_CHECK(hipEventRecord(ev->end, s));

@@ -106,7 +106,13 @@ inline size_t staged_lds_bytes(int32_t D)
 // Destination of slot i is dest[i] - dbase, valid when in [0, D). run_base(e)
 // gives the output slot of the tile's first item bound for e. Output slots
 // >= out_cap are never written (they cannot occur for a consistent table).
-template <int NW, int R, int W, typename RunBase>
+//
+// DB = false: one register buffer; the next chunk's loads are issued after
+// the place phase and overlap the write phase only.
+// DB = true: two register buffers; the next chunk's loads are issued before
+// the current chunk is ranked, so they overlap all of its phases (the shape
+// needs 2 x R x NW item registers per lane).
+template <int NW, int R, int W, bool DB = false, typename RunBase>
 __device__ inline void staged_scatter_tile(const uint32_t *__restrict__ items, const int32_t *__restrict__ dest,
                                            uint64_t tstart, uint64_t tend, int32_t D, int32_t dbase, int nbits,
                                            RunBase run_base, uint32_t *__restrict__ out, uint64_t out_cap,
@@ -129,10 +135,9 @@ __device__ inline void staged_scatter_tile(const uint32_t *__restrict__ items, c
 
     for (int32_t e = tid; e < D; e += NT) run[e] = run_base(e);
 
-    uint32_t item[R][NW];
-    int32_t dd[R];
-    uint16_t rank[R];
-    auto load_chunk = [&](uint64_t cbase) {
+    typedef uint32_t Items[R][NW];
+    typedef int32_t Dests[R];
+    auto load_chunk = [&](Items &item, Dests &dd, uint64_t cbase) {
         const uint64_t qbase = cbase + (uint64_t)w * SEG;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -154,9 +159,10 @@ __device__ inline void staged_scatter_tile(const uint32_t *__restrict__ items, c
             }
         }
     };
-    if (tstart < tend) load_chunk(tstart);
 
-    for (uint64_t cbase = tstart; cbase < tend; cbase += CH) {
+    // One chunk; `after_place` runs once the chunk's registers are free.
+    auto process = [&](Items &item, Dests &dd, auto after_place) {
+        uint16_t rank[R];
         for (int k = tid; k < (W * D + 1) / 2; k += NT) reinterpret_cast<uint32_t *>(cnt)[k] = 0;
         __syncthreads();
 
@@ -230,9 +236,7 @@ __device__ inline void staged_scatter_tile(const uint32_t *__restrict__ items, c
         }
         __syncthreads();
 
-        // the registers are free again: start loading the next chunk so its
-        // latency overlaps the write phase
-        if (cbase + CH < tend) load_chunk(cbase + CH);
+        after_place();
 
         // advance the per-destination output slots past this chunk
 #pragma unroll
@@ -258,6 +262,205 @@ __device__ inline void staged_scatter_tile(const uint32_t *__restrict__ items, c
             }
         }
         __syncthreads();
+    };
+
+    Items itemA;
+    Dests ddA;
+    if (tstart < tend) load_chunk(itemA, ddA, tstart);
+    if constexpr (!DB) {
+        for (uint64_t cbase = tstart; cbase < tend; cbase += CH)
+            process(itemA, ddA, [&] {
+                // the registers are free again: start loading the next chunk so
+                // its latency overlaps the write phase
+                if (cbase + CH < tend) load_chunk(itemA, ddA, cbase + CH);
+            });
+    } else {
+        Items itemB;
+        Dests ddB;
+        for (uint64_t cbase = tstart; cbase < tend; cbase += 2 * CH) {
+            const uint64_t c1 = cbase + CH;
+            if (c1 < tend) load_chunk(itemB, ddB, c1);
+            process(itemA, ddA, [] {});
+            if (c1 >= tend) break;
+            if (c1 + CH < tend) load_chunk(itemA, ddA, c1 + CH);
+            process(itemB, ddB, [] {});
+        }
+    }
+}
+
+// ------------------------------------------------- wide staged scatter ---
+// One workgroup per CU stages a chunk of CH = W x R x 64 slots (4096 for
+// 32-byte items), so that a destination's run in a chunk averages CH / D
+// items: 128 bytes at 1024 destinations. The output slot of chunk-sorted
+// slot j bound for e is rb[e] + j, so LDS holds only the items, the per-wave
+// counters, rb[D] and a 16-bit destination per sorted slot; each thread keeps
+// the output cursors of the destinations it scans in registers.
+// Every global load and store is issued unconditionally (reads past the tile
+// are clamped to its last slot, surplus store lanes repeat the last piece of
+// the chunk or write the 16-byte dummy), so the compiler can count
+// outstanding memory operations exactly and waits for a chunk's loads never
+// wait for the previous chunk's stores.
+// DB = true issues the next chunk's loads before the current chunk is ranked.
+template <int NW, int R, int W>
+constexpr size_t wide_lds_bytes_c(int32_t D)
+{
+    constexpr int CH = W * 64 * R;
+    return sizeof(uint32_t) * ((size_t)CH * NW + D) + sizeof(uint16_t) * ((size_t)W * D + 1 + CH);
+}
+
+template <int NW, int R, int W, bool DB, typename RunBase>
+__device__ inline void wide_scatter_tile(const uint32_t *__restrict__ items, const int32_t *__restrict__ dest,
+                                         uint64_t tstart, uint64_t tend, int32_t D, int32_t dbase, int nbits,
+                                         RunBase run_base, uint32_t *__restrict__ out, uint64_t out_cap,
+                                         uint32_t *__restrict__ dummy, uint32_t *lds)
+{
+    constexpr int NT = 64 * W, SEG = 64 * R, CH = W * SEG;
+    static_assert(NW % 4 == 0, "16-byte pieces");
+    static_assert(CH <= 65536, "chunk-local indices are 16-bit");
+    constexpr int PPI = NW / 4;                          // 16-byte pieces per item
+    constexpr int NPT = CH * PPI / NT;                   // store pieces per thread per chunk
+    constexpr int EPT = (kStagedMaxD + NT - 1) / NT;     // max destinations per thread
+    uint32_t *stage = lds;                               // [CH * NW]
+    uint32_t *rb = stage + CH * NW;                      // [D]
+    uint16_t *cnt = reinterpret_cast<uint16_t *>(rb + D);  // [W * D (+1)]
+    uint16_t *sdst = cnt + W * D + 1;                    // [CH] destination of sorted slot j
+    __shared__ uint32_t scan_lds[NT / 64 + 1];
+
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const int per = (D + NT - 1) / NT;
+    const int e0 = tid * per;
+
+    uint32_t cursor[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) cursor[k] = (k < per && e0 + k < D) ? run_base(e0 + k) : 0u;
+
+    typedef uint32_t Items[R][NW];
+    typedef int32_t Dests[R];
+    auto load_chunk = [&](Items &item, Dests &dd, uint64_t cbase) {
+        const uint64_t qbase = cbase + (uint64_t)w * SEG;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t i = qbase + 64 * r + lane;
+            const uint64_t ic = i < tend ? i : tend - 1;
+            const int32_t x = __builtin_nontemporal_load(dest + ic);
+            dd[r] = i < tend ? x - dbase : -1;
+            const uint32_t *src = items + ic * NW;
+#pragma unroll
+            for (int k = 0; k < NW / 4; ++k) {
+                const uint4 q = load_nt4(src + 4 * k);
+                item[r][4 * k] = q.x; item[r][4 * k + 1] = q.y;
+                item[r][4 * k + 2] = q.z; item[r][4 * k + 3] = q.w;
+            }
+        }
+        // keep these loads ahead of the memory operations that follow
+        __asm__ __volatile__("" ::: "memory");
+    };
+
+    auto process = [&](Items &item, Dests &dd, auto after_place) {
+        uint16_t rank[R];
+        for (int k = tid; k < (W * D + 1) / 2; k += NT) reinterpret_cast<uint32_t *>(cnt)[k] = 0;
+        __syncthreads();
+
+        uint16_t *mycnt = cnt + w * D;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int32_t d = dd[r];
+            const bool ok = d >= 0 && d < D;
+            const uint64_t peers = match_peers((uint32_t)d, ok, nbits);
+            uint16_t before = 0;
+            if (ok) before = mycnt[d];
+            __builtin_amdgcn_wave_barrier();
+            rank[r] = (uint16_t)(before + __popcll(peers & lt));
+            if (ok && (peers & lt) == 0ull) mycnt[d] = (uint16_t)(before + __popcll(peers));
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+
+        uint32_t tot_e[EPT];
+        uint32_t local = 0;
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int32_t e = e0 + k;
+            uint32_t t = 0;
+            if (k < per && e < D)
+#pragma unroll
+                for (int ww = 0; ww < W; ++ww) t += cnt[ww * D + e];
+            tot_e[k] = t;
+            local += t;
+        }
+        uint32_t chunk_total;
+        uint32_t base = block_excl_scan<NT>(local, scan_lds, &chunk_total);
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int32_t e = e0 + k;
+            if (k < per && e < D) {
+                rb[e] = cursor[k] - base;  // output slot = rb[e] + chunk-sorted index
+                cursor[k] += tot_e[k];
+                uint32_t b = base;
+#pragma unroll
+                for (int ww = 0; ww < W; ++ww) {
+                    const uint32_t c = cnt[ww * D + e];
+                    cnt[ww * D + e] = (uint16_t)b;
+                    b += c;
+                }
+            }
+            base += tot_e[k];
+        }
+        __syncthreads();
+
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int32_t d = dd[r];
+            if (d >= 0 && d < D) {
+                const uint32_t pos = (uint32_t)cnt[w * D + d] + rank[r];
+                uint32_t *dst = stage + pos * NW;
+#pragma unroll
+                for (int k = 0; k < NW / 4; ++k)
+                    reinterpret_cast<uint4 *>(dst)[k] =
+                        make_uint4(item[r][4 * k], item[r][4 * k + 1], item[r][4 * k + 2], item[r][4 * k + 3]);
+                sdst[pos] = (uint16_t)d;
+            }
+        }
+        __syncthreads();
+
+        after_place();
+
+        // write: NPT pieces per thread, all issued
+        const uint32_t n_pieces = chunk_total * PPI;
+#pragma unroll
+        for (int u = 0; u < NPT; ++u) {
+            const uint32_t q = (uint32_t)(u * NT + tid);
+            const uint32_t qq = q < n_pieces ? q : (n_pieces ? n_pieces - 1 : 0);
+            const uint32_t j = qq / PPI, part = qq - j * PPI;
+            // sdst[0] may be stale when the chunk is empty; keep the LDS index
+            // in range (the store then goes to the dummy)
+            const uint32_t e = min((uint32_t)sdst[j], (uint32_t)(D - 1));
+            const uint32_t g = rb[e] + j;
+            const uint4 v = *reinterpret_cast<const uint4 *>(stage + j * NW + part * 4);
+            uint32_t *dst = (n_pieces && g < out_cap) ? out + (uint64_t)g * NW + part * 4 : dummy;
+            *reinterpret_cast<uint4 *>(dst) = v;
+        }
+        __syncthreads();
+    };
+
+    Items itemA;
+    Dests ddA;
+    if (tstart >= tend) return;
+    load_chunk(itemA, ddA, tstart);
+    if constexpr (!DB) {
+        for (uint64_t cbase = tstart; cbase < tend; cbase += CH)
+            process(itemA, ddA, [&] { load_chunk(itemA, ddA, cbase + CH); });
+    } else {
+        Items itemB;
+        Dests ddB;
+        for (uint64_t cbase = tstart; cbase < tend; cbase += 2 * CH) {
+            load_chunk(itemB, ddB, cbase + CH);
+            process(itemA, ddA, [] {});
+            if (cbase + CH >= tend) break;
+            load_chunk(itemA, ddA, cbase + 2 * CH);
+            process(itemB, ddB, [] {});
+        }
     }
 }
 

@@ -157,7 +157,7 @@ __device__ inline void count_forwards(unsigned long long *counters, bool cross, 
 __global__ void __launch_bounds__(256)
 advance_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids)
 {
-    const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    const uint64_t i = rafi_xcd_block(blockIdx.x, gridDim.x) * (uint64_t)blockDim.x + threadIdx.x;
     if (i >= view.n_in) return;
     const Geo g = make_geo(job);
     const int32_t d = find_domain(view.in_offsets, view.n_domains, i);
