@@ -63,9 +63,9 @@ def streamline_job(args, dev):
     from paper_2605_30294_amd import workloads as W
 
     n, grid, N, h, max_steps = 256, (4, 4, 4), 1 << 20, 0.25, 2000
-    field = W.abc_field(n, device=dev)
-    f4 = rafi.sl_pack(field)
-    del field
+    field = W.abc_field(n, device=dev)          # [n, n, n, 3]: the unpadded layout
+    f4 = rafi.sl_pack(field)                    # [n, n, n, 4]: the padded layout
+    layouts = {"padded": f4, "unpadded": field}
     seeds_np = W.streamline_seeds(N, n)
     seeds = torch.from_numpy(seeds_np).to(dev)
     ctx = rafi.Context(64, rafi.SL_ITEM_BYTES, N)
@@ -81,6 +81,25 @@ def streamline_job(args, dev):
         tuned, _, sweep = autotune.tune_streamlines(ctx, job, seeds)
         log("streamline schedule sweep (ms, (steps_per_visit, tail_items, refill_lanes)): "
             + ", ".join(f"{m:.2f} {t}" for m, t in sweep))
+    # field layout: the same values with 16 or 12 bytes per voxel; keep the faster
+    layout_ms = {}
+    for name, f in layouts.items():
+        lj = rafi.sl_job(f, grid, endpoint, steps, reason, h, max_steps, job.steps_per_visit, counters,
+                         job.tail_items, job.refill_lanes)
+        rafi.sl_trace_job(ctx, lj, seeds)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(2):
+            rafi.sl_trace_job(ctx, lj, seeds)
+        b.record()
+        torch.cuda.synchronize()
+        layout_ms[name] = a.elapsed_time(b) / 2
+    layout = min(layout_ms, key=layout_ms.get)
+    log("streamline field layout (ms): " + ", ".join(f"{k} {v:.2f}" for k, v in layout_ms.items()))
+    job = rafi.sl_job(layouts[layout], grid, endpoint, steps, reason, h, max_steps, job.steps_per_visit, counters,
+                      job.tail_items, job.refill_lanes)
     for _ in range(args.warmup):
         rafi.sl_trace_job(ctx, job, seeds)
     torch.cuda.synchronize()
@@ -110,7 +129,7 @@ def streamline_job(args, dev):
     flops_per_launch = rk4_steps * RK4_FLOPS_PER_STEP / max(launches, 1)
     achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
     out = dict(ms=ms, rounds=rounds, forwarded=N + cross, step_items=fwd, self_fwd=self_fwd, rk4_steps=rk4_steps,
-               schedule=(job.steps_per_visit, job.tail_items, job.refill_lanes),
+               schedule=(job.steps_per_visit, job.tail_items, job.refill_lanes), field_layout=layout,
                domain_ms=dom_ms, split_ms=split_ms,
                launches=launches, avg_launch_ms=avg_launch_ms,
                roofline={"kernel": ("advance_persistent_kernel" if job.refill_lanes else "advance_kernel")
@@ -452,7 +471,7 @@ def main():
         "rounds": sl["rounds"], "forwarded_per_step": sl["forwarded"],
         "forward_step_items_per_step": sl["step_items"], "same_brick_forwards_per_step": sl["self_fwd"],
         "schedule": {"steps_per_visit": sl["schedule"][0], "tail_items": sl["schedule"][1],
-                     "refill_lanes": sl["schedule"][2]},
+                     "refill_lanes": sl["schedule"][2], "field_layout": sl["field_layout"]},
         "time_split": {"domain_kernels_ms": round(sl["domain_ms"], 4), "forward_steps_ms": round(sl["split_ms"], 4)},
         "roofline": sl["roofline"],
         "cpu_baseline": cpu,

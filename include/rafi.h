@@ -341,7 +341,8 @@ int rafi_batch_render(rafi_batch *b, const float *volumes, float *image, int32_t
  * forwarded when it crosses into another brick.
  * ------------------------------------------------------------------------ */
 typedef struct rafi_sl_job {
-    const float *field4;   /* device [n^3 * 4] packed field from rafi_sl_pack */
+    const float *field4;   /* device field: [n^3 * 4] from rafi_sl_pack (field_stride 0 or 4),
+                              or the [n^3 * 3] field itself (field_stride 3) */
     float *endpoint;       /* device [n_seeds * 3] final position per particle id */
     int32_t *steps;        /* device [n_seeds] steps taken */
     int32_t *reason;       /* device [n_seeds] 1 stagnant, 2 exited, 3 max steps; optional */
@@ -362,6 +363,10 @@ typedef struct rafi_sl_job {
                                 this many of its 64 lanes are idle (lanes stay busy while
                                 their neighbours cross the brick). Results do not depend on
                                 it. Outside 0..64: RAFI_ERR_ARG. */
+    int32_t field_stride;    /* floats per voxel of field4: 0 or 4 = the padded layout of
+                                rafi_sl_pack (16-byte loads), 3 = the unpadded field (12-byte
+                                loads, 3/4 of the bytes). Same results either way; other
+                                values: RAFI_ERR_ARG. */
 } rafi_sl_job;
 
 /* Item: position (3 x float32) and particle id; the step count lives in

@@ -97,7 +97,7 @@ march_lds_kernel(rafi_device_view view, rafi_ea_job job, uint32_t n_rays)
 {
     extern __shared__ float vl[];
     uint64_t tb, te;
-    const int32_t d = rafi_tile(view, blockIdx.x, &tb, &te);
+    const int32_t d = rafi_tile(view, rafi_xcd_block(blockIdx.x, gridDim.x), &tb, &te);
     const Geo g = job_geo(job);
     const Box box = ea::box_of(d, g);
     const ea::Region reg = ea::region_of(box, g);
@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(256)
 bwd_march_kernel(rafi_device_view view, rafi_ea_job job, const float *__restrict__ grad_image,
                  float *__restrict__ grad, uint32_t n_rays)
 {
-    const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    const uint64_t i = rafi_xcd_block(blockIdx.x, gridDim.x) * (uint64_t)blockDim.x + threadIdx.x;
     if (i >= view.n_in) return;
     const Geo g = job_geo(job);
     const int32_t d = ea::find_domain(view.in_offsets, view.n_domains, i);
@@ -233,7 +233,7 @@ bwd_march_lds_kernel(rafi_device_view view, rafi_ea_job job, const float *__rest
 {
     extern __shared__ float gl[];
     uint64_t tb, te;
-    const int32_t d = rafi_tile(view, blockIdx.x, &tb, &te);
+    const int32_t d = rafi_tile(view, rafi_xcd_block(blockIdx.x, gridDim.x), &tb, &te);
     const Geo g = job_geo(job);
     const Box box = ea::box_of(d, g);
     const int32_t ox = (int32_t)box.lo0 - 1, oy = (int32_t)box.lo1 - 1, oz = (int32_t)box.lo2 - 1;

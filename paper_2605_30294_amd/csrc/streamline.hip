@@ -23,16 +23,34 @@ static_assert(sizeof(SLItem) == RAFI_SL_ITEM_BYTES, "item layout");
 
 __device__ inline float lerpf(float a, float b, float t) { return __fmaf_rn(t, b - a, a); }
 
+// Velocity of one voxel as stored: FW = 4 floats per voxel (the padded layout
+// written by rafi_sl_pack, 16-byte loads) or FW = 3 (the caller's n^3 x 3
+// field as is; 25% fewer bytes per voxel, 12-byte loads).
+struct V3 {
+    float x, y, z;
+};
+template <int FW> struct Voxel;
+template <> struct Voxel<4> { typedef float4 type; };
+template <> struct Voxel<3> { typedef V3 type; };
+
+template <int FW>
+__device__ inline V3 load_voxel(const typename Voxel<FW>::type *__restrict__ f, int32_t i)
+{
+    const typename Voxel<FW>::type v = f[i];
+    return V3{v.x, v.y, v.z};
+}
+
 // The 8 voxels around the last sample point, kept in registers: consecutive
 // RK4 stages and steps usually fall in the same cell (a step moves a particle
 // by a fraction of a voxel), and then no memory is touched. Reuse is exact.
 struct CellCache {
     int32_t base = -1;  // linear index of corner (i0, j0, k0), -1 = empty
-    float4 c[8];
+    V3 c[8];
 };
 
-__device__ inline void field_at(const float4 *__restrict__ f, int32_t n, CellCache &cc, float qx, float qy,
-                                float qz, float &vx, float &vy, float &vz)
+template <int FW>
+__device__ inline void field_at(const typename Voxel<FW>::type *__restrict__ f, int32_t n, CellCache &cc, float qx,
+                                float qy, float qz, float &vx, float &vy, float &vz)
 {
     const float hi = (float)(n - 1);
     float u[3] = {qx - 0.5f, qy - 0.5f, qz - 0.5f};
@@ -48,18 +66,18 @@ __device__ inline void field_at(const float4 *__restrict__ f, int32_t n, CellCac
     const int32_t sy = n, sz = n * n;  // n^3 < 2^31 (checked by the entry points)
     const int32_t base = i0[0] + sy * i0[1] + sz * i0[2];
     if (base != cc.base) {
-        const float4 *b = f + base;
-        cc.c[0] = b[0];
-        cc.c[1] = b[1];
-        cc.c[2] = b[sy];
-        cc.c[3] = b[sy + 1];
-        cc.c[4] = b[sz];
-        cc.c[5] = b[sz + 1];
-        cc.c[6] = b[sz + sy];
-        cc.c[7] = b[sz + sy + 1];
+        const typename Voxel<FW>::type *b = f + base;
+        cc.c[0] = load_voxel<FW>(b, 0);
+        cc.c[1] = load_voxel<FW>(b, 1);
+        cc.c[2] = load_voxel<FW>(b, sy);
+        cc.c[3] = load_voxel<FW>(b, sy + 1);
+        cc.c[4] = load_voxel<FW>(b, sz);
+        cc.c[5] = load_voxel<FW>(b, sz + 1);
+        cc.c[6] = load_voxel<FW>(b, sz + sy);
+        cc.c[7] = load_voxel<FW>(b, sz + sy + 1);
         cc.base = base;
     }
-    const float4 *c = cc.c;
+    const V3 *c = cc.c;
 #define TRI(comp)                                                                                   \
     lerpf(lerpf(lerpf(c[0].comp, c[1].comp, w[0]), lerpf(c[2].comp, c[3].comp, w[0]), w[1]),        \
           lerpf(lerpf(c[4].comp, c[5].comp, w[0]), lerpf(c[6].comp, c[7].comp, w[0]), w[1]), w[2])
@@ -70,14 +88,15 @@ __device__ inline void field_at(const float4 *__restrict__ f, int32_t n, CellCac
 }
 
 // One classical RK4 step from (x, y, z), with the operation order fixed above.
-__device__ inline void rk4_step(const float4 *__restrict__ F, int32_t n, CellCache &cc, float h, float hh, float h6,
-                                float x, float y, float z, float &nx, float &ny, float &nz)
+template <int FW>
+__device__ inline void rk4_step(const typename Voxel<FW>::type *__restrict__ F, int32_t n, CellCache &cc, float h,
+                                float hh, float h6, float x, float y, float z, float &nx, float &ny, float &nz)
 {
     float k1x, k1y, k1z, k2x, k2y, k2z, k3x, k3y, k3z, k4x, k4y, k4z;
-    field_at(F, n, cc, x, y, z, k1x, k1y, k1z);
-    field_at(F, n, cc, __fmaf_rn(hh, k1x, x), __fmaf_rn(hh, k1y, y), __fmaf_rn(hh, k1z, z), k2x, k2y, k2z);
-    field_at(F, n, cc, __fmaf_rn(hh, k2x, x), __fmaf_rn(hh, k2y, y), __fmaf_rn(hh, k2z, z), k3x, k3y, k3z);
-    field_at(F, n, cc, __fmaf_rn(h, k3x, x), __fmaf_rn(h, k3y, y), __fmaf_rn(h, k3z, z), k4x, k4y, k4z);
+    field_at<FW>(F, n, cc, x, y, z, k1x, k1y, k1z);
+    field_at<FW>(F, n, cc, __fmaf_rn(hh, k1x, x), __fmaf_rn(hh, k1y, y), __fmaf_rn(hh, k1z, z), k2x, k2y, k2z);
+    field_at<FW>(F, n, cc, __fmaf_rn(hh, k2x, x), __fmaf_rn(hh, k2y, y), __fmaf_rn(hh, k2z, z), k3x, k3y, k3z);
+    field_at<FW>(F, n, cc, __fmaf_rn(h, k3x, x), __fmaf_rn(h, k3y, y), __fmaf_rn(h, k3z, z), k4x, k4y, k4z);
     const float sx = __fmaf_rn(2.0f, k3x, __fmaf_rn(2.0f, k2x, k1x)) + k4x;
     const float sy = __fmaf_rn(2.0f, k3y, __fmaf_rn(2.0f, k2y, k1y)) + k4y;
     const float sz = __fmaf_rn(2.0f, k3z, __fmaf_rn(2.0f, k2z, k1z)) + k4z;
@@ -154,6 +173,7 @@ __device__ inline void count_forwards(unsigned long long *counters, bool cross, 
     }
 }
 
+template <int FW>
 __global__ void __launch_bounds__(256)
 advance_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids)
 {
@@ -165,7 +185,7 @@ advance_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids)
     const float lo0 = (float)(bx * g.b0), hi0 = (float)((bx + 1) * g.b0);
     const float lo1 = (float)(by * g.b1), hi1 = (float)((by + 1) * g.b1);
     const float lo2 = (float)(bz * g.b2), hi2 = (float)((bz + 1) * g.b2);
-    const float4 *__restrict__ F = reinterpret_cast<const float4 *>(job.field4);
+    const typename Voxel<FW>::type *__restrict__ F = reinterpret_cast<const typename Voxel<FW>::type *>(job.field4);
 
     SLItem it = static_cast<const SLItem *>(view.in_items)[i];
     if ((uint64_t)(uint32_t)it.id >= n_ids) {  // never true for items this library emitted
@@ -181,7 +201,7 @@ advance_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids)
     CellCache cc;
     for (int32_t taken = 0;;) {
         float nx, ny, nz;
-        rk4_step(F, g.n, cc, h, hh, h6, x, y, z, nx, ny, nz);
+        rk4_step<FW>(F, g.n, cc, h, hh, h6, x, y, z, nx, ny, nz);
         ++steps;
         ++taken;
         const bool same = __float_as_uint(nx) == __float_as_uint(x) && __float_as_uint(ny) == __float_as_uint(y) &&
@@ -222,12 +242,13 @@ constexpr int kSLThreads = 256;
 // changes. Every wave exits once the queue is handed out and its lanes are
 // idle; each particle needs at most max_steps steps, so every wave ends.
 // The last wave to exit (work[1] reaching n_waves - 1) resets both counters.
+template <int FW>
 __global__ void __launch_bounds__(kSLThreads)
 advance_persistent_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids, unsigned long long *work,
                           uint32_t n_waves)
 {
     const Geo g = make_geo(job);
-    const float4 *__restrict__ F = reinterpret_cast<const float4 *>(job.field4);
+    const typename Voxel<FW>::type *__restrict__ F = reinterpret_cast<const typename Voxel<FW>::type *>(job.field4);
     const uint64_t n = view.n_in;
     const int lane = threadIdx.x & 63;
     const uint64_t lanes_below = (1ull << lane) - 1;
@@ -281,7 +302,7 @@ advance_persistent_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids
         }
         if (has) {
             float nx, ny, nz;
-            rk4_step(F, g.n, cc, h, hh, h6, it.x, it.y, it.z, nx, ny, nz);
+            rk4_step<FW>(F, g.n, cc, h, hh, h6, it.x, it.y, it.z, nx, ny, nz);
             ++steps;
             ++taken;
             const bool same = __float_as_uint(nx) == __float_as_uint(it.x) &&
@@ -347,7 +368,7 @@ uint32_t persistent_blocks()
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (dev != cached_dev) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, advance_persistent_kernel, kSLThreads, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, advance_persistent_kernel<4>, kSLThreads, 0) !=
                 hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             return 0;
@@ -362,6 +383,7 @@ bool job_ok(const rafi_ctx *c, const rafi_sl_job *j)
     if (!c || !j || !j->field4 || !j->endpoint || !j->steps) return false;
     if (j->n < 2 || j->n > 1290 || j->max_steps < 1 || !(j->h > 0.0f) || j->steps_per_visit < 0) return false;
     if (j->refill_lanes < 0 || j->refill_lanes > 64) return false;
+    if (j->field_stride != 0 && j->field_stride != 3 && j->field_stride != 4) return false;
     for (int a = 0; a < 3; ++a)
         if (j->grid[a] < 1 || j->n % j->grid[a] != 0) return false;
     return c->D == j->grid[0] * j->grid[1] * j->grid[2] && c->S == RAFI_SL_ITEM_BYTES;
@@ -410,11 +432,19 @@ int rafi_sl_advance(rafi_ctx *c, const rafi_sl_job *job)
     const int ph = prof_domain_begin(c);
     if (v.n_in && job->refill_lanes > 0) {
         const uint32_t blocks = (uint32_t)std::min<uint64_t>(one_per_item, resident);
-        hipLaunchKernelGGL(advance_persistent_kernel, dim3(blocks), dim3(kSLThreads), 0, c->stream, v, *job,
-                           c->wave_slots, c->work, blocks * (kSLThreads / 64));
+        if (job->field_stride == 3)
+            hipLaunchKernelGGL(advance_persistent_kernel<3>, dim3(blocks), dim3(kSLThreads), 0, c->stream, v, *job,
+                               c->wave_slots, c->work, blocks * (kSLThreads / 64));
+        else
+            hipLaunchKernelGGL(advance_persistent_kernel<4>, dim3(blocks), dim3(kSLThreads), 0, c->stream, v, *job,
+                               c->wave_slots, c->work, blocks * (kSLThreads / 64));
     } else if (v.n_in) {
-        hipLaunchKernelGGL(advance_kernel, dim3((uint32_t)one_per_item), dim3(kSLThreads), 0, c->stream, v, *job,
-                           c->wave_slots);
+        if (job->field_stride == 3)
+            hipLaunchKernelGGL(advance_kernel<3>, dim3((uint32_t)one_per_item), dim3(kSLThreads), 0, c->stream, v,
+                               *job, c->wave_slots);
+        else
+            hipLaunchKernelGGL(advance_kernel<4>, dim3((uint32_t)one_per_item), dim3(kSLThreads), 0, c->stream, v,
+                               *job, c->wave_slots);
     }
     prof_domain_end(c, ph);
     RAFI_LAUNCH_CHECK();

@@ -66,7 +66,7 @@ class SLJob(C.Structure):
     _fields_ = [("field4", C.c_void_p), ("endpoint", C.c_void_p), ("steps", C.c_void_p), ("reason", C.c_void_p),
                 ("counters", C.c_void_p), ("n", C.c_int32), ("grid", C.c_int32 * 3), ("h", C.c_float),
                 ("max_steps", C.c_int32), ("steps_per_visit", C.c_int32), ("tail_items", C.c_uint32),
-                ("refill_lanes", C.c_int32)]
+                ("refill_lanes", C.c_int32), ("field_stride", C.c_int32)]
 
 
 class ViewRec(C.Structure):
@@ -348,10 +348,15 @@ def sl_pack(field: torch.Tensor) -> torch.Tensor:
 
 def sl_job(field4: torch.Tensor, grid, endpoint, steps, reason=None, h=0.25, max_steps=2000,
            steps_per_visit=0, counters=None, tail_items=0, refill_lanes=0) -> SLJob:
-    """counters: optional int64 device tensor [2] (cross-brick forwards, same-brick forwards)."""
+    """field4: the packed [n, n, n, 4] field of sl_pack, or the [n, n, n, 3] field
+    itself (read unpadded). counters: optional int64 device tensor [2]
+    (cross-brick forwards, same-brick forwards)."""
+    stride = int(field4.shape[-1])
+    if field4.dim() != 4 or stride not in (3, 4) or not field4.is_contiguous():
+        raise ValueError("field must be a contiguous [n, n, n, 3] or [n, n, n, 4] tensor")
     return SLJob(_dptr(field4), _dptr(endpoint), _dptr(steps), _dptr(reason), _dptr(counters), field4.shape[0],
                  (C.c_int32 * 3)(*[int(g) for g in grid]), float(h), int(max_steps), int(steps_per_visit),
-                 int(tail_items), int(refill_lanes))
+                 int(tail_items), int(refill_lanes), stride)
 
 
 def sl_seed(ctx: Context, job: SLJob, seeds: torch.Tensor):

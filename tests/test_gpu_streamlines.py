@@ -14,10 +14,12 @@ from paper_2605_30294_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def _stepwise(field, grid, seeds, h=0.25, max_steps=2000, steps_per_visit=0, refill_lanes=0):
+def _stepwise(field, grid, seeds, h=0.25, max_steps=2000, steps_per_visit=0, refill_lanes=0, packed=True):
     dev = device()
     N = len(seeds)
-    f4 = rafi.sl_pack(torch.from_numpy(np.ascontiguousarray(field)).to(dev))
+    f4 = torch.from_numpy(np.ascontiguousarray(field)).to(dev)
+    if packed:
+        f4 = rafi.sl_pack(f4)
     ctx = rafi.Context(int(np.prod(grid)), rafi.SL_ITEM_BYTES, N, debug=True)
     ep = torch.zeros((N, 3), dtype=torch.float32, device=dev)
     st = torch.zeros(N, dtype=torch.int32, device=dev)
@@ -79,6 +81,19 @@ def test_steps_per_visit_cap(orc, cap, refill):
     assert np.array_equal(g["endpoint"], u["endpoint"]) and np.array_equal(g["steps"], u["steps"])
 
 
+@pytest.mark.parametrize("refill", [0, 16])
+def test_unpadded_field_layout(orc, refill):
+    """The n^3 x 3 field read as is (12-byte voxels) gives the same routing and
+    results as the padded layout."""
+    n, grid, N = 64, (4, 2, 2), 3000
+    field = W.abc_field(n)
+    seeds = W.streamline_seeds(N, n, seed=77)
+    announce(f"sl unpadded field refill={refill}")
+    g = _stepwise(field, grid, seeds, max_steps=900, refill_lanes=refill, packed=False)
+    o = orc.streamlines(field, grid, seeds, max_steps=900, queue_cap=1 << 24)
+    _compare(g, o)
+
+
 def test_constant_field_exact(orc):
     n = 256
     field = W.constant_field(n, (0.5, 0.0, 0.0))
@@ -121,6 +136,11 @@ def test_full_cfg1_sampled(orc):
         assert torch.equal(r["reason"], r4["reason"])
         assert int(r4["counters"][0]) == int(r["counters"][0])
         assert r4["forwarded"] == N + int(r4["counters"].sum())
+    # the unpadded field layout: same particles
+    r5 = rafi.sl_trace(torch.from_numpy(field).to(dev), (4, 4, 4), torch.from_numpy(seeds).to(dev),
+                       steps_per_visit=128)
+    assert torch.equal(r["endpoint"], r5["endpoint"]) and torch.equal(r["steps"], r5["steps"])
+    assert torch.equal(r["reason"], r5["reason"])
     ids = np.sort(np.random.default_rng(2).choice(N, 4096, replace=False))
     o = orc.streamlines_brute(field, (4, 4, 4), seeds[ids])
     assert np.array_equal(ep[ids].view(np.uint32), o["endpoint"].view(np.uint32))
