@@ -84,6 +84,7 @@ typedef struct rafi_device_view {
     int32_t n_domains;
     uint32_t tile_items;
     uint32_t n_tiles;                 /* host copy of in_tile_offsets[n_domains] */
+    unsigned long long *append;       /* device counter of slots taken by rafi_emit (append mode) */
 } rafi_device_view;
 
 typedef struct rafi_stats {
@@ -131,6 +132,25 @@ int rafi_view(const rafi_ctx *ctx, rafi_device_view *out);
  * slots (n_slots <= capacity) for a generator kernel (ray generation /
  * seeding) that emits into slots [0, n_slots). */
 int rafi_begin(rafi_ctx *ctx, uint64_t n_slots);
+
+/* Output modes of rafi_open. */
+#define RAFI_SLOTS_ORDERED 0
+#define RAFI_SLOTS_APPEND 1
+
+/* Reopen the output slots of the current round before a domain kernel runs,
+ * leaving the input queue as it is (rafi_begin and rafi_round open
+ * slot-ordered output with n_slots = the number of work units / input items).
+ *   RAFI_SLOTS_ORDERED: the thread handling work unit i writes slot i with
+ *     rafi_forward / rafi_done (fan-out k: unit i owns slots k*i .. k*i+k-1).
+ *   RAFI_SLOTS_APPEND: the paper's append queue (Sec. 3.2-3.3): every slot
+ *     starts as RAFI_DONE, the append counter starts at 0, and rafi_emit takes
+ *     the next free slot; any number of emits per thread. Emits beyond
+ *     n_slots are dropped and counted (rafi_round then returns
+ *     RAFI_ERR_OVERFLOW). The order of items within a destination depends on
+ *     the order in which waves reach their emits; the multiset does not.
+ * n_slots <= capacity, else RAFI_ERR_ARG; other modes: RAFI_ERR_ARG.
+ * Stream-ordered (one small fill kernel; no host synchronisation). */
+int rafi_open(rafi_ctx *ctx, uint64_t n_slots, int32_t mode);
 
 /* Bulk emission from device arrays: copy items [n * item_bytes] and dest [n]
  * (both device) into output slots [0, n) (n <= n_slots), as a generator
@@ -243,6 +263,14 @@ typedef struct rafi_ea_job {
     float dt;                       /* sample spacing along the ray */
     float c;                        /* extinction per unit density per sample (kappa * dt) */
     int32_t visit_stride;
+    int32_t emit_mode;              /* RAFI_SLOTS_ORDERED (0): ray in input slot i is emitted to
+                                       output slot i; RAFI_SLOTS_APPEND: forwarded rays are
+                                       appended (rafi_emit) and finished rays take no slot.
+                                       rafi_ea_render opens every march round's output in this
+                                       mode; callers of rafi_ea_march open it themselves
+                                       (rafi_open). Same images either way; the order of rays
+                                       within a domain queue is reproducible only when ordered.
+                                       Other values: RAFI_ERR_ARG. */
 } rafi_ea_job;
 
 /* Item size a context needs for the march (16 bytes: ray id, next sample,

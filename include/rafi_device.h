@@ -61,6 +61,35 @@ __device__ inline void rafi_forward_t(const rafi_device_view &v, uint64_t slot, 
     v.out_dest[slot] = dest;
 }
 
+/* Append emit (emitOutgoing with the paper's atomic queue, Sec. 3.2-3.3),
+ * for output opened with rafi_open(..., RAFI_SLOTS_APPEND): the item goes to
+ * the next free slot. Lanes of a wave that emit together take consecutive
+ * slots in lane order with one atomic per wave. May be called any number of
+ * times per thread and from divergent code. */
+template <typename T>
+__device__ inline void rafi_emit_t(const rafi_device_view &v, const T &item, int32_t dest)
+{
+    const uint64_t active = __ballot(1);
+    const int lane = (int)__lane_id();
+    const int leader = __ffsll((long long)active) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(v.append, (unsigned long long)__popcll(active));
+    base = __shfl(base, leader);
+    rafi_forward_t(v, base + (uint64_t)__popcll(active & ((1ull << lane) - 1ull)), item, dest);
+}
+
+/* Untyped append emit (item_bytes bytes, 4-byte aligned). */
+__device__ inline void rafi_emit(const rafi_device_view &v, const void *item, int32_t dest)
+{
+    const uint64_t active = __ballot(1);
+    const int lane = (int)__lane_id();
+    const int leader = __ffsll((long long)active) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(v.append, (unsigned long long)__popcll(active));
+    base = __shfl(base, leader);
+    rafi_forward(v, base + (uint64_t)__popcll(active & ((1ull << lane) - 1ull)), item, dest);
+}
+
 /* Mark slot `slot` as leaving the system (destination RAFI_DONE). */
 __device__ inline void rafi_done(const rafi_device_view &v, uint64_t slot)
 {

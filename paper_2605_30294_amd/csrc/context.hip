@@ -31,6 +31,15 @@ __global__ void reset_kernel(uint64_t *offsets, uint32_t *tile_offsets, int32_t 
 
 __global__ void clear_dropped_kernel(unsigned long long *dropped) { *dropped = 0; }
 
+// Append-mode output: every slot RAFI_DONE, append counter zero.
+__global__ void open_append_kernel(int32_t *dest, uint64_t n, unsigned long long *append)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *append = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        dest[i] = RAFI_DONE;
+}
+
 bool valid_shape(int32_t D, uint32_t S)
 {
     return D >= 1 && D <= RAFI_MAX_DOMAINS && S >= 4 && S <= RAFI_MAX_ITEM_BYTES && S % 4 == 0;
@@ -183,6 +192,8 @@ int rafi_create(int32_t n_domains, uint32_t item_bytes, uint64_t capacity, rafi_
          hipMalloc(reinterpret_cast<void **>(&c->dropped), sizeof(unsigned long long)) != hipSuccess ||
          hipMalloc(reinterpret_cast<void **>(&c->work), 2 * sizeof(unsigned long long)) != hipSuccess ||
          hipMemset(c->work, 0, 2 * sizeof(unsigned long long)) != hipSuccess ||
+         hipMalloc(reinterpret_cast<void **>(&c->append), sizeof(unsigned long long)) != hipSuccess ||
+         hipMemset(c->append, 0, sizeof(unsigned long long)) != hipSuccess ||
          hipHostMalloc(reinterpret_cast<void **>(&c->host_summary), sizeof(uint64_t) * 8, hipHostMallocDefault) != hipSuccess))
         rc = RAFI_ERR_OOM;
     if (rc == RAFI_OK) rc = empty_queue(c);
@@ -206,6 +217,7 @@ void rafi_destroy(rafi_ctx *c)
     if (c->summary) (void)hipFree(c->summary);
     if (c->dropped) (void)hipFree(c->dropped);
     if (c->work) (void)hipFree(c->work);
+    if (c->append) (void)hipFree(c->append);
     if (c->host_summary) (void)hipHostFree(c->host_summary);
     for (int i = 0; i < c->n_pending; ++i)
         for (int k = 0; k < (c->pending[i].kind == 0 ? 3 : 2); ++k)
@@ -262,6 +274,7 @@ int rafi_view(const rafi_ctx *c, rafi_device_view *v)
     v->n_domains = c->D;
     v->tile_items = c->tile_items;
     v->n_tiles = c->n_tiles;
+    v->append = c->append;
     return RAFI_OK;
 }
 
@@ -273,6 +286,17 @@ int rafi_begin(rafi_ctx *c, uint64_t n_slots)
     c->n_slots = n_slots;
     c->wave_slots = n_slots;
     return ctx_fill_poison(c, n_slots);
+}
+
+int rafi_open(rafi_ctx *c, uint64_t n_slots, int32_t mode)
+{
+    if (!c || n_slots > c->cap || (mode != RAFI_SLOTS_ORDERED && mode != RAFI_SLOTS_APPEND)) return RAFI_ERR_ARG;
+    c->n_slots = n_slots;
+    if (mode == RAFI_SLOTS_ORDERED) return ctx_fill_poison(c, n_slots);
+    const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n_slots + 255) / 256, 4096));
+    hipLaunchKernelGGL(open_append_kernel, dim3(blocks), dim3(256), 0, c->stream, c->dest, n_slots, c->append);
+    RAFI_LAUNCH_CHECK();
+    return RAFI_OK;
 }
 
 int rafi_emit_bulk(rafi_ctx *c, const void *items, const int32_t *dest, uint64_t n)

@@ -59,6 +59,30 @@ raygen_kernel(rafi_device_view view, rafi_ea_job job, uint64_t n_rays)
     }
 }
 
+// Emission of a marched ray from input slot i: to its own output slot, or
+// appended (rafi_open append mode, where every slot starts as RAFI_DONE).
+__device__ inline void emit_item(const rafi_device_view &view, const rafi_ea_job &job, uint64_t i, const Item &it,
+                                 int32_t dest)
+{
+    if (job.emit_mode == RAFI_SLOTS_APPEND) rafi_emit_t(view, it, dest);
+    else rafi_forward_t(view, i, it, dest);
+}
+
+// A ray leaving brick d: forwarded to `dest`, or finished (dest < 0) with its
+// integral, optical depth and end sample written out.
+__device__ inline void emit_ray(const rafi_device_view &view, const rafi_ea_job &job, uint64_t i, const Item &it,
+                                int32_t dest)
+{
+    if (dest >= 0) {
+        emit_item(view, job, i, it, dest);
+        return;
+    }
+    job.image[it.ray] = it.I;
+    if (job.tau) job.tau[it.ray] = it.tau;
+    if (job.klast) job.klast[it.ray] = it.k;
+    if (job.emit_mode != RAFI_SLOTS_APPEND) rafi_done(view, i);
+}
+
 // ------------------------------------------------------------- march ----
 __global__ void __launch_bounds__(256)
 march_kernel(rafi_device_view view, rafi_ea_job job, uint32_t n_rays)
@@ -69,7 +93,7 @@ march_kernel(rafi_device_view view, rafi_ea_job job, uint32_t n_rays)
     const int32_t d = ea::find_domain(view.in_offsets, view.n_domains, i);
     Item it = static_cast<const Item *>(view.in_items)[i];
     if ((uint32_t)it.ray >= n_rays) {  // never true for items this library emitted
-        rafi_forward_t(view, i, it, RAFI_POISON);
+        emit_item(view, job, i, it, RAFI_POISON);
         return;
     }
     log_visit(job, it.ray, d);
@@ -77,14 +101,7 @@ march_kernel(rafi_device_view view, rafi_ea_job job, uint32_t n_rays)
     int32_t K;
     job_ray(job, it.ray, org, dir, &K);
     const int32_t dest = ea::march_through(job.volume, g, ea::box_of(d, g), org, dir, K, job.dt, job.c, it);
-    if (dest >= 0) {
-        rafi_forward_t(view, i, it, dest);
-    } else {
-        job.image[it.ray] = it.I;
-        if (job.tau) job.tau[it.ray] = it.tau;
-        if (job.klast) job.klast[it.ray] = it.k;
-        rafi_done(view, i);
-    }
+    emit_ray(view, job, i, it, dest);
 }
 
 // LDS-staged march: one workgroup per domain-pure tile of the input queue
@@ -106,7 +123,7 @@ march_lds_kernel(rafi_device_view view, rafi_ea_job job, uint32_t n_rays)
     for (uint64_t i = tb + threadIdx.x; i < te; i += blockDim.x) {
         Item it = static_cast<const Item *>(view.in_items)[i];
         if ((uint32_t)it.ray >= n_rays) {
-            rafi_forward_t(view, i, it, RAFI_POISON);
+            emit_item(view, job, i, it, RAFI_POISON);
             continue;
         }
         log_visit(job, it.ray, d);
@@ -114,14 +131,7 @@ march_lds_kernel(rafi_device_view view, rafi_ea_job job, uint32_t n_rays)
         int32_t K;
         job_ray(job, it.ray, org, dir, &K);
         const int32_t dest = ea::march_through_lds(vl, reg, g, box, org, dir, K, job.dt, job.c, it);
-        if (dest >= 0) {
-            rafi_forward_t(view, i, it, dest);
-        } else {
-            job.image[it.ray] = it.I;
-            if (job.tau) job.tau[it.ray] = it.tau;
-            if (job.klast) job.klast[it.ray] = it.k;
-            rafi_done(view, i);
-        }
+        emit_ray(view, job, i, it, dest);
     }
 }
 
@@ -354,6 +364,7 @@ bool job_ok(const rafi_ctx *c, const rafi_ea_job *j)
         if (j->grid[a] < 1 || j->n % j->grid[a] != 0) return false;
     if (c->D != j->grid[0] * j->grid[1] * j->grid[2] || c->S != RAFI_EA_ITEM_BYTES) return false;
     if (j->visit_log && (!j->visit_count || j->visit_stride < 1)) return false;
+    if (j->emit_mode != RAFI_SLOTS_ORDERED && j->emit_mode != RAFI_SLOTS_APPEND) return false;
     const uint64_t rays = (uint64_t)j->n_views * j->width * j->height;
     return rays <= c->cap && rays < (1ull << 31);
 }
@@ -421,6 +432,10 @@ int rafi_ea_render(rafi_ctx *c, const rafi_ea_job *job, int32_t max_rounds, int3
         if (rc != RAFI_OK) break;
         if (total == 0) break;
         if (r >= max_rounds) { rc = RAFI_ERR_MAX_ROUNDS; break; }
+        if (job->emit_mode == RAFI_SLOTS_APPEND) {
+            rc = rafi_open(c, c->n_slots, RAFI_SLOTS_APPEND);
+            if (rc != RAFI_OK) break;
+        }
         rc = rafi_ea_march(c, job);
         if (rc != RAFI_OK) break;
     }

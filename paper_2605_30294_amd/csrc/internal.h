@@ -83,6 +83,7 @@ struct rafi_ctx {
     // Persistent domain kernels: [0] next queue index to hand out, [1] waves
     // that have exited. Zero between launches: the last wave to exit resets both.
     unsigned long long *work = nullptr;
+    unsigned long long *append = nullptr;  // slots taken by rafi_emit since the last rafi_open
     uint64_t *host_summary = nullptr;   // pinned [8]
     void *ws = nullptr;
     uint64_t ws_bytes = 0;

@@ -25,6 +25,7 @@ RAFI_OK = 0
 RAFI_DONE = -1
 RAFI_POISON = -2
 ERR_ARG, ERR_OOM, ERR_HIP, ERR_OVERFLOW, ERR_BAD_DEST, ERR_MAX_ROUNDS, ERR_STATE = range(-1, -8, -1)
+SLOTS_ORDERED, SLOTS_APPEND = 0, 1
 EA_ITEM_BYTES = 16
 SL_ITEM_BYTES = 16
 
@@ -40,7 +41,7 @@ class DeviceView(C.Structure):
                 ("out_items", C.c_void_p), ("out_dest", C.c_void_p), ("dropped", C.c_void_p),
                 ("n_in", C.c_uint64), ("n_slots", C.c_uint64), ("capacity", C.c_uint64),
                 ("item_bytes", C.c_uint32), ("n_domains", C.c_int32), ("tile_items", C.c_uint32),
-                ("n_tiles", C.c_uint32)]
+                ("n_tiles", C.c_uint32), ("append", C.c_void_p)]
 
 
 class Stats(C.Structure):
@@ -59,7 +60,7 @@ class EAJob(C.Structure):
                 ("klast", C.c_void_p), ("kfirst", C.c_void_p), ("visit_log", C.c_void_p),
                 ("visit_count", C.c_void_p), ("n", C.c_int32), ("grid", C.c_int32 * 3),
                 ("n_views", C.c_int32), ("width", C.c_int32), ("height", C.c_int32), ("dt", C.c_float),
-                ("c", C.c_float), ("visit_stride", C.c_int32)]
+                ("c", C.c_float), ("visit_stride", C.c_int32), ("emit_mode", C.c_int32)]
 
 
 class SLJob(C.Structure):
@@ -97,6 +98,7 @@ _SIGS = {
     "rafi_set_tile_items": ([_P, C.c_uint32], C.c_int),
     "rafi_view": ([_P, C.POINTER(DeviceView)], C.c_int),
     "rafi_begin": ([_P, C.c_uint64], C.c_int),
+    "rafi_open": ([_P, C.c_uint64, C.c_int32], C.c_int),
     "rafi_round": ([_P, _P, _U64P], C.c_int),
     "rafi_emit_bulk": ([_P, _P, _P, C.c_uint64], C.c_int),
     "rafi_copy_queue": ([_P, _P, _P], C.c_int),
@@ -212,6 +214,10 @@ class Context:
     def begin(self, n_slots: int):
         _check(lib().rafi_begin(self._h, n_slots), "rafi_begin")
 
+    def open(self, n_slots: int, mode: int = SLOTS_ORDERED):
+        """Reopen this round's output slots (ordered or append), keeping the input queue."""
+        _check(lib().rafi_open(self._h, n_slots, mode), "rafi_open")
+
     def emit_bulk(self, items: torch.Tensor, dest: torch.Tensor):
         _check(lib().rafi_emit_bulk(self._h, _dptr(items), _dptr(dest), dest.numel()), "rafi_emit_bulk")
 
@@ -285,12 +291,12 @@ def multisplit(items: torch.Tensor, dest: torch.Tensor, n_domains: int, out=None
 
 def ea_job(volume: torch.Tensor, grid, views_dev: torch.Tensor, n_views: int, width: int, height: int,
            image: torch.Tensor, tau=None, klast=None, dt=0.5, c=0.025, kfirst=None, visit_log=None,
-           visit_count=None) -> EAJob:
+           visit_count=None, emit_mode=SLOTS_ORDERED) -> EAJob:
     n = volume.shape[0]
     stride = 0 if visit_log is None else visit_log.shape[1]
     return EAJob(_dptr(volume), _dptr(views_dev), _dptr(image), _dptr(tau), _dptr(klast), _dptr(kfirst),
                  _dptr(visit_log), _dptr(visit_count), n, (C.c_int32 * 3)(*[int(g) for g in grid]), n_views,
-                 width, height, float(dt), float(c), stride)
+                 width, height, float(dt), float(c), stride, int(emit_mode))
 
 
 def ea_raygen(ctx: Context, job: EAJob):
@@ -317,7 +323,7 @@ def ea_backward_job(ctx: Context, job: EAJob, grad_image: torch.Tensor, grad_vol
 
 
 def ea_render(volume: torch.Tensor, grid, views: np.ndarray, dt=0.5, c=0.025, ctx: Context | None = None,
-              max_rounds: int = 1024, want_tau=False):
+              max_rounds: int = 1024, want_tau=False, emit_mode=SLOTS_ORDERED):
     """Render all rays of `views` through `volume` (device float32 [n,n,n]).
     Returns dict(image, tau, klast, rounds)."""
     dev = volume.device
@@ -331,7 +337,7 @@ def ea_render(volume: torch.Tensor, grid, views: np.ndarray, dt=0.5, c=0.025, ct
     tau = torch.empty(n_rays, dtype=torch.float32, device=dev) if want_tau else None
     klast = torch.empty(n_rays, dtype=torch.int32, device=dev) if want_tau else None
     kfirst = torch.empty(n_rays, dtype=torch.int32, device=dev) if want_tau else None
-    job = ea_job(volume, grid, vdev, nv, w, h, image, tau, klast, dt, c, kfirst)
+    job = ea_job(volume, grid, vdev, nv, w, h, image, tau, klast, dt, c, kfirst, emit_mode=emit_mode)
     rounds = ea_render_job(ctx, job, max_rounds)
     return dict(image=image, tau=tau, klast=klast, kfirst=kfirst, rounds=rounds, ctx=ctx, job=job,
                 views_dev=vdev)

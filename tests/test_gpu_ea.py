@@ -23,7 +23,7 @@ RTOL = 1e-5
 ATOL = 1e-35
 
 
-def _stepwise(vol_t, grid, views, dt=0.5, c=C32, tile_items=None):
+def _stepwise(vol_t, grid, views, dt=0.5, c=C32, tile_items=None, emit_mode=rafi.SLOTS_ORDERED):
     """Run the rounds one at a time, snapshotting every queue.  Tiles of 512
     items or more select the LDS-staged march kernel when the brick fits."""
     dev = vol_t.device
@@ -34,7 +34,7 @@ def _stepwise(vol_t, grid, views, dt=0.5, c=C32, tile_items=None):
     image = torch.full((n_rays,), -1.0, dtype=torch.float32, device=dev)
     tau = torch.zeros(n_rays, dtype=torch.float32, device=dev)
     klast = torch.zeros(n_rays, dtype=torch.int32, device=dev)
-    job = rafi.ea_job(vol_t, grid, vdev, nv, w, h, image, tau, klast, dt, c)
+    job = rafi.ea_job(vol_t, grid, vdev, nv, w, h, image, tau, klast, dt, c, emit_mode=emit_mode)
     rafi.ea_raygen(ctx, job)
     if tile_items:
         ctx.set_tile_items(tile_items)
@@ -46,6 +46,8 @@ def _stepwise(vol_t, grid, views, dt=0.5, c=C32, tile_items=None):
         queues.append(q.cpu().numpy().view(np.int32).reshape(-1, 4)[:, 0].copy())
         if total == 0:
             break
+        if emit_mode == rafi.SLOTS_APPEND:
+            ctx.open(total, rafi.SLOTS_APPEND)
         rafi.ea_march(ctx, job)
     torch.cuda.synchronize()
     st = ctx.stats()
@@ -92,6 +94,58 @@ def test_rotated_views(orc, n, grid, nv, w, h, seed, tile_items):
     g = _stepwise(torch.from_numpy(vol).to(dev), grid, views, tile_items=tile_items)
     o = orc.ea_render(vol, grid, views, c=C32, queue_cap=1 << 22)
     _compare(g, o)
+
+
+def _segments(queue, counts):
+    """Split a concatenation of per-round, per-domain queues into its segments."""
+    ends = np.cumsum(counts.reshape(-1).astype(np.int64))
+    return np.split(queue, ends[:-1])
+
+
+@pytest.mark.parametrize("n,grid,nv,w,seed", [(64, (4, 4, 4), 2, 48, 11), (48, (3, 2, 1), 3, 30, 12)])
+def test_append_emission(orc, n, grid, nv, w, seed):
+    """Forwarding through the paper's append queue (rafi_emit): every round's
+    per-domain queue holds the oracle's rays as a multiset, and images,
+    optical depths and end samples equal the slot-ordered run bit for bit."""
+    dev = device()
+    vol = W.blob_volume(n, 300 + seed)
+    views = W.random_views(nv, n, w, w, seed=400 + seed)
+    announce(f"ea append n={n} grid={grid}")
+    t = torch.from_numpy(vol).to(dev)
+    a = _stepwise(t, grid, views, emit_mode=rafi.SLOTS_APPEND)
+    g = _stepwise(t, grid, views)
+    o = orc.ea_render(vol, grid, views, c=C32, queue_cap=1 << 22)
+    assert np.array_equal(a["counts"], o["round_counts"])
+    for sa, so in zip(_segments(a["queue"], a["counts"]), _segments(o["queue"], o["round_counts"])):
+        assert np.array_equal(np.sort(sa), np.sort(so))
+    for key in ("image", "tau", "klast"):
+        assert np.array_equal(a[key].view(np.uint32), g[key].view(np.uint32)), key
+    assert a["stats"]["bad_dest"] == 0 and a["stats"]["dropped"] == 0
+    r = rafi.ea_render(t, grid, views, c=C32, want_tau=True, emit_mode=rafi.SLOTS_APPEND)
+    torch.cuda.synchronize()
+    assert np.array_equal(r["image"].cpu().numpy().view(np.uint32), g["image"].view(np.uint32))
+
+
+def test_append_overflow_is_counted():
+    """Append emits beyond the opened slots are dropped, counted and reported."""
+    dev = device()
+    n, grid = 64, (2, 2, 2)
+    vol = torch.from_numpy(W.blob_volume(n, W.SEED_CFG0_VOLUME)).to(dev)
+    views = W.plusz_view(n, 128, 128)
+    n_rays = 128 * 128
+    ctx = rafi.Context(8, rafi.EA_ITEM_BYTES, n_rays)
+    vdev = rafi.views_to_device(views, dev)
+    image = torch.zeros(n_rays, dtype=torch.float32, device=dev)
+    job = rafi.ea_job(vol, grid, vdev, 1, 128, 128, image, emit_mode=rafi.SLOTS_APPEND)
+    rafi.ea_raygen(ctx, job)
+    _, total, _ = ctx.round(counts=False)
+    assert total == n_rays                      # every +z ray enters a z-low brick
+    ctx.open(1000, rafi.SLOTS_APPEND)            # room for 1000 of the 16384 forwards
+    rafi.ea_march(ctx, job)
+    _, total, rc = ctx.round(counts=False, allow=(0, rafi.ERR_OVERFLOW))
+    assert rc == rafi.ERR_OVERFLOW and total == 1000
+    assert ctx.stats()["dropped"] == n_rays - 1000
+    ctx.close()
 
 
 def test_render_entry_point_and_determinism(orc):
