@@ -56,10 +56,23 @@ class SLParams(C.Structure):
     _fields_ = [("n", C.c_int32), ("g", C.c_int32 * 3), ("h", C.c_float), ("max_steps", C.c_int32)]
 
 
+class DTParams(C.Structure):
+    _fields_ = [("n", C.c_int32), ("g", C.c_int32 * 3), ("kappa", C.c_float), ("smax", C.c_float),
+                ("albedo", C.c_float), ("light", C.c_float * 3), ("radiance", C.c_float),
+                ("max_bounce", C.c_int32), ("seed", C.c_uint32)]
+
+
 _p = C.c_void_p
 
 
 def _declare(L):
+    L.oracle_philox4x32_10.argtypes = [_p, _p, _p]
+    L.oracle_philox4x32_10.restype = None
+    L.oracle_dt_logf.argtypes = [C.c_float]
+    L.oracle_dt_logf.restype = C.c_float
+    L.oracle_dt_render.argtypes = [_p, C.POINTER(DTParams), _p, C.c_int32, _p, _p, C.c_int32, _p, _p,
+                                   C.c_uint64, _p]
+    L.oracle_dt_render.restype = C.c_int
     L.oracle_multisplit.argtypes = [C.c_uint64, C.c_uint32, _p, _p, C.c_int32, _p, _p, _p, _p, _p]
     L.oracle_multisplit.restype = C.c_int
     L.oracle_trilinear.argtypes = [_p, C.c_int32, C.c_float, C.c_float, C.c_float]
@@ -251,3 +264,58 @@ def streamlines_brute(field, grid, seeds, h=0.25, max_steps=2000, visit_stride=0
     lib().oracle_streamlines_brute(_ptr(f), C.byref(P), _ptr(s), N, _ptr(ep), _ptr(st), _ptr(why),
                                    _ptr(vis), visit_stride)
     return dict(endpoint=ep, steps=st, reason=why, visits=vis)
+
+
+# ------------------------------------------------------------ delta tracking
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 block: counter (4 x uint32), key (2 x uint32) -> 4 x uint32."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    lib().oracle_philox4x32_10(_ptr(c), _ptr(k), _ptr(o))
+    return o
+
+
+def dt_logf(x):
+    """The float32 natural logarithm used for free-flight distances, x in (0, 1]."""
+    L = lib()
+    return np.array([L.oracle_dt_logf(float(v)) for v in np.asarray(x, dtype=np.float32).ravel()],
+                    dtype=np.float32)
+
+
+def dt_params(n, grid, kappa, smax, albedo, light, radiance, max_bounce, seed):
+    return DTParams(int(n), (C.c_int32 * 3)(*[int(g) for g in grid]), float(kappa), float(smax), float(albedo),
+                    (C.c_float * 3)(*[float(v) for v in light]), float(radiance), int(max_bounce),
+                    int(seed) & 0xFFFFFFFF)
+
+
+def dt_render(volume, grid, views, kappa, smax, albedo, light, radiance, max_bounce, seed,
+              max_rounds=4096, queue_cap=0):
+    """Delta-tracking round loop (O7). Returns dict(contrib [n_paths, max_bounce]
+    float64, image (sum over scattering events, float64), rounds,
+    round_counts [rounds, D], queue [len, 11] uint32 (p, d bits, path, stream,
+    count, bounce, kind per queued item), weights [len] float64)."""
+    vol = np.ascontiguousarray(volume, dtype=np.float32)
+    n = vol.shape[0]
+    views = np.ascontiguousarray(views)
+    n_paths = n_rays_of(views)
+    D = int(np.prod(grid))
+    P = dt_params(n, grid, kappa, smax, albedo, light, radiance, max_bounce, seed)
+    contrib = np.zeros((n_paths, max_bounce), dtype=np.float64)
+    rc = np.zeros((max_rounds, D), dtype=np.uint64)
+    q = np.zeros((max(queue_cap, 1), 11), dtype=np.uint32)
+    wl = np.zeros(max(queue_cap, 1), dtype=np.float64)
+    qlen = C.c_uint64(0)
+    rounds = lib().oracle_dt_render(_ptr(vol), C.byref(P), _ptr(views), len(views), _ptr(contrib),
+                                    _ptr(wl) if queue_cap else None, max_rounds, _ptr(rc),
+                                    _ptr(q) if queue_cap else None, queue_cap, C.byref(qlen))
+    if rounds < 0:
+        raise RuntimeError(f"oracle_dt_render failed: {rounds}")
+    out = dict(contrib=contrib, image=contrib.sum(axis=1), rounds=rounds, round_counts=rc[:rounds])
+    if queue_cap:
+        m = min(qlen.value, queue_cap)
+        out["queue"] = q[:m]
+        out["weights"] = wl[:m]
+        out["queue_len"] = qlen.value
+    return out

@@ -721,3 +721,310 @@ int oracle_streamlines_brute(const float *field, const orc_sl_params *P, const f
     }
     return 0;
 }
+
+/* ======================================================================
+ * O7. Delta-tracking volume path tracing over bricks.
+ *
+ * The volume path tracer of Sec. 5.1 traces rays through the local brick with
+ * delta (Woodcock) tracking; a ray that scatters is forwarded to its own
+ * rank for the next round, a ray that leaves the brick to the rank owning
+ * the point it reached, and a shading event may spawn a shadow ray beside the
+ * bounced ray (Sec. 5.1 figure, Sec. 5.2 Lander with volumetric shadows,
+ * Sec. 6.3 on one item spawning several). Reading used here:
+ *
+ *   medium    sigma_t(x) = kappa * V(x), V the float32 trilinear density;
+ *             one global majorant smax >= kappa * max V, so the sequence of
+ *             tentative collisions along a ray does not depend on the bricks;
+ *   path      tentative points p += s d, s = -ln(1 - u) / smax; at a
+ *             tentative point inside brick D a path collides for real when
+ *             u * smax < sigma_t(p) (u a fresh draw), else continues;
+ *             leaving the volume ends it (black background);
+ *   scatter   weight w *= albedo; a shadow ray toward the light starts at the
+ *             collision point with weight w * radiance / (4 pi) (isotropic
+ *             phase); the path takes a new isotropic direction (Marsaglia
+ *             1972) unless it has scattered max_bounce times;
+ *   shadow    ratio tracking: at each tentative point the weight is
+ *             multiplied by 1 - sigma_t(p) / smax; on leaving the volume its
+ *             weight is the contribution of that scattering event;
+ *   output    contrib[path * max_bounce + b] for the shadow ray of the b-th
+ *             scattering event (0 where there was none);
+ *   slots     fixed fan-out 2: the item in input slot i owns output slots 2i
+ *             (the item itself, or the shadow ray of its scattering event)
+ *             and 2i + 1 (the bounced path, or DONE);
+ *   random    Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011), key
+ *             (seed, path id), counter (stream, draw index, 0, 0), word 0,
+ *             u = (word >> 8) * 2^-24; stream 2b is the path after b
+ *             scattering events, 2b + 1 the shadow ray of event b.
+ * Positions, draws and every decision are float32 with each operation
+ * written out; weights are float64.
+ * ====================================================================== */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static float f32_of(uint32_t b) { float f; memcpy(&f, &b, 4); return f; }
+static uint32_t bits_of(float f) { uint32_t b; memcpy(&b, &f, 4); return b; }
+
+/* Natural logarithm of a normal float32 x in (0, 1], from x = m 2^e with
+ * m in [sqrt(1/2), sqrt(2)) and ln m = 2 atanh(s), s = (m - 1) / (m + 1),
+ * summed as 2s + 2s (s^2/3 + s^4/5 + ... + s^12/13) (|s| < 0.172, so the
+ * first omitted term is below 2^-40 relative); ln x = e ln2 + ln m with ln2
+ * split in two parts. Each operation is one float32 rounding. */
+float oracle_dt_logf(float x)
+{
+    const uint32_t b = bits_of(x);
+    int32_t e = (int32_t)(b >> 23) - 127;
+    float m = f32_of((b & 0x007FFFFFu) | 0x3F800000u);
+    if (m > 1.41421354f) {
+        m = m * 0.5f;
+        e += 1;
+    }
+    const float f = m - 1.0f;
+    const float s = f / (2.0f + f);
+    const float z = s * s;
+    float q = fmaf(z, 1.0f / 13.0f, 1.0f / 11.0f);
+    q = fmaf(z, q, 1.0f / 9.0f);
+    q = fmaf(z, q, 1.0f / 7.0f);
+    q = fmaf(z, q, 1.0f / 5.0f);
+    q = fmaf(z, q, 1.0f / 3.0f);
+    q = q * z;
+    const float s2 = s + s;
+    const float lnm = fmaf(s2, q, s2);
+    const float fe = (float)e;
+    return fmaf(fe, 0.693145751953125f, fmaf(fe, 1.42860677e-06f, lnm));
+}
+
+typedef struct {
+    int32_t n;
+    int32_t g[3];
+    float kappa, smax, albedo;
+    float light[3];
+    float radiance;
+    int32_t max_bounce;
+    uint32_t seed;
+} orc_dt_params;
+
+enum { DT_PATH = 0, DT_SHADOW = 1 };
+
+typedef struct {
+    float p[3], d[3];
+    double w;
+    int32_t path;
+    uint32_t stream, count;
+    int32_t bounce, kind;
+} orc_dt_item;
+
+static float dt_draw(const orc_dt_params *P, orc_dt_item *it)
+{
+    const uint32_t ctr[4] = {it->stream, it->count, 0u, 0u};
+    const uint32_t key[2] = {P->seed, (uint32_t)it->path};
+    uint32_t o[4];
+    oracle_philox4x32_10(ctr, key, o);
+    it->count++;
+    return (float)(o[0] >> 8) * 5.9604644775390625e-08f; /* 2^-24 */
+}
+
+static void dt_fly(const orc_dt_params *P, orc_dt_item *it)
+{
+    const float s = -oracle_dt_logf(1.0f - dt_draw(P, it)) / P->smax;
+    for (int a = 0; a < 3; ++a) it->p[a] = fmaf(s, it->d[a], it->p[a]);
+}
+
+/* float32 trilinear, clamp-to-edge, lerping x, then y, then z */
+static float dt_density(const float *vol, int32_t n, const float q[3])
+{
+    int32_t i0[3];
+    float f[3];
+    const float hi = (float)(n - 1);
+    for (int a = 0; a < 3; ++a) {
+        const float u = fminf(fmaxf(q[a] - 0.5f, 0.0f), hi);
+        int32_t i = (int32_t)floorf(u);
+        if (i > n - 2) i = n - 2;
+        i0[a] = i;
+        f[a] = u - (float)i;
+    }
+    const size_t sy = (size_t)n, sz = (size_t)n * n;
+    const float *b = vol + (size_t)i0[0] + sy * (size_t)i0[1] + sz * (size_t)i0[2];
+    const float x00 = lerpf(b[0], b[1], f[0]), x01 = lerpf(b[sy], b[sy + 1], f[0]);
+    const float x10 = lerpf(b[sz], b[sz + 1], f[0]), x11 = lerpf(b[sz + sy], b[sz + sy + 1], f[0]);
+    return lerpf(lerpf(x00, x01, f[1]), lerpf(x10, x11, f[1]), f[2]);
+}
+
+static void dt_isotropic(const orc_dt_params *P, orc_dt_item *it)
+{
+    for (int tries = 0; tries < 64; ++tries) {
+        const float x1 = fmaf(2.0f, dt_draw(P, it), -1.0f);
+        const float x2 = fmaf(2.0f, dt_draw(P, it), -1.0f);
+        const float s = fmaf(x1, x1, x2 * x2);
+        if (s < 1.0f && s > 0.0f) {
+            const float t = 2.0f * sqrtf(1.0f - s);
+            it->d[0] = x1 * t;
+            it->d[1] = x2 * t;
+            it->d[2] = fmaf(-2.0f, s, 1.0f);
+            return;
+        }
+    }
+    it->d[0] = 0.0f; it->d[1] = 0.0f; it->d[2] = 1.0f;
+}
+
+/* Primary ray of path r: entry into [0,n)^3 by the slab test, then its
+ * first tentative point. Returns the owner of that point (-1: no collision
+ * possible, the path is done). */
+static int32_t dt_raygen(const orc_dt_params *P, const orc_view *views, int64_t r, orc_dt_item *it)
+{
+    const orc_view *v;
+    int32_t px, py;
+    ray_of(views, r, &v, &px, &py);
+    float o[3];
+    ray_origin(v, px, py, o);
+    memset(it, 0, sizeof(*it));
+    it->path = (int32_t)r;
+    it->w = 1.0;
+    it->kind = DT_PATH;
+    const float fn = (float)P->n;
+    float t0 = 0.0f, t1 = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        it->d[a] = v->dir[a];
+        if (v->dir[a] != 0.0f) {
+            const float ta = (0.0f - o[a]) / v->dir[a], tb = (fn - o[a]) / v->dir[a];
+            t0 = fmaxf(t0, fminf(ta, tb));
+            t1 = fminf(t1, fmaxf(ta, tb));
+        } else if (!(o[a] >= 0.0f && o[a] < fn)) {
+            return -1;
+        }
+    }
+    if (!(t0 < t1)) return -1;
+    for (int a = 0; a < 3; ++a) it->p[a] = fmaf(t0, it->d[a], o[a]);
+    dt_fly(P, it);
+    return owner_of(it->p, P->n, P->g);
+}
+
+/* One visit of item `it` to brick `d` (its tentative point lies in d). Writes
+ * the content of the item's two output slots: out[0] / dest[0] and
+ * out[1] / dest[1] (ORC_DONE when a slot carries nothing). */
+static void dt_visit(const float *vol, const orc_dt_params *P, int32_t d, orc_dt_item it, double *contrib,
+                     orc_dt_item out[2], int32_t dest[2])
+{
+    dest[0] = ORC_DONE;
+    dest[1] = ORC_DONE;
+    for (;;) {
+        const float sigma = P->kappa * dt_density(vol, P->n, it.p);
+        if (it.kind == DT_PATH) {
+            const float u = dt_draw(P, &it);
+            if (u * P->smax < sigma) {
+                const int32_t b = it.bounce;
+                const double w = it.w * (double)P->albedo;
+                orc_dt_item sh = it;
+                sh.kind = DT_SHADOW;
+                sh.stream = 2u * (uint32_t)b + 1u;
+                sh.count = 0;
+                sh.w = w * (double)P->radiance / (4.0 * 3.14159265358979323846);
+                for (int a = 0; a < 3; ++a) sh.d[a] = P->light[a];
+                dt_fly(P, &sh);
+                const int32_t es = owner_of(sh.p, P->n, P->g);
+                if (es < 0) contrib[(size_t)sh.path * P->max_bounce + b] = sh.w;
+                else { out[0] = sh; dest[0] = es; }
+                if (b + 1 < P->max_bounce) {
+                    orc_dt_item pa = it;
+                    pa.bounce = b + 1;
+                    pa.stream = 2u * (uint32_t)(b + 1);
+                    pa.count = 0;
+                    pa.w = w;
+                    dt_isotropic(P, &pa);
+                    dt_fly(P, &pa);
+                    const int32_t ep = owner_of(pa.p, P->n, P->g);
+                    if (ep >= 0) { out[1] = pa; dest[1] = ep; }
+                }
+                return;
+            }
+        } else {
+            it.w *= 1.0 - (double)sigma / (double)P->smax;
+        }
+        dt_fly(P, &it);
+        const int32_t e = owner_of(it.p, P->n, P->g);
+        if (e == d) continue;
+        if (e < 0) {
+            if (it.kind == DT_SHADOW) contrib[(size_t)it.path * P->max_bounce + it.bounce] = it.w;
+            return;
+        }
+        out[0] = it;
+        dest[0] = e;
+        return;
+    }
+}
+
+/* The round loop for delta tracking (O2 with fan-out 2): round 0 emits every
+ * path to the owner of its first tentative point; each later round visits
+ * the domains in order and their queued items in order, and the 2 slots of
+ * each item go through the stable counting sort of O1. Logged per forward
+ * step: counts per domain, and every queued item as 11 words (p, d as float32
+ * bits; path, stream, count, bounce, kind) in queue order. */
+int oracle_dt_render(const float *vol, const orc_dt_params *P, const orc_view *views, int32_t n_views,
+                     double *contrib, double *weights_log, int32_t max_rounds, uint64_t *round_counts,
+                     uint32_t *queue_log, uint64_t queue_cap, uint64_t *queue_len)
+{
+    const int32_t D = P->g[0] * P->g[1] * P->g[2];
+    int64_t n_paths = 0;
+    for (int32_t v = 0; v < n_views; ++v) n_paths += (int64_t)views[v].width * views[v].height;
+    memset(contrib, 0, sizeof(double) * (size_t)n_paths * P->max_bounce);
+    /* a path has at most itself and one shadow ray per scattering event alive */
+    const size_t live = (size_t)n_paths * (size_t)(P->max_bounce + 1) + 1;
+    orc_dt_item *slots = (orc_dt_item *)malloc(sizeof(orc_dt_item) * 2 * live);
+    orc_dt_item *queue = (orc_dt_item *)malloc(sizeof(orc_dt_item) * live);
+    int32_t *sdest = (int32_t *)malloc(sizeof(int32_t) * 2 * live);
+    uint64_t *counts = (uint64_t *)calloc((size_t)D, sizeof(uint64_t));
+    uint64_t *offs = (uint64_t *)calloc((size_t)D + 1, sizeof(uint64_t));
+    if (!slots || !queue || !sdest || !counts || !offs) return -2;
+    uint64_t n_slots = (uint64_t)n_paths, qlen = 0;
+    for (int64_t r = 0; r < n_paths; ++r) sdest[r] = dt_raygen(P, views, r, &slots[r]);
+    int32_t rounds = 0;
+    for (;;) {
+        /* forward step: stable counting sort of the slots by destination */
+        for (int32_t e = 0; e < D; ++e) counts[e] = 0;
+        for (uint64_t i = 0; i < n_slots; ++i)
+            if (sdest[i] >= 0) counts[sdest[i]]++;
+        offs[0] = 0;
+        for (int32_t e = 0; e < D; ++e) offs[e + 1] = offs[e] + counts[e];
+        uint64_t *fill = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)D);
+        for (int32_t e = 0; e < D; ++e) fill[e] = offs[e];
+        for (uint64_t i = 0; i < n_slots; ++i)
+            if (sdest[i] >= 0) queue[fill[sdest[i]]++] = slots[i];
+        free(fill);
+        const uint64_t total = offs[D];
+        if (total >= live) return -3; /* cannot happen: see the bound above */
+        if (round_counts && rounds < max_rounds)
+            for (int32_t e = 0; e < D; ++e) round_counts[(size_t)rounds * D + e] = counts[e];
+        for (uint64_t i = 0; i < total; ++i, ++qlen) {
+            if (!queue_log || qlen >= queue_cap) continue;
+            uint32_t *q = queue_log + qlen * 11;
+            for (int a = 0; a < 3; ++a) { q[a] = bits_of(queue[i].p[a]); q[3 + a] = bits_of(queue[i].d[a]); }
+            q[6] = (uint32_t)queue[i].path; q[7] = queue[i].stream; q[8] = queue[i].count;
+            q[9] = (uint32_t)queue[i].bounce; q[10] = (uint32_t)queue[i].kind;
+            if (weights_log) weights_log[qlen] = queue[i].w;
+        }
+        rounds++;
+        if (total == 0) break;
+        if (rounds >= max_rounds) { rounds = -1; break; }
+        /* domain kernels, fan-out 2 */
+        for (int32_t e = 0; e < D; ++e)
+            for (uint64_t i = offs[e]; i < offs[e + 1]; ++i)
+                dt_visit(vol, P, e, queue[i], contrib, &slots[2 * i], &sdest[2 * i]);
+        n_slots = 2 * total;
+    }
+    if (queue_len) *queue_len = qlen;
+    free(slots); free(queue); free(sdest); free(counts); free(offs);
+    return rounds;
+}
