@@ -285,6 +285,50 @@ def ea_forward(dev, reps):
     return out
 
 
+def delta_tracking(dev, reps):
+    """Delta-tracking path tracing: 128^3 blobs, 4x4x4 bricks, 16 views x 256^2
+    paths (one per pixel), up to 4 scattering events each with a shadow ray."""
+    import numpy as np
+    import torch
+
+    from paper_2605_30294_amd import rafi
+    from paper_2605_30294_amd import workloads as W
+
+    n, grid, B = 128, (4, 4, 4), 4
+    vol = W.blob_volume(n, W.SEED_ADJ_VOLUME, device=dev)
+    views = W.random_views(16, n, 256, 256)
+    kappa = 0.05
+    smax = float(np.float32(kappa * float(vol.max().item())))
+    counters = torch.zeros(2, dtype=torch.int64, device=dev)
+    r = rafi.dt_render(vol, grid, views, kappa, smax, 0.8, (0.0, 0.6, 0.8), 1.0, B, 11)
+    ctx, job = r["ctx"], r["job"]
+    job.counters = rafi._dptr(counters)
+    rafi.dt_render_job(ctx, job)
+    torch.cuda.synchronize()
+    counters.zero_()
+    ctx.set_profiling(True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        rounds = rafi.dt_render_job(ctx, job)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    p = ctx.profile()
+    points, hits = (int(v) // reps for v in counters.cpu().tolist())
+    n_paths = 16 * 256 * 256
+    ctx.close()
+    out = {"workload": "128^3 blobs, 4x4x4 domains, 16 views x 256^2 paths, <=4 scattering events + shadow rays",
+           "ms": round(ms, 4), "rounds": rounds, "paths_per_s": n_paths / (ms * 1e-3),
+           "tentative_points": points, "real_collisions": hits, "points_per_s": points / (ms * 1e-3),
+           "trace_ms": round(p["domain_ms"] / reps, 4), "split_ms": round(p["split_ms"] / reps, 4),
+           "forwarded_items_per_s": p["split_items"] / reps / (ms * 1e-3)}
+    log(f"delta tracking: {ms:.3f} ms, {rounds} rounds, {points} tentative points, {hits} collisions, "
+        f"{out['points_per_s']:.3g} points/s")
+    return out
+
+
 def ea_adjoint(dev, reps):
     """128^3 / 64 bricks / 64 views x 256^2: forward render, then the
     reverse-replay backward of the L2 image loss against a second volume."""
@@ -404,7 +448,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seeds", type=int, default=262144)
     ap.add_argument("--only", default=None,
-                    choices=["streamlines", "split", "split-domains", "ea", "adjoint", "batched", "copy"],
+                    choices=["streamlines", "split", "split-domains", "ea", "adjoint", "batched", "dt", "copy"],
                     help="run one leg alone (for profilers) and print its result")
     ap.add_argument("--tail-items", type=int, default=0,
                     help="launches with at most this many particles integrate uncapped")
@@ -443,6 +487,8 @@ def main():
             res = ea_adjoint(dev, reps=args.steps)
         elif args.only == "batched":
             res = batched(dev, reps=args.steps)
+        elif args.only == "dt":
+            res = delta_tracking(dev, reps=args.steps)
         else:
             res = plain_copy(dev, reps=args.steps)
         print(json.dumps({"only": args.only, "result": res}, default=str), flush=True)
@@ -455,6 +501,7 @@ def main():
         extras["ea_forward"] = ea_forward(dev, reps=5)
         extras["adjoint_vs_forward"] = ea_adjoint(dev, reps=3)
         extras["batched_vs_plain"] = batched(dev, reps=2)
+        extras["delta_tracking"] = delta_tracking(dev, reps=3)
     cpu = None if args.no_cpu else cpu_baseline(seeds_np, args.cpu_seeds)
 
     value = sl["forwarded"] / (sl["ms"] * 1e-3)

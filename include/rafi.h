@@ -421,6 +421,74 @@ int rafi_sl_advance(rafi_ctx *ctx, const rafi_sl_job *job);
 int rafi_sl_trace(rafi_ctx *ctx, const rafi_sl_job *job, const float *seeds, uint64_t n_seeds,
                   int32_t max_rounds, int32_t *rounds, uint64_t *forwarded);
 
+/* ------------------------------------------------------------------------
+ * Delta-tracking volume path tracing over bricked domains (the stochastic
+ * transport of Sec. 5.1: Woodcock tracking inside the local brick, scattered
+ * and shadow rays forwarded between rounds; one item may spawn two).
+ *
+ * Medium sigma_t(x) = kappa V(x) with V the float32 trilinear density (as for
+ * the emission-absorption march); one global majorant smax >= kappa max V.
+ * A path draws tentative points p += s d with s = -ln(1 - u) / smax; at a
+ * point inside its brick it collides for real when u' smax < sigma_t(p),
+ * otherwise it continues; leaving the volume ends it (black background). At a
+ * real collision its weight is multiplied by the albedo, a shadow ray leaves
+ * toward the light with weight w radiance / (4 pi) (isotropic phase) and is
+ * ratio-tracked (weight times 1 - sigma_t / smax per tentative point) until it
+ * leaves the volume, where its weight is the contribution of that scattering
+ * event; the path takes a new isotropic direction (Marsaglia 1972) unless it
+ * has scattered max_bounce times.
+ * Random numbers: Philox4x32-10 (Salmon et al., SC 2011) with key
+ * (seed, path id) and counter (stream, draw index, 0, 0), first word,
+ * u = (word >> 8) 2^-24; stream 2b is the path after b scattering events,
+ * 2b + 1 the shadow ray of event b. Logarithms use a fixed float32 series
+ * (range reduction to [sqrt(1/2), sqrt(2)) and 2 atanh((m-1)/(m+1)) to s^13),
+ * so the random walk is reproducible bit for bit.
+ * Slots: fixed fan-out 2 per visit (input slot i owns output slots 2i, 2i+1).
+ * ------------------------------------------------------------------------ */
+typedef struct rafi_dt_job {
+    const float *volume;            /* device [n^3] densities, x fastest */
+    const rafi_ortho_view *views;   /* device [n_views], all width x height; path id =
+                                       ray id = (view * height + py) * width + px */
+    float *contrib;                 /* device [n_paths * max_bounce]: contribution of the
+                                       shadow ray of each scattering event (0: none);
+                                       zeroed by rafi_dt_raygen */
+    float *image;                   /* device [n_paths], optional: sum of contrib over the
+                                       events, in event order, written by rafi_dt_render */
+    int32_t n;
+    int32_t grid[3];
+    int32_t n_views, width, height;
+    float kappa;                    /* extinction per unit density per unit length */
+    float smax;                     /* global majorant, >= kappa * max density, > 0 */
+    float albedo;                   /* in [0, 1] */
+    float light[3];                 /* unit direction toward the (directional) light */
+    float radiance;                 /* light radiance */
+    int32_t max_bounce;             /* scattering events per path, >= 1 */
+    uint32_t seed;
+    unsigned long long *counters;   /* device [2], optional, accumulated: tentative points
+                                       evaluated, real collisions */
+} rafi_dt_job;
+
+/* Item size a context needs (position, direction, weight, path id, stream,
+ * draw count, scattering events, kind). */
+#define RAFI_DT_ITEM_BYTES 48
+
+/* Context capacity that always suffices: a path has at most itself and one
+ * shadow ray per scattering event alive, and each visit opens 2 slots. */
+int rafi_dt_capacity(uint64_t n_paths, int32_t max_bounce, uint64_t *capacity);
+
+/* Round 0: one slot per path; each primary ray enters the volume (slab test)
+ * and goes to the owner of its first tentative point, or finishes. */
+int rafi_dt_raygen(rafi_ctx *ctx, const rafi_dt_job *job);
+
+/* One domain-kernel launch: opens 2 ordered slots per queued item and traces
+ * every item through its brick until it leaves the brick, leaves the volume,
+ * or (paths) collides for real. RAFI_ERR_ARG if 2 n_in exceeds the capacity. */
+int rafi_dt_trace(rafi_ctx *ctx, const rafi_dt_job *job);
+
+/* Whole render: raygen, then rafi_round / rafi_dt_trace until nothing is
+ * left; then image (if set). *rounds receives the number of forward steps. */
+int rafi_dt_render(rafi_ctx *ctx, const rafi_dt_job *job, int32_t max_rounds, int32_t *rounds);
+
 #ifdef __cplusplus
 }
 #endif

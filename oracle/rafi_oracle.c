@@ -818,6 +818,9 @@ typedef struct {
 } orc_dt_params;
 
 enum { DT_PATH = 0, DT_SHADOW = 1 };
+/* tentative points evaluated per brick visit before the item is forwarded to
+ * its own brick (its walk then continues unchanged in the next round) */
+#define DT_MAX_POINTS 65536u
 
 typedef struct {
     float p[3], d[3];
@@ -920,7 +923,12 @@ static void dt_visit(const float *vol, const orc_dt_params *P, int32_t d, orc_dt
 {
     dest[0] = ORC_DONE;
     dest[1] = ORC_DONE;
-    for (;;) {
+    for (uint32_t points = 0;; ++points) {
+        if (points == DT_MAX_POINTS) { /* bounded visit: continue next round in the same brick */
+            out[0] = it;
+            dest[0] = d;
+            return;
+        }
         const float sigma = P->kappa * dt_density(vol, P->n, it.p);
         if (it.kind == DT_PATH) {
             const float u = dt_draw(P, &it);

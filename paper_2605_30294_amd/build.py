@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librafi.so")
 
-SOURCES = ["context.hip", "multisplit.hip", "ea.hip", "streamline.hip", "batched.hip"]
+SOURCES = ["context.hip", "multisplit.hip", "ea.hip", "streamline.hip", "batched.hip", "dt.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -27,6 +27,8 @@ FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # every float32 operation rounded once, as written: no contraction, no fast-math
     "-ffp-contract=off", "-fno-fast-math", "-fno-gpu-flush-denormals-to-zero",
+    # IEEE (correctly rounded) float32 division and square root (the HIP default, stated)
+    "-fhip-fp32-correctly-rounded-divide-sqrt",
     # no packed-fp32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",

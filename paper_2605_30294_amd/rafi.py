@@ -27,6 +27,7 @@ RAFI_POISON = -2
 ERR_ARG, ERR_OOM, ERR_HIP, ERR_OVERFLOW, ERR_BAD_DEST, ERR_MAX_ROUNDS, ERR_STATE = range(-1, -8, -1)
 SLOTS_ORDERED, SLOTS_APPEND = 0, 1
 EA_ITEM_BYTES = 16
+DT_ITEM_BYTES = 48
 SL_ITEM_BYTES = 16
 
 
@@ -68,6 +69,14 @@ class SLJob(C.Structure):
                 ("counters", C.c_void_p), ("n", C.c_int32), ("grid", C.c_int32 * 3), ("h", C.c_float),
                 ("max_steps", C.c_int32), ("steps_per_visit", C.c_int32), ("tail_items", C.c_uint32),
                 ("refill_lanes", C.c_int32), ("field_stride", C.c_int32)]
+
+
+class DTJob(C.Structure):
+    _fields_ = [("volume", C.c_void_p), ("views", C.c_void_p), ("contrib", C.c_void_p), ("image", C.c_void_p),
+                ("n", C.c_int32), ("grid", C.c_int32 * 3), ("n_views", C.c_int32), ("width", C.c_int32),
+                ("height", C.c_int32), ("kappa", C.c_float), ("smax", C.c_float), ("albedo", C.c_float),
+                ("light", C.c_float * 3), ("radiance", C.c_float), ("max_bounce", C.c_int32),
+                ("seed", C.c_uint32), ("counters", C.c_void_p)]
 
 
 class ViewRec(C.Structure):
@@ -123,6 +132,10 @@ _SIGS = {
     "rafi_sl_seed": ([_P, C.POINTER(SLJob), _P, C.c_uint64], C.c_int),
     "rafi_sl_advance": ([_P, C.POINTER(SLJob)], C.c_int),
     "rafi_sl_trace": ([_P, C.POINTER(SLJob), _P, C.c_uint64, C.c_int32, C.POINTER(C.c_int32), _U64P], C.c_int),
+    "rafi_dt_capacity": ([C.c_uint64, C.c_int32, _U64P], C.c_int),
+    "rafi_dt_raygen": ([_P, _P], C.c_int),
+    "rafi_dt_trace": ([_P, _P], C.c_int),
+    "rafi_dt_render": ([_P, _P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
 }
 
 _lib = None
@@ -495,3 +508,59 @@ def build_batch_inputs(specs, device, views=None):
         scenes.append((sp.n, sp.grid, view, off))
         off += v.numel()
     return torch.cat(vols), scenes
+
+
+# ------------------------------------------------------- delta tracking ---
+
+def dt_capacity(n_paths: int, max_bounce: int) -> int:
+    cap = C.c_uint64(0)
+    _check(lib().rafi_dt_capacity(n_paths, max_bounce, C.byref(cap)), "rafi_dt_capacity")
+    return cap.value
+
+
+def dt_job(volume: torch.Tensor, grid, views_dev: torch.Tensor, n_views: int, width: int, height: int,
+           contrib: torch.Tensor, image=None, kappa=0.05, smax=None, albedo=0.8, light=(0.0, 0.0, -1.0),
+           radiance=1.0, max_bounce=4, seed=0, counters=None) -> DTJob:
+    """smax defaults to kappa * max(volume) (the smallest valid majorant).
+    counters: optional int64 device tensor [2] (tentative points, real collisions)."""
+    n = volume.shape[0]
+    if smax is None:
+        smax = float(kappa) * float(volume.max())
+    return DTJob(_dptr(volume), _dptr(views_dev), _dptr(contrib), _dptr(image), n,
+                 (C.c_int32 * 3)(*[int(g) for g in grid]), n_views, width, height, float(kappa), float(smax),
+                 float(albedo), (C.c_float * 3)(*[float(v) for v in light]), float(radiance), int(max_bounce),
+                 int(seed) & 0xFFFFFFFF, _dptr(counters))
+
+
+def dt_raygen(ctx: Context, job: DTJob):
+    _check(lib().rafi_dt_raygen(ctx.handle, C.byref(job)), "rafi_dt_raygen")
+
+
+def dt_trace(ctx: Context, job: DTJob):
+    _check(lib().rafi_dt_trace(ctx.handle, C.byref(job)), "rafi_dt_trace")
+
+
+def dt_render_job(ctx: Context, job: DTJob, max_rounds: int = 100000) -> int:
+    r = C.c_int32(0)
+    _check(lib().rafi_dt_render(ctx.handle, C.byref(job), max_rounds, C.byref(r)), "rafi_dt_render")
+    return r.value
+
+
+def dt_render(volume: torch.Tensor, grid, views: np.ndarray, kappa=0.05, smax=None, albedo=0.8,
+              light=(0.0, 0.0, -1.0), radiance=1.0, max_bounce=4, seed=0, ctx: Context | None = None,
+              max_rounds: int = 100000):
+    """Delta-tracking render of all paths of `views` (one path per pixel).
+    Returns dict(image [n_paths], contrib [n_paths, max_bounce], rounds, ctx)."""
+    dev = volume.device
+    nv = len(views)
+    w, h = int(views[0]["width"]), int(views[0]["height"])
+    n_paths = nv * w * h
+    if ctx is None:
+        ctx = Context(int(np.prod(grid)), DT_ITEM_BYTES, dt_capacity(max(n_paths, 1), max_bounce))
+    vdev = views_to_device(views, dev)
+    contrib = torch.empty((n_paths, max_bounce), dtype=torch.float32, device=dev)
+    image = torch.empty(n_paths, dtype=torch.float32, device=dev)
+    job = dt_job(volume, grid, vdev, nv, w, h, contrib, image, kappa, smax, albedo, light, radiance, max_bounce,
+                 seed)
+    rounds = dt_render_job(ctx, job, max_rounds)
+    return dict(image=image, contrib=contrib, rounds=rounds, ctx=ctx, job=job, views_dev=vdev)
