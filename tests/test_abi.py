@@ -54,3 +54,46 @@ def test_argument_validation_without_device():
     assert L.rafi_round(None, None, None) == rafi.ERR_ARG
     assert L.rafi_ea_render(None, None, 1, None) == rafi.ERR_ARG
     assert L.rafi_sl_trace(None, None, None, 0, 1, None, None) == rafi.ERR_ARG
+    assert L.rafi_open(None, 10, rafi.SLOTS_APPEND) == rafi.ERR_ARG
+    assert L.rafi_dt_raygen(None, None) == rafi.ERR_ARG
+    assert L.rafi_dt_trace(None, None) == rafi.ERR_ARG
+    assert L.rafi_dt_render(None, None, 10, None) == rafi.ERR_ARG
+    assert L.rafi_split_set_variant(14) == rafi.ERR_ARG
+    assert L.rafi_split_set_variant(-1) == rafi.ERR_ARG
+
+
+def test_dt_capacity_bound():
+    """Capacity for delta tracking: 2 slots per visit x (the path + one shadow
+    ray per scattering event) per path."""
+    L = rafi.lib()
+    cap = C.c_uint64(0)
+    assert L.rafi_dt_capacity(1000, 4, C.byref(cap)) == rafi.RAFI_OK and cap.value == 2 * 1000 * 5
+    assert L.rafi_dt_capacity(1000, 0, C.byref(cap)) == rafi.ERR_ARG
+    assert L.rafi_dt_capacity(1 << 31, 1, C.byref(cap)) == rafi.ERR_ARG
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes struct of the binding has the field offsets and size that a
+    C compiler gives the header's struct (compiled here with gcc)."""
+    import subprocess
+    structs = {"rafi_device_view": rafi.DeviceView, "rafi_ea_job": rafi.EAJob, "rafi_sl_job": rafi.SLJob,
+               "rafi_dt_job": rafi.DTJob, "rafi_ortho_view": rafi.ViewRec, "rafi_ea_scene": rafi.SceneRec,
+               "rafi_batch_tuning": rafi.BatchTuning, "rafi_stats": rafi.Stats, "rafi_profile": rafi.Profile}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "rafi.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, key, val = line.split()
+        got[(cname, key)] = int(val)
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == C.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
