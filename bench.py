@@ -351,6 +351,23 @@ def ea_adjoint(dev, reps):
     rafi.ea_backward_job(ctx, job, grad_image, grad)      # warm-up
     torch.cuda.synchronize()
     samples = int((r["klast"] - r["kfirst"]).clamp(min=0).sum().item())
+    # rays per backward workgroup (each workgroup flushes its brick's gradient
+    # once): the same gradient up to float32 summation order; keep the fastest
+    sweep = {}
+    for tile in (0, 8192, 16384, 32768):
+        job.bwd_tile_items = tile
+        rafi.ea_backward_job(ctx, job, grad_image, grad)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(2):
+            grad.zero_()
+            rafi.ea_backward_job(ctx, job, grad_image, grad)
+        b.record()
+        torch.cuda.synchronize()
+        sweep[tile] = round(a.elapsed_time(b) / 2, 4)
+    job.bwd_tile_items = min(sweep, key=sweep.get)
+    log(f"adjoint backward tile sweep (ms): {sweep}")
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     ev[0].record()
     for _ in range(reps):
@@ -368,7 +385,8 @@ def ea_adjoint(dev, reps):
     out = {"workload": "128^3, 4x4x4 bricks, 64 views x 256^2, L2 loss vs second volume",
            "forward_ms": round(fwd, 4), "backward_ms": round(bwd, 4), "backward_over_forward": round(bwd / fwd, 3),
            "samples": samples, "forward_samples_per_s": samples / (fwd * 1e-3),
-           "backward_samples_per_s": samples / (bwd * 1e-3)}
+           "backward_samples_per_s": samples / (bwd * 1e-3), "bwd_tile_items": job.bwd_tile_items,
+           "bwd_tile_sweep_ms": sweep}
     log(f"adjoint: forward {fwd:.3f} ms, backward {bwd:.3f} ms ({bwd / fwd:.2f}x)")
     return out
 

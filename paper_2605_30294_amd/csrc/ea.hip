@@ -463,8 +463,8 @@ int rafi_ea_backward(rafi_ctx *c, const rafi_ea_job *job, const float *grad_imag
     const uint32_t saved_tile = c->tile_items;
     int32_t r = 0;
     for (;;) {
-        // tiles sized so a round has a few hundred workgroups
-        if (use_lds) c->tile_items = staged_tile(c->n_slots);
+        // tiles sized so a round has a few hundred workgroups, unless the job sets them
+        if (use_lds) c->tile_items = job->bwd_tile_items ? job->bwd_tile_items : staged_tile(c->n_slots);
         uint64_t total = 0;
         rc = rafi_round(c, nullptr, &total);
         ++r;

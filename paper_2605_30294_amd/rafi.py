@@ -61,7 +61,8 @@ class EAJob(C.Structure):
                 ("klast", C.c_void_p), ("kfirst", C.c_void_p), ("visit_log", C.c_void_p),
                 ("visit_count", C.c_void_p), ("n", C.c_int32), ("grid", C.c_int32 * 3),
                 ("n_views", C.c_int32), ("width", C.c_int32), ("height", C.c_int32), ("dt", C.c_float),
-                ("c", C.c_float), ("visit_stride", C.c_int32), ("emit_mode", C.c_int32)]
+                ("c", C.c_float), ("visit_stride", C.c_int32), ("emit_mode", C.c_int32),
+                ("bwd_tile_items", C.c_uint32)]
 
 
 class SLJob(C.Structure):
@@ -309,7 +310,7 @@ def ea_job(volume: torch.Tensor, grid, views_dev: torch.Tensor, n_views: int, wi
     stride = 0 if visit_log is None else visit_log.shape[1]
     return EAJob(_dptr(volume), _dptr(views_dev), _dptr(image), _dptr(tau), _dptr(klast), _dptr(kfirst),
                  _dptr(visit_log), _dptr(visit_count), n, (C.c_int32 * 3)(*[int(g) for g in grid]), n_views,
-                 width, height, float(dt), float(c), stride, int(emit_mode))
+                 width, height, float(dt), float(c), stride, int(emit_mode), 0)
 
 
 def ea_raygen(ctx: Context, job: EAJob):
