@@ -354,7 +354,7 @@ def ea_adjoint(dev, reps):
     # rays per backward workgroup (each workgroup flushes its brick's gradient
     # once): the same gradient up to float32 summation order; keep the fastest
     sweep = {}
-    for tile in (0, 8192, 16384, 32768):
+    for tile in (0, 4096, 8192, 16384):
         job.bwd_tile_items = tile
         rafi.ea_backward_job(ctx, job, grad_image, grad)
         a = torch.cuda.Event(enable_timing=True)

@@ -271,10 +271,11 @@ typedef struct rafi_ea_job {
                                        (rafi_open). Same images either way; the order of rays
                                        within a domain queue is reproducible only when ordered.
                                        Other values: RAFI_ERR_ARG. */
-    uint32_t bwd_tile_items;        /* rays per workgroup of the LDS-privatised backward
-                                       (each workgroup flushes its brick's gradient once);
-                                       0: automatic. Same gradients up to float32 atomic
-                                       summation order. */
+    uint32_t bwd_tile_items;        /* LDS-privatised backward: 0 = one workgroup per CU, each
+                                       taking an equal contiguous slice of the queue and
+                                       flushing its brick's gradient once per brick it spans;
+                                       k > 0 = one workgroup per k-ray domain-pure tile. Same
+                                       gradients up to float32 atomic summation order. */
 } rafi_ea_job;
 
 /* Item size a context needs for the march (16 bytes: ray id, next sample,

@@ -237,13 +237,14 @@ bwd_march_kernel(rafi_device_view view, rafi_ea_job job, const float *__restrict
 // entries are added to the global gradient.
 constexpr int kBwdThreads = 1024;
 
-__global__ void __launch_bounds__(kBwdThreads)
-bwd_march_lds_kernel(rafi_device_view view, rafi_ea_job job, const float *__restrict__ grad_image,
-                     float *__restrict__ grad, uint32_t n_rays)
+// The backward of the queue items [first, last), all in domain d, by the whole
+// workgroup: zero the brick's gradient region in LDS, march every ray back
+// through the brick accumulating into it, then add its non-zero entries to
+// the global gradient.
+__device__ inline void bwd_segment(const rafi_device_view &view, const rafi_ea_job &job,
+                                   const float *__restrict__ grad_image, float *__restrict__ grad, uint32_t n_rays,
+                                   int32_t d, uint64_t first, uint64_t last, float *gl)
 {
-    extern __shared__ float gl[];
-    uint64_t tb, te;
-    const int32_t d = rafi_tile(view, rafi_xcd_block(blockIdx.x, gridDim.x), &tb, &te);
     const Geo g = job_geo(job);
     const Box box = ea::box_of(d, g);
     const int32_t ox = (int32_t)box.lo0 - 1, oy = (int32_t)box.lo1 - 1, oz = (int32_t)box.lo2 - 1;
@@ -253,7 +254,7 @@ bwd_march_lds_kernel(rafi_device_view view, rafi_ea_job job, const float *__rest
     __syncthreads();
 
     const float c = job.c;
-    for (uint64_t i = tb + threadIdx.x; i < te; i += blockDim.x) {
+    for (uint64_t i = first + threadIdx.x; i < last; i += blockDim.x) {
         Item it = static_cast<const Item *>(view.in_items)[i];
         if ((uint32_t)it.ray >= n_rays) {
             rafi_forward_t(view, i, it, RAFI_POISON);
@@ -332,6 +333,39 @@ bwd_march_lds_kernel(rafi_device_view view, rafi_ea_job job, const float *__rest
             const int64_t idx = (ox + lx) + (int64_t)g.n * ((oy + ly) + (int64_t)g.n * (oz + lz));
             unsafeAtomicAdd(&grad[idx], v);
         }
+    }
+    __syncthreads();  // the region is reused by the next segment
+}
+
+// One workgroup per domain-pure tile of the input queue.
+__global__ void __launch_bounds__(kBwdThreads)
+bwd_march_lds_kernel(rafi_device_view view, rafi_ea_job job, const float *__restrict__ grad_image,
+                     float *__restrict__ grad, uint32_t n_rays)
+{
+    extern __shared__ float gl[];
+    uint64_t tb, te;
+    const int32_t d = rafi_tile(view, rafi_xcd_block(blockIdx.x, gridDim.x), &tb, &te);
+    bwd_segment(view, job, grad_image, grad, n_rays, d, tb, te, gl);
+}
+
+// One workgroup per CU, each taking an equal contiguous slice of the queue
+// and working through the brick segments it spans (usually one or two), so
+// every CU is busy for the whole launch and the gradient region is flushed
+// about once per workgroup.
+__global__ void __launch_bounds__(kBwdThreads)
+bwd_march_range_kernel(rafi_device_view view, rafi_ea_job job, const float *__restrict__ grad_image,
+                       float *__restrict__ grad, uint32_t n_rays)
+{
+    extern __shared__ float gl[];
+    const uint64_t w = rafi_xcd_block(blockIdx.x, gridDim.x);
+    const uint64_t n = view.n_in;
+    uint64_t i = n * w / gridDim.x;
+    const uint64_t end = n * (w + 1) / gridDim.x;
+    while (i < end) {
+        const int32_t d = ea::find_domain(view.in_offsets, view.n_domains, i);
+        const uint64_t seg_end = min(end, view.in_offsets[d + 1]);
+        bwd_segment(view, job, grad_image, grad, n_rays, d, i, seg_end, gl);
+        i = seg_end;
     }
 }
 
@@ -460,11 +494,15 @@ int rafi_ea_backward(rafi_ctx *c, const rafi_ea_job *job, const float *grad_imag
     // LDS privatisation when the brick's region fits a workgroup's LDS
     const size_t lds = region_bytes(job);
     const bool use_lds = lds <= max_lds_bytes();
+    int cus = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        return RAFI_ERR_HIP;
     const uint32_t saved_tile = c->tile_items;
     int32_t r = 0;
     for (;;) {
-        // tiles sized so a round has a few hundred workgroups, unless the job sets them
-        if (use_lds) c->tile_items = job->bwd_tile_items ? job->bwd_tile_items : staged_tile(c->n_slots);
+        // tile-per-workgroup form only when the job sets a tile size
+        if (use_lds && job->bwd_tile_items) c->tile_items = job->bwd_tile_items;
         uint64_t total = 0;
         rc = rafi_round(c, nullptr, &total);
         ++r;
@@ -473,10 +511,15 @@ int rafi_ea_backward(rafi_ctx *c, const rafi_ea_job *job, const float *grad_imag
         if (r >= max_rounds) { rc = RAFI_ERR_MAX_ROUNDS; break; }
         rafi_view(c, &v);
         const int ph = prof_domain_begin(c);
-        if (use_lds)
+        if (use_lds && job->bwd_tile_items == 0) {
+            const uint64_t want = (v.n_in + kBwdThreads - 1) / kBwdThreads;
+            const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, cus));
+            hipLaunchKernelGGL(bwd_march_range_kernel, dim3(blocks), dim3(kBwdThreads), lds, c->stream, v, *job,
+                               grad_image, grad_volume, (uint32_t)rays);
+        } else if (use_lds) {
             hipLaunchKernelGGL(bwd_march_lds_kernel, dim3(v.n_tiles), dim3(kBwdThreads), lds, c->stream, v, *job,
                                grad_image, grad_volume, (uint32_t)rays);
-        else
+        } else
             hipLaunchKernelGGL(bwd_march_kernel, dim3((uint32_t)((v.n_in + 255) / 256)), dim3(256), 0, c->stream,
                                v, *job, grad_image, grad_volume, (uint32_t)rays);
         prof_domain_end(c, ph);

@@ -420,8 +420,9 @@ class EARender(torch.autograd.Function):
     Both run in the library; this class only moves tensors."""
 
     @staticmethod
-    def forward(fctx, volume, grid, views, dt, c, rafi_ctx):
+    def forward(fctx, volume, grid, views, dt, c, rafi_ctx, bwd_tile_items=0):
         out = ea_render(volume.contiguous(), grid, views, dt=dt, c=c, ctx=rafi_ctx, want_tau=True)
+        out["job"].bwd_tile_items = int(bwd_tile_items)
         fctx.keep = (out["ctx"], out["job"], out["views_dev"], out["tau"], out["klast"], out["kfirst"],
                      out["image"])
         fctx.save_for_backward(volume)
@@ -433,15 +434,17 @@ class EARender(torch.autograd.Function):
         rctx, job, _views, _tau, _klast, _kfirst, _image = fctx.keep
         grad = torch.zeros_like(volume)
         ea_backward_job(rctx, job, grad_image.contiguous().to(torch.float32), grad)
-        return grad, None, None, None, None, None
+        return grad, None, None, None, None, None, None
 
 
 def ea_render_differentiable(volume: torch.Tensor, grid, views: np.ndarray, dt=0.5, c=0.025,
-                             rafi_ctx: Context | None = None) -> torch.Tensor:
+                             rafi_ctx: Context | None = None, bwd_tile_items: int = 0) -> torch.Tensor:
+    """bwd_tile_items: 0 lets the backward spread the queue evenly over one
+    workgroup per CU; k > 0 gives each k-ray tile its own workgroup."""
     if rafi_ctx is None:
         n_rays = len(views) * int(views[0]["width"]) * int(views[0]["height"])
         rafi_ctx = Context(int(np.prod(grid)), EA_ITEM_BYTES, max(n_rays, 1))
-    return EARender.apply(volume, tuple(grid), views, float(dt), float(c), rafi_ctx)
+    return EARender.apply(volume, tuple(grid), views, float(dt), float(c), rafi_ctx, int(bwd_tile_items))
 
 
 # ---------------------------------------------------------------- batched ---

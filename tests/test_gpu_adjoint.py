@@ -19,12 +19,12 @@ C32 = float(np.float32(0.025))
 REL_L2 = 1e-4
 
 
-def _gpu_loss_grad(vol_np, tgt_np, grid, views, ray_mask=None):
+def _gpu_loss_grad(vol_np, tgt_np, grid, views, ray_mask=None, bwd_tile_items=0):
     dev = device()
     vol = torch.from_numpy(vol_np).to(dev).requires_grad_(True)
     with torch.no_grad():
         target = rafi.ea_render(torch.from_numpy(tgt_np).to(dev), grid, views, c=C32)["image"]
-    img = rafi.ea_render_differentiable(vol, grid, views, c=C32)
+    img = rafi.ea_render_differentiable(vol, grid, views, c=C32, bwd_tile_items=bwd_tile_items)
     r = img - target
     if ray_mask is not None:
         r = r * torch.from_numpy(ray_mask.astype(np.float32)).to(dev)
@@ -58,14 +58,16 @@ def _rel_l2(a, b):
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
 
 
+# bwd_tile_items 0: one workgroup per CU over slices of the queue; 512: one per 512-ray tile
+@pytest.mark.parametrize("bwd_tile", [0, 512])
 @pytest.mark.parametrize("n,grid,nv,w", [(32, (2, 2, 2), 3, 32), (32, (4, 4, 4), 2, 40), (48, (3, 1, 2), 2, 24),
                                          (48, (1, 1, 1), 2, 30)])   # last: brick too big for LDS (global path)
-def test_gradient_matches_float64_oracle(orc, n, grid, nv, w):
+def test_gradient_matches_float64_oracle(orc, n, grid, nv, w, bwd_tile):
     vol = W.blob_volume(n, 61)
     tgt = W.blob_volume(n, 62)
     views = W.random_views(nv, n, w, w, seed=63)
-    announce(f"adjoint n={n} grid={grid}")
-    L, g, target = _gpu_loss_grad(vol, tgt, grid, views)
+    announce(f"adjoint n={n} grid={grid} bwd_tile={bwd_tile}")
+    L, g, target = _gpu_loss_grad(vol, tgt, grid, views, bwd_tile_items=bwd_tile)
     L64, g64, _ = orc.ea_loss_grad(vol, grid, views, target, c=C32)
     assert abs(L - L64) <= 1e-4 * abs(L64)
     assert _rel_l2(g, g64) <= REL_L2, _rel_l2(g, g64)
