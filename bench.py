@@ -297,7 +297,7 @@ def delta_tracking(dev, reps):
     n, grid, B = 128, (4, 4, 4), 4
     vol = W.blob_volume(n, W.SEED_ADJ_VOLUME, device=dev)
     views = W.random_views(16, n, 256, 256)
-    kappa = 0.05
+    kappa = 0.5                      # about 0.3 scattering events per path in this volume
     smax = float(np.float32(kappa * float(vol.max().item())))
     counters = torch.zeros(2, dtype=torch.int64, device=dev)
     r = rafi.dt_render(vol, grid, views, kappa, smax, 0.8, (0.0, 0.6, 0.8), 1.0, B, 11)
@@ -319,7 +319,8 @@ def delta_tracking(dev, reps):
     points, hits = (int(v) // reps for v in counters.cpu().tolist())
     n_paths = 16 * 256 * 256
     ctx.close()
-    out = {"workload": "128^3 blobs, 4x4x4 domains, 16 views x 256^2 paths, <=4 scattering events + shadow rays",
+    out = {"workload": "128^3 blobs, 4x4x4 domains, 16 views x 256^2 paths, kappa 0.5, albedo 0.8, "
+                       "<=4 scattering events + shadow rays",
            "ms": round(ms, 4), "rounds": rounds, "paths_per_s": n_paths / (ms * 1e-3),
            "tentative_points": points, "real_collisions": hits, "points_per_s": points / (ms * 1e-3),
            "trace_ms": round(p["domain_ms"] / reps, 4), "split_ms": round(p["split_ms"] / reps, 4),
