@@ -96,8 +96,9 @@ def streamline_job(args, dev):
         b.record()
         torch.cuda.synchronize()
         layout_ms[name] = a.elapsed_time(b) / 2
-    layout = min(layout_ms, key=layout_ms.get)
-    log("streamline field layout (ms): " + ", ".join(f"{k} {v:.2f}" for k, v in layout_ms.items()))
+    layout = min(layout_ms, key=layout_ms.get) if args.field_layout == "auto" else args.field_layout
+    log("streamline field layout (ms): " + ", ".join(f"{k} {v:.2f}" for k, v in layout_ms.items())
+        + f"; using {layout}")
     job = rafi.sl_job(layouts[layout], grid, endpoint, steps, reason, h, max_steps, job.steps_per_visit, counters,
                       job.tail_items, job.refill_lanes)
     for _ in range(args.warmup):
@@ -474,6 +475,8 @@ def main():
     ap.add_argument("--refill-lanes", type=int, default=0,
                     help="persistent RK4 waves refill when this many lanes are idle (0: one thread per "
                          "particle); ignored when the schedule is autotuned")
+    ap.add_argument("--field-layout", default="auto", choices=["auto", "padded", "unpadded"],
+                    help="RK4 field with 16-byte (padded) or 12-byte voxels; auto keeps the faster")
     ap.add_argument("--steps-per-visit", type=int, default=-1,
                     help="RK4 steps a particle takes per domain visit before it is forwarded to its own "
                          "brick (0 = until it leaves, -1 = autotune with the tail threshold); results do "

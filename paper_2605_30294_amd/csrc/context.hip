@@ -29,8 +29,6 @@ __global__ void reset_kernel(uint64_t *offsets, uint32_t *tile_offsets, int32_t 
     if (threadIdx.x == 0) *dropped = 0;
 }
 
-__global__ void clear_dropped_kernel(unsigned long long *dropped) { *dropped = 0; }
-
 // Append-mode output: every slot RAFI_DONE, append counter zero.
 __global__ void open_append_kernel(int32_t *dest, uint64_t n, unsigned long long *append)
 {
@@ -67,6 +65,12 @@ int alloc_queues(rafi_ctx *c, uint64_t cap)
         (void)hipGetLastError();
         free_queues(c);
         return RAFI_ERR_OOM;
+    }
+    // the workspace head holds the fused scan's finished-tile counter: zero once
+    if (hipMemset(c->ws, 0, 256) != hipSuccess) {
+        (void)hipGetLastError();
+        free_queues(c);
+        return RAFI_ERR_HIP;
     }
     c->ws_bytes = p.bytes;
     c->cap = cap;
@@ -188,7 +192,7 @@ int rafi_create(int32_t n_domains, uint32_t item_bytes, uint64_t capacity, rafi_
     if (rc == RAFI_OK &&
         (hipMalloc(reinterpret_cast<void **>(&c->offsets), sizeof(uint64_t) * (n_domains + 1)) != hipSuccess ||
          hipMalloc(reinterpret_cast<void **>(&c->tile_offsets), sizeof(uint32_t) * (n_domains + 1)) != hipSuccess ||
-         hipMalloc(reinterpret_cast<void **>(&c->summary), sizeof(uint64_t) * 4) != hipSuccess ||
+         hipMalloc(reinterpret_cast<void **>(&c->summary), sizeof(uint64_t) * 8) != hipSuccess ||
          hipMalloc(reinterpret_cast<void **>(&c->dropped), sizeof(unsigned long long)) != hipSuccess ||
          hipMalloc(reinterpret_cast<void **>(&c->work), 2 * sizeof(unsigned long long)) != hipSuccess ||
          hipMemset(c->work, 0, 2 * sizeof(unsigned long long)) != hipSuccess ||
@@ -328,15 +332,12 @@ int rafi_round(rafi_ctx *c, uint64_t *counts, uint64_t *total)
             c->n_pending++;
         }
     }
+    // the split also moves the dropped-emit count into summary[4] and resets it
     int rc = split_run(p, c->buf[1], c->dest, c->buf[0], c->offsets, c->summary, c->tile_offsets,
-                       c->tile_items, c->ws, c->stream, evp);
+                       c->tile_items, c->ws, c->stream, evp, c->dropped, true);
     if (rc != RAFI_OK) return rc;
-    RAFI_HIP_CHECK(hipMemcpyAsync(c->host_summary, c->summary, sizeof(uint64_t) * 4, hipMemcpyDeviceToHost,
+    RAFI_HIP_CHECK(hipMemcpyAsync(c->host_summary, c->summary, sizeof(uint64_t) * 5, hipMemcpyDeviceToHost,
                                   c->stream));
-    RAFI_HIP_CHECK(hipMemcpyAsync(c->host_summary + 4, c->dropped, sizeof(uint64_t), hipMemcpyDeviceToHost,
-                                  c->stream));
-    hipLaunchKernelGGL(clear_dropped_kernel, dim3(1), dim3(1), 0, c->stream, c->dropped);
-    RAFI_LAUNCH_CHECK();
     if (counts) {
         uint64_t *tmp = static_cast<uint64_t *>(std::malloc(sizeof(uint64_t) * (c->D + 1)));
         if (!tmp) return RAFI_ERR_OOM;

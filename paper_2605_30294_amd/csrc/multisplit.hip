@@ -39,11 +39,10 @@ using dev::load_nt4;
 using dev::match_peers;
 
 // ---------------------------------------------------------------- pass 1 ---
-__global__ void __launch_bounds__(256)
-hist_kernel(const int32_t *__restrict__ dest, uint64_t n, int32_t D, uint32_t T, uint32_t n_tiles,
-            uint32_t *__restrict__ table)
+// Destination histogram of tile blockIdx.x into column blockIdx.x of table.
+__device__ inline void hist_tile(const int32_t *__restrict__ dest, uint64_t n, int32_t D, uint32_t T,
+                                 uint32_t n_tiles, uint32_t *__restrict__ table, uint32_t *h)
 {
-    extern __shared__ uint32_t h[];  // D + 2
     const uint32_t rows = (uint32_t)D + 2u;
     for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x) h[e] = 0;
     __syncthreads();
@@ -78,6 +77,14 @@ hist_kernel(const int32_t *__restrict__ dest, uint64_t n, int32_t D, uint32_t T,
     __syncthreads();
     for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x)
         table[(uint64_t)e * n_tiles + blockIdx.x] = h[e];
+}
+
+__global__ void __launch_bounds__(256)
+hist_kernel(const int32_t *__restrict__ dest, uint64_t n, int32_t D, uint32_t T, uint32_t n_tiles,
+            uint32_t *__restrict__ table)
+{
+    extern __shared__ uint32_t h[];  // D + 2
+    hist_tile(dest, n, D, T, n_tiles, table, h);
 }
 
 // ---------------------------------------------------------------- pass 2 ---
@@ -162,21 +169,23 @@ scan_apply_kernel(uint32_t *__restrict__ a, uint64_t M, const uint32_t *__restri
     }
 }
 
-// Offsets, summary and the tile table for domain-pure launches.
-__global__ void __launch_bounds__(1024)
-finalize_kernel(const uint32_t *__restrict__ table, uint32_t n_tiles, int32_t D, uint64_t n,
-                uint64_t *__restrict__ offsets, uint64_t *__restrict__ summary,
-                uint32_t *__restrict__ tile_offsets, uint32_t tile_items)
+// Offsets, summary and the tile table for domain-pure launches, from the
+// scanned table; with `dropped`, its count goes to summary[4] and is reset
+// (the domain kernels that add to it have completed).
+template <int NT>
+__device__ inline void finalize_body(const uint32_t *__restrict__ table, uint32_t n_tiles, int32_t D, uint64_t n,
+                                     uint64_t *__restrict__ offsets, uint64_t *__restrict__ summary,
+                                     uint32_t *__restrict__ tile_offsets, uint32_t tile_items,
+                                     unsigned long long *__restrict__ dropped, uint32_t *lds)
 {
-    __shared__ uint32_t lds[1024 / 64 + 1];
     auto row_start = [&](int32_t e) -> uint64_t {
         return n_tiles ? (uint64_t)table[(uint64_t)e * n_tiles] : 0ull;
     };
-    for (int32_t e = threadIdx.x; e <= D; e += blockDim.x) offsets[e] = row_start(e);
+    for (int32_t e = threadIdx.x; e <= D; e += NT) offsets[e] = row_start(e);
     const uint64_t total = row_start(D);
     const uint64_t done_end = n_tiles ? row_start(D + 1) : 0ull;
     // per-domain tile counts, scanned (each thread owns a contiguous run)
-    const int32_t per = (D + 1023) / 1024;
+    const int32_t per = (D + NT - 1) / NT;
     const int32_t e0 = threadIdx.x * per;
     uint32_t local = 0;
     for (int32_t e = e0; e < min(e0 + per, D); ++e) {
@@ -184,7 +193,7 @@ finalize_kernel(const uint32_t *__restrict__ table, uint32_t n_tiles, int32_t D,
         local += (uint32_t)((c + tile_items - 1) / tile_items);
     }
     uint32_t tot;
-    uint32_t run = block_excl_scan<1024>(local, lds, &tot);
+    uint32_t run = block_excl_scan<NT>(local, lds, &tot);
     if (tile_offsets) {
         for (int32_t e = e0; e < min(e0 + per, D); ++e) {
             tile_offsets[e] = run;
@@ -198,7 +207,62 @@ finalize_kernel(const uint32_t *__restrict__ table, uint32_t n_tiles, int32_t D,
         summary[1] = done_end - total;
         summary[2] = n - done_end;
         summary[3] = tot;
+        if (dropped) {
+            summary[4] = *dropped;
+            *dropped = 0;
+        }
     }
+}
+
+__global__ void __launch_bounds__(1024)
+finalize_kernel(const uint32_t *__restrict__ table, uint32_t n_tiles, int32_t D, uint64_t n,
+                uint64_t *__restrict__ offsets, uint64_t *__restrict__ summary,
+                uint32_t *__restrict__ tile_offsets, uint32_t tile_items, unsigned long long *__restrict__ dropped)
+{
+    __shared__ uint32_t lds[1024 / 64 + 1];
+    finalize_body<1024>(table, n_tiles, D, n, offsets, summary, tile_offsets, tile_items, dropped, lds);
+}
+
+// ----------------------------------------------------- passes 1 + 2 fused ---
+// For a small count table (M entries): every workgroup writes its tile's
+// histogram, and the last one to finish (a device-scope fence, then an atomic
+// count of finished tiles) scans the whole table in place and finalizes. No
+// workgroup waits for another. The counter is zero between launches: the last
+// workgroup resets it.
+constexpr uint64_t kFusedMaxM = 65536;
+
+__global__ void __launch_bounds__(256)
+hist_scan_kernel(const int32_t *__restrict__ dest, uint64_t n, int32_t D, uint32_t T, uint32_t n_tiles,
+                 uint32_t *__restrict__ table, uint64_t M, uint32_t *__restrict__ tiles_done,
+                 uint64_t *__restrict__ offsets, uint64_t *__restrict__ summary,
+                 uint32_t *__restrict__ tile_offsets, uint32_t tile_items, unsigned long long *__restrict__ dropped)
+{
+    extern __shared__ uint32_t h[];  // D + 2
+    __shared__ uint32_t lds[256 / 64 + 1];
+    __shared__ uint32_t is_last;
+    hist_tile(dest, n, D, T, n_tiles, table, h);
+    __threadfence();  // this tile's column is visible device-wide before it is counted
+    __syncthreads();
+    if (threadIdx.x == 0) is_last = atomicAdd(tiles_done, 1u) == n_tiles - 1 ? 1u : 0u;
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();  // every other column was made visible before its count
+    // exclusive scan of table[0, M) in place: thread t owns a contiguous run
+    const uint64_t per = (M + 255) / 256;
+    const uint64_t b0 = min((uint64_t)threadIdx.x * per, M), b1 = min(b0 + per, M);
+    uint32_t sum = 0;
+    for (uint64_t k = b0; k < b1; ++k) sum += table[k];
+    uint32_t tot;
+    uint32_t run = block_excl_scan<256>(sum, lds, &tot);
+    for (uint64_t k = b0; k < b1; ++k) {
+        const uint32_t v = table[k];
+        table[k] = run;
+        run += v;
+    }
+    __syncthreads();
+    __threadfence_block();
+    finalize_body<256>(table, n_tiles, D, n, offsets, summary, tile_offsets, tile_items, dropped, lds);
+    if (threadIdx.x == 0) atomicExch(tiles_done, 0u);
 }
 
 // ---------------------------------------------------------------- pass 3 ---
@@ -458,10 +522,12 @@ void finish_plan(SplitPlan &p)
     p.rows = (uint64_t)p.D + 2;
     p.M = p.rows * p.n_tiles;
     p.scan_blocks = (uint32_t)((p.M + kScanChunk - 1) / kScanChunk);
-    p.off_table = 0;
-    p.off_part = (p.M * 4 + 255) / 256 * 256;
-    p.off_dummy = p.off_part + ((uint64_t)std::max<uint32_t>(p.scan_blocks, 1) * 4 + 255) / 256 * 256;
-    p.bytes = p.off_dummy + 256;
+    // fixed head: the fused scan's finished-tile counter, then the dummy slot
+    p.off_done = 0;
+    p.off_dummy = 256;
+    p.off_table = 512;
+    p.off_part = p.off_table + (p.M * 4 + 255) / 256 * 256;
+    p.bytes = p.off_part + ((uint64_t)std::max<uint32_t>(p.scan_blocks, 1) * 4 + 255) / 256 * 256;
 }
 }  // namespace
 
@@ -501,28 +567,37 @@ SplitPlan split_plan_bound(uint64_t cap, int32_t D, uint32_t S)
 
 int split_run(const SplitPlan &p, const void *items, const int32_t *dest, void *out,
               uint64_t *offsets, uint64_t *summary, uint32_t *tile_offsets, uint32_t tile_items,
-              void *workspace, hipStream_t s, const SplitEvents *ev)
+              void *workspace, hipStream_t s, const SplitEvents *ev, unsigned long long *dropped, bool fused)
 {
     if (p.scan_blocks > (uint32_t)kPartMax) return RAFI_ERR_ARG;
     if (ev) RAFI_HIP_CHECK(hipEventRecord(ev->begin, s));
     uint32_t *table = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + p.off_table);
     uint32_t *part = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + p.off_part);
     uint32_t *dummy = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + p.off_dummy);
-    if (p.n_tiles > 0) {
-        hipLaunchKernelGGL(hist_kernel, dim3(p.n_tiles), dim3(256), sizeof(uint32_t) * p.rows, s,
-                           dest, p.n, p.D, p.tile, p.n_tiles, table);
+    uint32_t *tiles_done = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + p.off_done);
+    const uint32_t ti = tile_items ? tile_items : 1u;
+    if (p.n_tiles > 0 && fused && p.M <= kFusedMaxM) {
+        hipLaunchKernelGGL(hist_scan_kernel, dim3(p.n_tiles), dim3(256), sizeof(uint32_t) * p.rows, s, dest, p.n,
+                           p.D, p.tile, p.n_tiles, table, p.M, tiles_done, offsets, summary, tile_offsets, ti,
+                           dropped);
         RAFI_LAUNCH_CHECK();
-        hipLaunchKernelGGL(scan_reduce_kernel, dim3(p.scan_blocks), dim3(kScanThreads), 0, s, table,
-                           p.M, part);
-        hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kPartThreads), 0, s, part,
-                           p.scan_blocks);
-        hipLaunchKernelGGL(scan_apply_kernel, dim3(p.scan_blocks), dim3(kScanThreads), 0, s, table,
-                           p.M, part);
+    } else {
+        if (p.n_tiles > 0) {
+            hipLaunchKernelGGL(hist_kernel, dim3(p.n_tiles), dim3(256), sizeof(uint32_t) * p.rows, s,
+                               dest, p.n, p.D, p.tile, p.n_tiles, table);
+            RAFI_LAUNCH_CHECK();
+            hipLaunchKernelGGL(scan_reduce_kernel, dim3(p.scan_blocks), dim3(kScanThreads), 0, s, table,
+                               p.M, part);
+            hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kPartThreads), 0, s, part,
+                               p.scan_blocks);
+            hipLaunchKernelGGL(scan_apply_kernel, dim3(p.scan_blocks), dim3(kScanThreads), 0, s, table,
+                               p.M, part);
+            RAFI_LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, s, table, p.n_tiles, p.D, p.n,
+                           offsets, summary, tile_offsets, ti, dropped);
         RAFI_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, s, table, p.n_tiles, p.D, p.n,
-                       offsets, summary, tile_offsets, tile_items ? tile_items : 1u);
-    RAFI_LAUNCH_CHECK();
     if (ev) RAFI_HIP_CHECK(hipEventRecord(ev->before_scatter, s));
     if (p.n_tiles == 0) {
         if (ev) RAFI_HIP_CHECK(hipEventRecord(ev->end, s));
