@@ -103,6 +103,30 @@ __device__ inline void load16(const uint32_t *__restrict__ a, uint64_t M, uint64
     }
 }
 
+// a[base + k] = run + v[0] + ... + v[k - 1] for the thread's 16 entries
+__device__ inline void store16_excl(uint32_t *__restrict__ a, uint64_t M, uint64_t base, const uint32_t v[kScanPer],
+                                    uint32_t run)
+{
+    if (base + kScanPer <= M) {
+        uint4 *p = reinterpret_cast<uint4 *>(a + base);
+#pragma unroll
+        for (int k = 0; k < kScanPer / 4; ++k) {
+            uint4 q;
+            q.x = run; run += v[4 * k];
+            q.y = run; run += v[4 * k + 1];
+            q.z = run; run += v[4 * k + 2];
+            q.w = run; run += v[4 * k + 3];
+            p[k] = q;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            if (base + k < M) a[base + k] = run;
+            run += v[k];
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kScanThreads)
 scan_reduce_kernel(const uint32_t *__restrict__ a, uint64_t M, uint32_t *__restrict__ part)
 {
@@ -149,24 +173,7 @@ scan_apply_kernel(uint32_t *__restrict__ a, uint64_t M, const uint32_t *__restri
     for (int k = 0; k < kScanPer; ++k) s += v[k];
     uint32_t tot;
     uint32_t run = block_excl_scan<kScanThreads>(s, lds, &tot) + part[blockIdx.x];
-    if (base + kScanPer <= M) {
-        uint4 *p = reinterpret_cast<uint4 *>(a + base);
-#pragma unroll
-        for (int k = 0; k < kScanPer / 4; ++k) {
-            uint4 q;
-            q.x = run; run += v[4 * k];
-            q.y = run; run += v[4 * k + 1];
-            q.z = run; run += v[4 * k + 2];
-            q.w = run; run += v[4 * k + 3];
-            p[k] = q;
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < kScanPer; ++k) {
-            if (base + k < M) a[base + k] = run;
-            run += v[k];
-        }
-    }
+    store16_excl(a, M, base, v, run);
 }
 
 // Offsets, summary and the tile table for domain-pure launches, from the
@@ -223,46 +230,102 @@ finalize_kernel(const uint32_t *__restrict__ table, uint32_t n_tiles, int32_t D,
     finalize_body<1024>(table, n_tiles, D, n, offsets, summary, tile_offsets, tile_items, dropped, lds);
 }
 
+// True in exactly one workgroup of the launch: the last to get here. Each
+// workgroup's global writes before the call are visible to that one (device
+// fences around a count of finished workgroups). The counter is zero between
+// launches: the last workgroup resets it.
+__device__ inline bool last_workgroup(uint32_t *counter, uint32_t n_groups)
+{
+    __shared__ uint32_t is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) is_last = atomicAdd(counter, 1u) == n_groups - 1 ? 1u : 0u;
+    __syncthreads();
+    if (!is_last) return false;
+    __threadfence();
+    if (threadIdx.x == 0) atomicExch(counter, 0u);
+    return true;
+}
+
+// Exclusive scan of a[0, m) in place by one workgroup of NT threads, each
+// owning a contiguous run (m small).
+template <int NT>
+__device__ inline void block_scan_inplace(uint32_t *a, uint64_t m, uint32_t *lds)
+{
+    const uint64_t per = (m + NT - 1) / NT;
+    const uint64_t b0 = min((uint64_t)threadIdx.x * per, m), b1 = min(b0 + per, m);
+    uint32_t sum = 0;
+    for (uint64_t k = b0; k < b1; ++k) sum += a[k];
+    uint32_t tot;
+    uint32_t run = block_excl_scan<NT>(sum, lds, &tot);
+    for (uint64_t k = b0; k < b1; ++k) {
+        const uint32_t v = a[k];
+        a[k] = run;
+        run += v;
+    }
+    __syncthreads();
+}
+
 // ----------------------------------------------------- passes 1 + 2 fused ---
 // For a small count table (M entries): every workgroup writes its tile's
 // histogram, and the last one to finish (a device-scope fence, then an atomic
 // count of finished tiles) scans the whole table in place and finalizes. No
 // workgroup waits for another. The counter is zero between launches: the last
 // workgroup resets it.
-constexpr uint64_t kFusedMaxM = 65536;
+constexpr uint64_t kFusedMaxM = 4096;  // at most 16 entries per thread in the last workgroup's scan
 
 __global__ void __launch_bounds__(256)
 hist_scan_kernel(const int32_t *__restrict__ dest, uint64_t n, int32_t D, uint32_t T, uint32_t n_tiles,
-                 uint32_t *__restrict__ table, uint64_t M, uint32_t *__restrict__ tiles_done,
+                 uint32_t *__restrict__ table, uint64_t M, uint32_t *__restrict__ counter,
                  uint64_t *__restrict__ offsets, uint64_t *__restrict__ summary,
                  uint32_t *__restrict__ tile_offsets, uint32_t tile_items, unsigned long long *__restrict__ dropped)
 {
     extern __shared__ uint32_t h[];  // D + 2
     __shared__ uint32_t lds[256 / 64 + 1];
-    __shared__ uint32_t is_last;
     hist_tile(dest, n, D, T, n_tiles, table, h);
-    __threadfence();  // this tile's column is visible device-wide before it is counted
-    __syncthreads();
-    if (threadIdx.x == 0) is_last = atomicAdd(tiles_done, 1u) == n_tiles - 1 ? 1u : 0u;
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();  // every other column was made visible before its count
-    // exclusive scan of table[0, M) in place: thread t owns a contiguous run
-    const uint64_t per = (M + 255) / 256;
-    const uint64_t b0 = min((uint64_t)threadIdx.x * per, M), b1 = min(b0 + per, M);
-    uint32_t sum = 0;
-    for (uint64_t k = b0; k < b1; ++k) sum += table[k];
-    uint32_t tot;
-    uint32_t run = block_excl_scan<256>(sum, lds, &tot);
-    for (uint64_t k = b0; k < b1; ++k) {
-        const uint32_t v = table[k];
-        table[k] = run;
-        run += v;
-    }
-    __syncthreads();
-    __threadfence_block();
+    if (!last_workgroup(counter, n_tiles)) return;
+    block_scan_inplace<256>(table, M, lds);
     finalize_body<256>(table, n_tiles, D, n, offsets, summary, tile_offsets, tile_items, dropped, lds);
-    if (threadIdx.x == 0) atomicExch(tiles_done, 0u);
+}
+
+// Pass 2 in two launches: partial sums per chunk (the last workgroup scans the
+// partials), then the chunks with their offsets (the last workgroup finalizes).
+__global__ void __launch_bounds__(kScanThreads)
+scan_reduce_last_kernel(const uint32_t *__restrict__ a, uint64_t M, uint32_t *__restrict__ part,
+                        uint32_t *__restrict__ counter)
+{
+    __shared__ uint32_t lds[kScanThreads / 64 + 1];
+    uint32_t v[kScanPer];
+    load16(a, M, (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanPer, v);
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) s += v[k];
+    uint32_t tot;
+    block_excl_scan<kScanThreads>(s, lds, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+    if (!last_workgroup(counter, gridDim.x)) return;
+    block_scan_inplace<kScanThreads>(part, gridDim.x, lds);
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+scan_apply_last_kernel(uint32_t *__restrict__ a, uint64_t M, const uint32_t *__restrict__ part,
+                       uint32_t *__restrict__ counter, uint32_t n_tiles, int32_t D, uint64_t n,
+                       uint64_t *__restrict__ offsets, uint64_t *__restrict__ summary,
+                       uint32_t *__restrict__ tile_offsets, uint32_t tile_items,
+                       unsigned long long *__restrict__ dropped)
+{
+    __shared__ uint32_t lds[kScanThreads / 64 + 1];
+    uint32_t v[kScanPer];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanPer;
+    load16(a, M, base, v);
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) s += v[k];
+    uint32_t tot;
+    uint32_t run = block_excl_scan<kScanThreads>(s, lds, &tot) + part[blockIdx.x];
+    store16_excl(a, M, base, v, run);
+    if (!last_workgroup(counter, gridDim.x)) return;
+    finalize_body<kScanThreads>(a, n_tiles, D, n, offsets, summary, tile_offsets, tile_items, dropped, lds);
 }
 
 // ---------------------------------------------------------------- pass 3 ---
@@ -574,12 +637,20 @@ int split_run(const SplitPlan &p, const void *items, const int32_t *dest, void *
     uint32_t *table = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + p.off_table);
     uint32_t *part = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + p.off_part);
     uint32_t *dummy = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + p.off_dummy);
-    uint32_t *tiles_done = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + p.off_done);
+    uint32_t *counters = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + p.off_done);
     const uint32_t ti = tile_items ? tile_items : 1u;
     if (p.n_tiles > 0 && fused && p.M <= kFusedMaxM) {
         hipLaunchKernelGGL(hist_scan_kernel, dim3(p.n_tiles), dim3(256), sizeof(uint32_t) * p.rows, s, dest, p.n,
-                           p.D, p.tile, p.n_tiles, table, p.M, tiles_done, offsets, summary, tile_offsets, ti,
+                           p.D, p.tile, p.n_tiles, table, p.M, counters, offsets, summary, tile_offsets, ti,
                            dropped);
+        RAFI_LAUNCH_CHECK();
+    } else if (p.n_tiles > 0 && fused) {
+        hipLaunchKernelGGL(hist_kernel, dim3(p.n_tiles), dim3(256), sizeof(uint32_t) * p.rows, s,
+                           dest, p.n, p.D, p.tile, p.n_tiles, table);
+        hipLaunchKernelGGL(scan_reduce_last_kernel, dim3(p.scan_blocks), dim3(kScanThreads), 0, s, table, p.M,
+                           part, counters + 1);
+        hipLaunchKernelGGL(scan_apply_last_kernel, dim3(p.scan_blocks), dim3(kScanThreads), 0, s, table, p.M,
+                           part, counters + 2, p.n_tiles, p.D, p.n, offsets, summary, tile_offsets, ti, dropped);
         RAFI_LAUNCH_CHECK();
     } else {
         if (p.n_tiles > 0) {
