@@ -43,8 +43,8 @@ struct SplitPlan {
     uint64_t M = 0;          // rows * n_tiles table entries
     uint32_t scan_blocks = 0;
     uint64_t off_table = 0, off_part = 0, off_dummy = 0, off_done = 0, bytes = 0;  // workspace layout
-    // off_dummy: 16 bytes any scatter lane may overwrite; off_done: finished-workgroup
-    // counters [3] of the fused histogram / scan launches (zero between launches)
+    // off_dummy: 16 bytes any scatter lane may overwrite; off_done: the finished-tile
+    // counter of the fused histogram + scan launch (zero between launches)
 };
 
 SplitPlan split_plan(uint64_t n, int32_t D, uint32_t S);
@@ -62,8 +62,8 @@ struct SplitEvents {
 // with dropped: {total, done, bad, n_tiles_app, dropped}; tile_offsets
 // (optional): device u32 [D+1] built for tiles of tile_items. dropped
 // (optional): device counter read into summary[4] and reset. fused: allow the
-// launches whose last workgroup scans or finalizes (the workspace's first 16
-// bytes must be zero, as the context keeps them).
+// one-launch histogram + scan + finalize for small tables (the workspace's
+// first 4 bytes must be zero, as the context keeps them).
 int split_run(const SplitPlan &p, const void *items, const int32_t *dest, void *out,
               uint64_t *offsets, uint64_t *summary, uint32_t *tile_offsets, uint32_t tile_items,
               void *workspace, hipStream_t stream, const SplitEvents *ev = nullptr,

@@ -272,7 +272,8 @@ __device__ inline void block_scan_inplace(uint32_t *a, uint64_t m, uint32_t *lds
 // count of finished tiles) scans the whole table in place and finalizes. No
 // workgroup waits for another. The counter is zero between launches: the last
 // workgroup resets it.
-constexpr uint64_t kFusedMaxM = 4096;  // at most 16 entries per thread in the last workgroup's scan
+constexpr uint64_t kFusedMaxM = 4096;     // at most 16 entries per thread in the last workgroup's scan
+constexpr uint32_t kFusedMaxTiles = 512;  // workgroups, each with its own fence
 
 __global__ void __launch_bounds__(256)
 hist_scan_kernel(const int32_t *__restrict__ dest, uint64_t n, int32_t D, uint32_t T, uint32_t n_tiles,
@@ -286,46 +287,6 @@ hist_scan_kernel(const int32_t *__restrict__ dest, uint64_t n, int32_t D, uint32
     if (!last_workgroup(counter, n_tiles)) return;
     block_scan_inplace<256>(table, M, lds);
     finalize_body<256>(table, n_tiles, D, n, offsets, summary, tile_offsets, tile_items, dropped, lds);
-}
-
-// Pass 2 in two launches: partial sums per chunk (the last workgroup scans the
-// partials), then the chunks with their offsets (the last workgroup finalizes).
-__global__ void __launch_bounds__(kScanThreads)
-scan_reduce_last_kernel(const uint32_t *__restrict__ a, uint64_t M, uint32_t *__restrict__ part,
-                        uint32_t *__restrict__ counter)
-{
-    __shared__ uint32_t lds[kScanThreads / 64 + 1];
-    uint32_t v[kScanPer];
-    load16(a, M, (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanPer, v);
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) s += v[k];
-    uint32_t tot;
-    block_excl_scan<kScanThreads>(s, lds, &tot);
-    if (threadIdx.x == 0) part[blockIdx.x] = tot;
-    if (!last_workgroup(counter, gridDim.x)) return;
-    block_scan_inplace<kScanThreads>(part, gridDim.x, lds);
-}
-
-__global__ void __launch_bounds__(kScanThreads)
-scan_apply_last_kernel(uint32_t *__restrict__ a, uint64_t M, const uint32_t *__restrict__ part,
-                       uint32_t *__restrict__ counter, uint32_t n_tiles, int32_t D, uint64_t n,
-                       uint64_t *__restrict__ offsets, uint64_t *__restrict__ summary,
-                       uint32_t *__restrict__ tile_offsets, uint32_t tile_items,
-                       unsigned long long *__restrict__ dropped)
-{
-    __shared__ uint32_t lds[kScanThreads / 64 + 1];
-    uint32_t v[kScanPer];
-    const uint64_t base = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanPer;
-    load16(a, M, base, v);
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) s += v[k];
-    uint32_t tot;
-    uint32_t run = block_excl_scan<kScanThreads>(s, lds, &tot) + part[blockIdx.x];
-    store16_excl(a, M, base, v, run);
-    if (!last_workgroup(counter, gridDim.x)) return;
-    finalize_body<kScanThreads>(a, n_tiles, D, n, offsets, summary, tile_offsets, tile_items, dropped, lds);
 }
 
 // ---------------------------------------------------------------- pass 3 ---
@@ -639,18 +600,12 @@ int split_run(const SplitPlan &p, const void *items, const int32_t *dest, void *
     uint32_t *dummy = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + p.off_dummy);
     uint32_t *counters = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + p.off_done);
     const uint32_t ti = tile_items ? tile_items : 1u;
-    if (p.n_tiles > 0 && fused && p.M <= kFusedMaxM) {
+    // The fused launch costs one device-scope fence (an L2 write-back on this
+    // multi-XCD part) per workgroup: worth it only for small tables.
+    if (p.n_tiles > 0 && fused && p.M <= kFusedMaxM && p.n_tiles <= kFusedMaxTiles) {
         hipLaunchKernelGGL(hist_scan_kernel, dim3(p.n_tiles), dim3(256), sizeof(uint32_t) * p.rows, s, dest, p.n,
                            p.D, p.tile, p.n_tiles, table, p.M, counters, offsets, summary, tile_offsets, ti,
                            dropped);
-        RAFI_LAUNCH_CHECK();
-    } else if (p.n_tiles > 0 && fused) {
-        hipLaunchKernelGGL(hist_kernel, dim3(p.n_tiles), dim3(256), sizeof(uint32_t) * p.rows, s,
-                           dest, p.n, p.D, p.tile, p.n_tiles, table);
-        hipLaunchKernelGGL(scan_reduce_last_kernel, dim3(p.scan_blocks), dim3(kScanThreads), 0, s, table, p.M,
-                           part, counters + 1);
-        hipLaunchKernelGGL(scan_apply_last_kernel, dim3(p.scan_blocks), dim3(kScanThreads), 0, s, table, p.M,
-                           part, counters + 2, p.n_tiles, p.D, p.n, offsets, summary, tile_offsets, ti, dropped);
         RAFI_LAUNCH_CHECK();
     } else {
         if (p.n_tiles > 0) {
