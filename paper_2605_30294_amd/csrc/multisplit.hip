@@ -474,6 +474,13 @@ bool launch_staged(const SplitPlan &p, const uint32_t *items, const int32_t *des
         }
         return false;
     }
+    if (v == 0) {  // automatic: the wide shape when a tile fills at least one of its chunks
+        if constexpr (NW == 8) {
+            if (p.tile >= 8 * 8 * 64 && try_wide<8, 8, 8, false>(p, items, dest, table, out, dummy, s)) return true;
+        } else if constexpr (NW == 4) {
+            if (p.tile >= 8 * 12 * 64 && try_wide<4, 12, 8, false>(p, items, dest, table, out, dummy, s)) return true;
+        }
+    }
     if (v >= 8) {  // shapes 1-4 with double-buffered chunk loads
         if constexpr (NW == 8) {
             if (v == 8) return try_staged<8, 7, 4, 2, true>(p, items, dest, table, out, s);
