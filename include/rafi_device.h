@@ -26,6 +26,15 @@ __device__ inline uint64_t rafi_num_incoming(const rafi_device_view &v, int32_t 
     return v.in_offsets[d + 1] - v.in_offsets[d];
 }
 
+/* Number of items in the input queue, read on the device (the view's n_in
+ * is the host's copy). Domain kernels that the library launches before the
+ * host has read the forward step's total use this, with a grid sized for an
+ * upper bound; threads at or past it do nothing. */
+__device__ inline uint64_t rafi_queue_length(const rafi_device_view &v)
+{
+    return v.in_offsets[v.n_domains];
+}
+
 /* Pointer to input item i of domain d (getIncoming, Sec. 3.3). */
 __device__ inline const void *rafi_incoming(const rafi_device_view &v, int32_t d, uint64_t i)
 {

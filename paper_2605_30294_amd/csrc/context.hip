@@ -115,12 +115,21 @@ void give_event(rafi_ctx *c, hipEvent_t e)
 }
 }  // namespace
 
-int prof_resolve(rafi_ctx *c)
+int prof_resolve(rafi_ctx *c, bool wait)
 {
     if (c->n_pending == 0) return RAFI_OK;
-    RAFI_HIP_CHECK(hipStreamSynchronize(c->stream));
-    for (int i = 0; i < c->n_pending; ++i) {
-        rafi_ctx::Pending &p = c->pending[i];
+    if (wait) RAFI_HIP_CHECK(hipStreamSynchronize(c->stream));
+    int done = 0;
+    for (; done < c->n_pending; ++done) {
+        rafi_ctx::Pending &p = c->pending[done];
+        if (!wait) {  // only pairs whose last event has completed, in order
+            const hipError_t q = hipEventQuery(p.e[p.kind == 0 ? 2 : 1]);
+            if (q == hipErrorNotReady) {
+                (void)hipGetLastError();
+                break;
+            }
+            RAFI_HIP_CHECK(q);
+        }
         float a = 0.0f, b = 0.0f;
         if (p.kind == 0) {
             if (hipEventElapsedTime(&a, p.e[0], p.e[2]) == hipSuccess) c->prof.split_ms += a;
@@ -134,14 +143,15 @@ int prof_resolve(rafi_ctx *c)
         }
         for (int k = 0; k < (p.kind == 0 ? 3 : 2); ++k) give_event(c, p.e[k]);
     }
-    c->n_pending = 0;
+    for (int i = done; i < c->n_pending; ++i) c->pending[i - done] = c->pending[i];
+    c->n_pending -= done;
     return RAFI_OK;
 }
 
 int prof_domain_begin(rafi_ctx *c)
 {
     if (!c->prof_on) return -1;
-    if (c->n_pending >= rafi_ctx::kMaxPending && prof_resolve(c) != RAFI_OK) return -1;
+    if (c->n_pending >= rafi_ctx::kMaxPending && prof_resolve(c, true) != RAFI_OK) return -1;
     rafi_ctx::Pending &p = c->pending[c->n_pending];
     p.kind = 1;
     p.e[0] = take_event(c);
@@ -155,6 +165,60 @@ void prof_domain_end(rafi_ctx *c, int h)
 {
     if (h < 0) return;
     (void)hipEventRecord(c->pending[h].e[1], c->stream);
+}
+
+int round_enqueue(rafi_ctx *c)
+{
+    const SplitPlan p = split_plan(c->n_slots, c->D, c->S);
+    if (p.bytes > c->ws_bytes) return RAFI_ERR_STATE;
+    SplitEvents ev;
+    const SplitEvents *evp = nullptr;
+    if (c->prof_on && (c->n_pending < rafi_ctx::kMaxPending || prof_resolve(c, true) == RAFI_OK)) {
+        rafi_ctx::Pending &pp = c->pending[c->n_pending];
+        pp.kind = 0;
+        pp.slots = c->n_slots;
+        for (int k = 0; k < 3; ++k) pp.e[k] = take_event(c);
+        if (pp.e[0] && pp.e[1] && pp.e[2]) {
+            ev.begin = pp.e[0];
+            ev.before_scatter = pp.e[1];
+            ev.end = pp.e[2];
+            evp = &ev;
+            c->n_pending++;
+        }
+    }
+    // the split also moves the dropped-emit count into summary[4] and resets it
+    int rc = split_run(p, c->buf[1], c->dest, c->buf[0], c->offsets, c->summary, c->tile_offsets,
+                       c->tile_items, c->ws, c->stream, evp, c->dropped, true);
+    if (rc != RAFI_OK) return rc;
+    RAFI_HIP_CHECK(hipMemcpyAsync(c->host_summary, c->summary, sizeof(uint64_t) * 5, hipMemcpyDeviceToHost,
+                                  c->stream));
+    if (!c->summary_ready) RAFI_HIP_CHECK(hipEventCreateWithFlags(&c->summary_ready, hipEventDisableTiming));
+    RAFI_HIP_CHECK(hipEventRecord(c->summary_ready, c->stream));
+    return RAFI_OK;
+}
+
+int round_finish(rafi_ctx *c, uint64_t *total)
+{
+    RAFI_HIP_CHECK(hipEventSynchronize(c->summary_ready));
+    const uint64_t *h = c->host_summary;
+    if (c->n_pending) {
+        int rc = prof_resolve(c, false);
+        if (rc != RAFI_OK) return rc;
+    }
+    c->prof.split_items += c->prof_on ? h[0] : 0;
+    c->n_in = h[0];
+    c->n_slots = h[0];
+    c->n_tiles = (uint32_t)h[3];
+    c->stats.rounds++;
+    c->stats.forwarded += h[0];
+    c->stats.done += h[1];
+    c->stats.bad_dest += h[2];
+    c->stats.dropped += h[4];
+    c->stats.last_total = h[0];
+    if (total) *total = h[0];
+    if (h[2]) return RAFI_ERR_BAD_DEST;
+    if (h[4]) return RAFI_ERR_OVERFLOW;
+    return RAFI_OK;
 }
 
 }  // namespace rafi
@@ -223,6 +287,7 @@ void rafi_destroy(rafi_ctx *c)
     if (c->work) (void)hipFree(c->work);
     if (c->append) (void)hipFree(c->append);
     if (c->host_summary) (void)hipHostFree(c->host_summary);
+    if (c->summary_ready) (void)hipEventDestroy(c->summary_ready);
     for (int i = 0; i < c->n_pending; ++i)
         for (int k = 0; k < (c->pending[i].kind == 0 ? 3 : 2); ++k)
             if (c->pending[i].e[k]) (void)hipEventDestroy(c->pending[i].e[k]);
@@ -315,29 +380,8 @@ int rafi_emit_bulk(rafi_ctx *c, const void *items, const int32_t *dest, uint64_t
 int rafi_round(rafi_ctx *c, uint64_t *counts, uint64_t *total)
 {
     if (!c) return RAFI_ERR_ARG;
-    const SplitPlan p = split_plan(c->n_slots, c->D, c->S);
-    if (p.bytes > c->ws_bytes) return RAFI_ERR_STATE;
-    SplitEvents ev;
-    const SplitEvents *evp = nullptr;
-    if (c->prof_on && (c->n_pending < rafi_ctx::kMaxPending || prof_resolve(c) == RAFI_OK)) {
-        rafi_ctx::Pending &pp = c->pending[c->n_pending];
-        pp.kind = 0;
-        pp.slots = c->n_slots;
-        for (int k = 0; k < 3; ++k) pp.e[k] = take_event(c);
-        if (pp.e[0] && pp.e[1] && pp.e[2]) {
-            ev.begin = pp.e[0];
-            ev.before_scatter = pp.e[1];
-            ev.end = pp.e[2];
-            evp = &ev;
-            c->n_pending++;
-        }
-    }
-    // the split also moves the dropped-emit count into summary[4] and resets it
-    int rc = split_run(p, c->buf[1], c->dest, c->buf[0], c->offsets, c->summary, c->tile_offsets,
-                       c->tile_items, c->ws, c->stream, evp, c->dropped, true);
+    int rc = round_enqueue(c);
     if (rc != RAFI_OK) return rc;
-    RAFI_HIP_CHECK(hipMemcpyAsync(c->host_summary, c->summary, sizeof(uint64_t) * 5, hipMemcpyDeviceToHost,
-                                  c->stream));
     if (counts) {
         uint64_t *tmp = static_cast<uint64_t *>(std::malloc(sizeof(uint64_t) * (c->D + 1)));
         if (!tmp) return RAFI_ERR_OOM;
@@ -348,30 +392,10 @@ int rafi_round(rafi_ctx *c, uint64_t *counts, uint64_t *total)
             for (int32_t d = 0; d < c->D; ++d) counts[d] = tmp[d + 1] - tmp[d];
         std::free(tmp);
         RAFI_HIP_CHECK(e);
-    } else {
-        RAFI_HIP_CHECK(hipStreamSynchronize(c->stream));
     }
-    const uint64_t *h = c->host_summary;
-    if (evp) c->prof.split_items += h[0];
-    if (c->n_pending) {
-        rc = prof_resolve(c);
-        if (rc != RAFI_OK) return rc;
-    }
-    c->n_in = h[0];
-    c->n_slots = h[0];
-    c->n_tiles = (uint32_t)h[3];
-    c->stats.rounds++;
-    c->stats.forwarded += h[0];
-    c->stats.done += h[1];
-    c->stats.bad_dest += h[2];
-    c->stats.dropped += h[4];
-    c->stats.last_total = h[0];
-    if (total) *total = h[0];
-    rc = ctx_fill_poison(c, c->n_slots);
-    if (rc != RAFI_OK) return rc;
-    if (h[2]) return RAFI_ERR_BAD_DEST;
-    if (h[4]) return RAFI_ERR_OVERFLOW;
-    return RAFI_OK;
+    rc = round_finish(c, total);
+    const int fill = ctx_fill_poison(c, c->n_slots);
+    return rc != RAFI_OK ? rc : fill;
 }
 
 int rafi_copy_queue(const rafi_ctx *c, void *items_dst, uint64_t *offsets_dst)
@@ -388,7 +412,7 @@ int rafi_copy_queue(const rafi_ctx *c, void *items_dst, uint64_t *offsets_dst)
 int rafi_set_profiling(rafi_ctx *c, int32_t on)
 {
     if (!c) return RAFI_ERR_ARG;
-    int rc = prof_resolve(c);
+    int rc = prof_resolve(c, true);
     if (rc != RAFI_OK) return rc;
     c->prof_on = on ? 1 : 0;
     if (on) c->prof = rafi_profile{};
@@ -398,7 +422,7 @@ int rafi_set_profiling(rafi_ctx *c, int32_t on)
 int rafi_get_profile(rafi_ctx *c, rafi_profile *out)
 {
     if (!c || !out) return RAFI_ERR_ARG;
-    int rc = prof_resolve(c);
+    int rc = prof_resolve(c, true);
     if (rc != RAFI_OK) return rc;
     *out = c->prof;
     return RAFI_OK;

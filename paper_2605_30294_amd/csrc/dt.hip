@@ -183,8 +183,12 @@ dt_raygen_kernel(rafi_device_view view, rafi_dt_job job, uint64_t n_paths)
 __global__ void __launch_bounds__(256)
 dt_trace_kernel(rafi_device_view view, rafi_dt_job job, uint64_t n_paths)
 {
-    const uint64_t i = rafi_xcd_block(blockIdx.x, gridDim.x) * (uint64_t)blockDim.x + threadIdx.x;
-    const bool live = i < view.n_in;
+    // the grid may be sized for an upper bound: number the live workgroups only
+    const uint64_t n_in = rafi_queue_length(view);
+    const uint32_t nb = (uint32_t)((n_in + blockDim.x - 1) / blockDim.x);
+    if (blockIdx.x >= nb) return;  // whole workgroups: no lane is left out of the counter sums
+    const uint64_t i = rafi_xcd_block(blockIdx.x, nb) * (uint64_t)blockDim.x + threadIdx.x;
+    const bool live = i < n_in;
     uint32_t points = 0, hits = 0;
     if (live) {
         const ea::Geo g = ea::make_geo(job.n, job.grid);
@@ -346,20 +350,25 @@ int rafi_dt_render(rafi_ctx *c, const rafi_dt_job *job, int32_t max_rounds, int3
     if (max_rounds < 1) return RAFI_ERR_ARG;
     int rc = rafi_dt_raygen(c, job);
     if (rc != RAFI_OK) return rc;
-    int32_t r = 0;
-    for (;;) {
-        uint64_t total = 0;
-        rc = rafi_round(c, nullptr, &total);
-        ++r;
-        if (rc != RAFI_OK) break;
-        if (total == 0) break;
-        if (r >= max_rounds) { rc = RAFI_ERR_MAX_ROUNDS; break; }
-        rc = rafi_dt_trace(c, job);
-        if (rc != RAFI_OK) break;
-    }
-    if (rounds) *rounds = r;
+    const uint64_t paths = n_paths_of(job);
+    // each trace launch is enqueued one step ahead of the host (run_rounds)
+    auto launch = [&](uint64_t bound) -> int {
+        if (2 * bound > c->cap) return RAFI_ERR_ARG;
+        const int orc = rafi_open(c, 2 * bound, RAFI_SLOTS_ORDERED);
+        if (orc != RAFI_OK) return orc;
+        rafi_device_view v;
+        rafi_view(c, &v);
+        v.n_in = bound;
+        const int ph = prof_domain_begin(c);
+        if (bound)
+            hipLaunchKernelGGL(dt_trace_kernel, dim3((uint32_t)((bound + 255) / 256)), dim3(256), 0, c->stream, v,
+                               *job, paths);
+        prof_domain_end(c, ph);
+        RAFI_LAUNCH_CHECK();
+        return RAFI_OK;
+    };
+    rc = run_rounds(c, max_rounds, rounds, nullptr, launch, [](uint64_t n) { return 2 * n; });
     if (rc == RAFI_OK && job->image) {
-        const uint64_t paths = n_paths_of(job);
         if (paths)
             hipLaunchKernelGGL(dt_resolve_kernel, dim3((uint32_t)((paths + 255) / 256)), dim3(256), 0, c->stream,
                                *job, paths);

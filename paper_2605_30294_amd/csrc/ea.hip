@@ -87,8 +87,12 @@ __device__ inline void emit_ray(const rafi_device_view &view, const rafi_ea_job 
 __global__ void __launch_bounds__(256)
 march_kernel(rafi_device_view view, rafi_ea_job job, uint32_t n_rays)
 {
-    const uint64_t i = rafi_xcd_block(blockIdx.x, gridDim.x) * (uint64_t)blockDim.x + threadIdx.x;
-    if (i >= view.n_in) return;
+    // the grid may be sized for an upper bound: number the live workgroups only
+    const uint64_t n_in = rafi_queue_length(view);
+    const uint32_t nb = (uint32_t)((n_in + blockDim.x - 1) / blockDim.x);
+    if (blockIdx.x >= nb) return;
+    const uint64_t i = rafi_xcd_block(blockIdx.x, nb) * (uint64_t)blockDim.x + threadIdx.x;
+    if (i >= n_in) return;
     const Geo g = job_geo(job);
     const int32_t d = ea::find_domain(view.in_offsets, view.n_domains, i);
     Item it = static_cast<const Item *>(view.in_items)[i];
@@ -182,8 +186,12 @@ __global__ void __launch_bounds__(256)
 bwd_march_kernel(rafi_device_view view, rafi_ea_job job, const float *__restrict__ grad_image,
                  float *__restrict__ grad, uint32_t n_rays)
 {
-    const uint64_t i = rafi_xcd_block(blockIdx.x, gridDim.x) * (uint64_t)blockDim.x + threadIdx.x;
-    if (i >= view.n_in) return;
+    // the grid may be sized for an upper bound: number the live workgroups only
+    const uint64_t n_in = rafi_queue_length(view);
+    const uint32_t nb = (uint32_t)((n_in + blockDim.x - 1) / blockDim.x);
+    if (blockIdx.x >= nb) return;
+    const uint64_t i = rafi_xcd_block(blockIdx.x, nb) * (uint64_t)blockDim.x + threadIdx.x;
+    if (i >= n_in) return;
     const Geo g = job_geo(job);
     const int32_t d = ea::find_domain(view.in_offsets, view.n_domains, i);
     const Box box = ea::box_of(d, g);
@@ -358,7 +366,7 @@ bwd_march_range_kernel(rafi_device_view view, rafi_ea_job job, const float *__re
 {
     extern __shared__ float gl[];
     const uint64_t w = rafi_xcd_block(blockIdx.x, gridDim.x);
-    const uint64_t n = view.n_in;
+    const uint64_t n = rafi_queue_length(view);
     uint64_t i = n * w / gridDim.x;
     const uint64_t end = n * (w + 1) / gridDim.x;
     while (i < end) {
@@ -455,26 +463,40 @@ int rafi_ea_render(rafi_ctx *c, const rafi_ea_job *job, int32_t max_rounds, int3
     if (!job_ok(c, job) || max_rounds < 1) return RAFI_ERR_ARG;
     int rc = rafi_ea_raygen(c, job);
     if (rc != RAFI_OK) return rc;
-    // The march kernel is chosen by the context's tile size (see rafi_ea_march);
-    // the default tiles select the gather kernel, which measured faster than
-    // the LDS-staged one on coherent view batches.
-    int32_t r = 0;
-    for (;;) {
-        uint64_t total = 0;
-        rc = rafi_round(c, nullptr, &total);
-        ++r;
-        if (rc != RAFI_OK) break;
-        if (total == 0) break;
-        if (r >= max_rounds) { rc = RAFI_ERR_MAX_ROUNDS; break; }
-        if (job->emit_mode == RAFI_SLOTS_APPEND) {
-            rc = rafi_open(c, c->n_slots, RAFI_SLOTS_APPEND);
-            if (rc != RAFI_OK) break;
+    // Tiles of 512 or more (rafi_set_tile_items) select the LDS-staged march,
+    // whose grid is the host's tile count: rounds then wait for each total.
+    if (c->tile_items >= 512 && region_bytes(job) <= max_lds_bytes()) {
+        int32_t r = 0;
+        for (;;) {
+            uint64_t total = 0;
+            rc = rafi_round(c, nullptr, &total);
+            ++r;
+            if (rc != RAFI_OK || total == 0) break;
+            if (r >= max_rounds) { rc = RAFI_ERR_MAX_ROUNDS; break; }
+            if (job->emit_mode == RAFI_SLOTS_APPEND && (rc = rafi_open(c, c->n_slots, RAFI_SLOTS_APPEND)) != RAFI_OK)
+                break;
+            if ((rc = rafi_ea_march(c, job)) != RAFI_OK) break;
         }
-        rc = rafi_ea_march(c, job);
-        if (rc != RAFI_OK) break;
+        if (rounds) *rounds = r;
+        return rc;
     }
-    if (rounds) *rounds = r;
-    return rc;
+    // The gather march, launched one step ahead of the host (run_rounds).
+    const uint32_t n_rays = n_rays_of(job);
+    auto launch = [&](uint64_t bound) -> int {
+        const int orc = rafi_open(c, bound, job->emit_mode);
+        if (orc != RAFI_OK) return orc;
+        rafi_device_view v;
+        rafi_view(c, &v);
+        v.n_in = bound;
+        const int ph = prof_domain_begin(c);
+        if (bound)
+            hipLaunchKernelGGL(march_kernel, dim3((uint32_t)((bound + 255) / 256)), dim3(256), 0, c->stream, v,
+                               *job, n_rays);
+        prof_domain_end(c, ph);
+        RAFI_LAUNCH_CHECK();
+        return RAFI_OK;
+    };
+    return run_rounds(c, max_rounds, rounds, nullptr, launch, [](uint64_t n) { return n; });
 }
 
 int rafi_ea_backward(rafi_ctx *c, const rafi_ea_job *job, const float *grad_image, float *grad_volume,
@@ -498,37 +520,51 @@ int rafi_ea_backward(rafi_ctx *c, const rafi_ea_job *job, const float *grad_imag
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
         return RAFI_ERR_HIP;
-    const uint32_t saved_tile = c->tile_items;
-    int32_t r = 0;
-    for (;;) {
-        // tile-per-workgroup form only when the job sets a tile size
-        if (use_lds && job->bwd_tile_items) c->tile_items = job->bwd_tile_items;
-        uint64_t total = 0;
-        rc = rafi_round(c, nullptr, &total);
-        ++r;
-        if (rc != RAFI_OK) break;
-        if (total == 0) break;
-        if (r >= max_rounds) { rc = RAFI_ERR_MAX_ROUNDS; break; }
-        rafi_view(c, &v);
-        const int ph = prof_domain_begin(c);
-        if (use_lds && job->bwd_tile_items == 0) {
-            const uint64_t want = (v.n_in + kBwdThreads - 1) / kBwdThreads;
-            const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, cus));
-            hipLaunchKernelGGL(bwd_march_range_kernel, dim3(blocks), dim3(kBwdThreads), lds, c->stream, v, *job,
-                               grad_image, grad_volume, (uint32_t)rays);
-        } else if (use_lds) {
+    if (use_lds && job->bwd_tile_items) {  // tile per workgroup: the host's tile count sizes the grid
+        const uint32_t saved_tile = c->tile_items;
+        c->tile_items = job->bwd_tile_items;
+        int32_t r = 0;
+        for (;;) {
+            uint64_t total = 0;
+            rc = rafi_round(c, nullptr, &total);
+            ++r;
+            if (rc != RAFI_OK || total == 0) break;
+            if (r >= max_rounds) { rc = RAFI_ERR_MAX_ROUNDS; break; }
+            rafi_view(c, &v);
+            const int ph = prof_domain_begin(c);
             hipLaunchKernelGGL(bwd_march_lds_kernel, dim3(v.n_tiles), dim3(kBwdThreads), lds, c->stream, v, *job,
                                grad_image, grad_volume, (uint32_t)rays);
-        } else
-            hipLaunchKernelGGL(bwd_march_kernel, dim3((uint32_t)((v.n_in + 255) / 256)), dim3(256), 0, c->stream,
-                               v, *job, grad_image, grad_volume, (uint32_t)rays);
-        prof_domain_end(c, ph);
-        rc = hipGetLastError() == hipSuccess ? RAFI_OK : RAFI_ERR_HIP;
-        if (rc != RAFI_OK) break;
+            prof_domain_end(c, ph);
+            rc = hipGetLastError() == hipSuccess ? RAFI_OK : RAFI_ERR_HIP;
+            if (rc != RAFI_OK) break;
+        }
+        c->tile_items = saved_tile;
+        if (rounds) *rounds = r;
+        return rc;
     }
-    c->tile_items = saved_tile;
-    if (rounds) *rounds = r;
-    return rc;
+    // one workgroup per CU over slices of the queue (or global atomics when the
+    // brick's region does not fit), launched one step ahead of the host
+    auto launch = [&](uint64_t bound) -> int {
+        const int orc = rafi_open(c, bound, RAFI_SLOTS_ORDERED);
+        if (orc != RAFI_OK) return orc;
+        rafi_device_view lv;
+        rafi_view(c, &lv);
+        lv.n_in = bound;
+        const int ph = prof_domain_begin(c);
+        if (bound && use_lds) {
+            const uint64_t want = (bound + kBwdThreads - 1) / kBwdThreads;
+            const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, cus));
+            hipLaunchKernelGGL(bwd_march_range_kernel, dim3(blocks), dim3(kBwdThreads), lds, c->stream, lv, *job,
+                               grad_image, grad_volume, (uint32_t)rays);
+        } else if (bound) {
+            hipLaunchKernelGGL(bwd_march_kernel, dim3((uint32_t)((bound + 255) / 256)), dim3(256), 0, c->stream,
+                               lv, *job, grad_image, grad_volume, (uint32_t)rays);
+        }
+        prof_domain_end(c, ph);
+        RAFI_LAUNCH_CHECK();
+        return RAFI_OK;
+    };
+    return run_rounds(c, max_rounds, rounds, nullptr, launch, [](uint64_t n) { return n; });
 }
 
 }  // extern "C"

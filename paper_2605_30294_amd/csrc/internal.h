@@ -90,6 +90,7 @@ struct rafi_ctx {
     unsigned long long *work = nullptr;
     unsigned long long *append = nullptr;  // slots taken by rafi_emit since the last rafi_open
     uint64_t *host_summary = nullptr;   // pinned [8]
+    hipEvent_t summary_ready = nullptr; // recorded after each round's summary copy
     void *ws = nullptr;
     uint64_t ws_bytes = 0;
     uint64_t n_in = 0, n_slots = 0;
@@ -118,6 +119,50 @@ int ctx_fill_poison(rafi_ctx *ctx, uint64_t n);
 // to pass to prof_domain_end after the launch.
 int prof_domain_begin(rafi_ctx *ctx);
 void prof_domain_end(rafi_ctx *ctx, int h);
-// Resolve all pending event pairs (synchronises the context stream).
-int prof_resolve(rafi_ctx *ctx);
+// Resolve pending event pairs: all of them after synchronising the context
+// stream (wait), or only those already complete, in order.
+int prof_resolve(rafi_ctx *ctx, bool wait);
+// The two halves of rafi_round: enqueue the split of the current output slots
+// and the copy of its summary to the host (no wait); then wait for that copy
+// only and take the results (queue length, statistics). Work enqueued between
+// the two keeps running. round_finish does not touch the output slots.
+int round_enqueue(rafi_ctx *ctx);
+int round_finish(rafi_ctx *ctx, uint64_t *total);
+
+// The round loop with the host one step ahead of the device. After a forward
+// step is enqueued, the next domain launch is enqueued at once as
+// launch(bound), with bound >= the queue length that step will produce (the
+// kernel reads the exact length on the device), and only then does the host
+// wait for the step's total; so the device never waits for the host between
+// the two. slots(n): output slots a launch over n queued items writes. The
+// last launch, over an empty queue, does nothing. *rounds: forward steps;
+// *forwarded: items they delivered.
+template <typename Launch, typename Slots>
+int run_rounds(rafi_ctx *c, int32_t max_rounds, int32_t *rounds, uint64_t *forwarded, Launch launch, Slots slots)
+{
+    int32_t r = 0;
+    uint64_t fwd = 0;
+    int rc = round_enqueue(c);
+    uint64_t bound = c->n_slots;
+    while (rc == RAFI_OK) {
+        ++r;
+        const bool more = r < max_rounds;
+        const int lrc = more ? launch(bound) : RAFI_OK;
+        uint64_t total = 0;
+        rc = round_finish(c, &total);
+        fwd += total;
+        if (rc == RAFI_OK) rc = lrc;
+        if (rc != RAFI_OK || total == 0) break;
+        if (!more) {
+            rc = RAFI_ERR_MAX_ROUNDS;
+            break;
+        }
+        c->n_slots = slots(total);
+        bound = c->n_slots;
+        rc = round_enqueue(c);
+    }
+    if (rounds) *rounds = r;
+    if (forwarded) *forwarded = fwd;
+    return rc;
+}
 }

@@ -177,8 +177,12 @@ template <int FW>
 __global__ void __launch_bounds__(256)
 advance_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids)
 {
-    const uint64_t i = rafi_xcd_block(blockIdx.x, gridDim.x) * (uint64_t)blockDim.x + threadIdx.x;
-    if (i >= view.n_in) return;
+    // the grid may be sized for an upper bound: number the live workgroups only
+    const uint64_t n_in = rafi_queue_length(view);
+    const uint32_t nb = (uint32_t)((n_in + blockDim.x - 1) / blockDim.x);
+    if (blockIdx.x >= nb) return;
+    const uint64_t i = rafi_xcd_block(blockIdx.x, nb) * (uint64_t)blockDim.x + threadIdx.x;
+    if (i >= n_in) return;
     const Geo g = make_geo(job);
     const int32_t d = find_domain(view.in_offsets, view.n_domains, i);
     const int32_t bx = d % g.g0, by = (d / g.g0) % g.g1, bz = d / (g.g0 * g.g1);
@@ -194,7 +198,7 @@ advance_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids)
     }
     int32_t steps = job.steps[it.id];
     const float h = job.h, hh = job.h * 0.5f, h6 = (float)((double)job.h / 6.0);
-    const bool capped = job.steps_per_visit > 0 && view.n_in > job.tail_items;
+    const bool capped = job.steps_per_visit > 0 && n_in > job.tail_items;
     const int32_t cap = capped ? job.steps_per_visit : 0x7fffffff;
     float x = it.x, y = it.y, z = it.z;
     int32_t dest = d, why = 0;
@@ -249,7 +253,7 @@ advance_persistent_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids
 {
     const Geo g = make_geo(job);
     const typename Voxel<FW>::type *__restrict__ F = reinterpret_cast<const typename Voxel<FW>::type *>(job.field4);
-    const uint64_t n = view.n_in;
+    const uint64_t n = rafi_queue_length(view);
     const int lane = threadIdx.x & 63;
     const uint64_t lanes_below = (1ull << lane) - 1;
     const float h = job.h, hh = job.h * 0.5f, h6 = (float)((double)job.h / 6.0);
@@ -389,6 +393,35 @@ bool job_ok(const rafi_ctx *c, const rafi_sl_job *j)
     return c->D == j->grid[0] * j->grid[1] * j->grid[2] && c->S == RAFI_SL_ITEM_BYTES;
 }
 
+// One domain launch over the queue in view v; v.n_in sizes the grid and may
+// be an upper bound (the kernels read the queue length on the device).
+int launch_advance(rafi_ctx *c, const rafi_sl_job *job, const rafi_device_view &v)
+{
+    const uint64_t one_per_item = (v.n_in + kSLThreads - 1) / kSLThreads;
+    const uint32_t resident = job->refill_lanes > 0 ? persistent_blocks() : 1;
+    if (!resident) return RAFI_ERR_HIP;
+    const int ph = prof_domain_begin(c);
+    if (v.n_in && job->refill_lanes > 0) {
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>(one_per_item, resident);
+        if (job->field_stride == 3)
+            hipLaunchKernelGGL(advance_persistent_kernel<3>, dim3(blocks), dim3(kSLThreads), 0, c->stream, v, *job,
+                               c->wave_slots, c->work, blocks * (kSLThreads / 64));
+        else
+            hipLaunchKernelGGL(advance_persistent_kernel<4>, dim3(blocks), dim3(kSLThreads), 0, c->stream, v, *job,
+                               c->wave_slots, c->work, blocks * (kSLThreads / 64));
+    } else if (v.n_in) {
+        if (job->field_stride == 3)
+            hipLaunchKernelGGL(advance_kernel<3>, dim3((uint32_t)one_per_item), dim3(kSLThreads), 0, c->stream, v,
+                               *job, c->wave_slots);
+        else
+            hipLaunchKernelGGL(advance_kernel<4>, dim3((uint32_t)one_per_item), dim3(kSLThreads), 0, c->stream, v,
+                               *job, c->wave_slots);
+    }
+    prof_domain_end(c, ph);
+    RAFI_LAUNCH_CHECK();
+    return RAFI_OK;
+}
+
 }  // namespace
 }  // namespace rafi
 
@@ -426,29 +459,7 @@ int rafi_sl_advance(rafi_ctx *c, const rafi_sl_job *job)
     if (!job_ok(c, job)) return RAFI_ERR_ARG;
     rafi_device_view v;
     rafi_view(c, &v);
-    const uint64_t one_per_item = (v.n_in + kSLThreads - 1) / kSLThreads;
-    const uint32_t resident = job->refill_lanes > 0 ? persistent_blocks() : 1;
-    if (!resident) return RAFI_ERR_HIP;
-    const int ph = prof_domain_begin(c);
-    if (v.n_in && job->refill_lanes > 0) {
-        const uint32_t blocks = (uint32_t)std::min<uint64_t>(one_per_item, resident);
-        if (job->field_stride == 3)
-            hipLaunchKernelGGL(advance_persistent_kernel<3>, dim3(blocks), dim3(kSLThreads), 0, c->stream, v, *job,
-                               c->wave_slots, c->work, blocks * (kSLThreads / 64));
-        else
-            hipLaunchKernelGGL(advance_persistent_kernel<4>, dim3(blocks), dim3(kSLThreads), 0, c->stream, v, *job,
-                               c->wave_slots, c->work, blocks * (kSLThreads / 64));
-    } else if (v.n_in) {
-        if (job->field_stride == 3)
-            hipLaunchKernelGGL(advance_kernel<3>, dim3((uint32_t)one_per_item), dim3(kSLThreads), 0, c->stream, v,
-                               *job, c->wave_slots);
-        else
-            hipLaunchKernelGGL(advance_kernel<4>, dim3((uint32_t)one_per_item), dim3(kSLThreads), 0, c->stream, v,
-                               *job, c->wave_slots);
-    }
-    prof_domain_end(c, ph);
-    RAFI_LAUNCH_CHECK();
-    return RAFI_OK;
+    return launch_advance(c, job, v);
 }
 
 int rafi_sl_trace(rafi_ctx *c, const rafi_sl_job *job, const float *seeds, uint64_t n_seeds, int32_t max_rounds,
@@ -457,22 +468,16 @@ int rafi_sl_trace(rafi_ctx *c, const rafi_sl_job *job, const float *seeds, uint6
     if (max_rounds < 1) return RAFI_ERR_ARG;
     int rc = rafi_sl_seed(c, job, seeds, n_seeds);
     if (rc != RAFI_OK) return rc;
-    int32_t r = 0;
-    uint64_t fwd = 0;
-    for (;;) {
-        uint64_t total = 0;
-        rc = rafi_round(c, nullptr, &total);
-        ++r;
-        fwd += total;
-        if (rc != RAFI_OK) break;
-        if (total == 0) break;
-        if (r >= max_rounds) { rc = RAFI_ERR_MAX_ROUNDS; break; }
-        rc = rafi_sl_advance(c, job);
-        if (rc != RAFI_OK) break;
-    }
-    if (rounds) *rounds = r;
-    if (forwarded) *forwarded = fwd;
-    return rc;
+    // each advance launch is enqueued one step ahead of the host (run_rounds)
+    auto launch = [&](uint64_t bound) -> int {
+        const int orc = rafi_open(c, bound, RAFI_SLOTS_ORDERED);
+        if (orc != RAFI_OK) return orc;
+        rafi_device_view v;
+        rafi_view(c, &v);
+        v.n_in = bound;
+        return launch_advance(c, job, v);
+    };
+    return run_rounds(c, max_rounds, rounds, forwarded, launch, [](uint64_t n) { return n; });
 }
 
 }  // extern "C"
