@@ -76,14 +76,14 @@ def streamline_job(args, dev):
     job = rafi.sl_job(f4, grid, endpoint, steps, reason, h, max_steps, args.steps_per_visit, counters,
                       args.tail_items, args.refill_lanes)
     tuned = None
-    if args.steps_per_visit < 0:      # autotune the schedule (results do not depend on it)
+    if args.autotune or args.steps_per_visit < 0:      # sweep the schedule (results do not depend on it)
         from paper_2605_30294_amd import autotune
         tuned, _, sweep = autotune.tune_streamlines(ctx, job, seeds)
         log("streamline schedule sweep (ms, (steps_per_visit, tail_items, refill_lanes)): "
             + ", ".join(f"{m:.2f} {t}" for m, t in sweep))
     # field layout: the same values with 16 or 12 bytes per voxel; keep the faster
     layout_ms = {}
-    for name, f in layouts.items():
+    for name, f in (layouts.items() if args.field_layout == "auto" or args.autotune else ()):
         lj = rafi.sl_job(f, grid, endpoint, steps, reason, h, max_steps, job.steps_per_visit, counters,
                          job.tail_items, job.refill_lanes)
         rafi.sl_trace_job(ctx, lj, seeds)
@@ -96,7 +96,7 @@ def streamline_job(args, dev):
         b.record()
         torch.cuda.synchronize()
         layout_ms[name] = a.elapsed_time(b) / 2
-    layout = min(layout_ms, key=layout_ms.get) if args.field_layout == "auto" else args.field_layout
+    layout = min(layout_ms, key=layout_ms.get) if layout_ms else args.field_layout
     log("streamline field layout (ms): " + ", ".join(f"{k} {v:.2f}" for k, v in layout_ms.items())
         + f"; using {layout}")
     job = rafi.sl_job(layouts[layout], grid, endpoint, steps, reason, h, max_steps, job.steps_per_visit, counters,
@@ -105,7 +105,6 @@ def streamline_job(args, dev):
         rafi.sl_trace_job(ctx, job, seeds)
     torch.cuda.synchronize()
     counters.zero_()
-    ctx.set_profiling(True)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record()
@@ -115,14 +114,18 @@ def streamline_job(args, dev):
     t1.record()
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / args.steps
-    prof = ctx.profile()
     rk4_steps = int(steps.sum().item())
     cross = int(counters[0].item()) // args.steps
     self_fwd = int(counters[1].item()) // args.steps
+    # per-kernel breakdown from one more job with event pairs around every launch
+    # (outside the timed region: the events cost a few microseconds per round)
+    ctx.set_profiling(True)
+    rafi.sl_trace_job(ctx, job, seeds)
+    prof = ctx.profile()
     ctx.set_profiling(False)
     log(f"streamlines: {ms:.3f} ms/job, rounds {rounds}, forward-step items {fwd} "
         f"(seeds {N}, cross-brick {cross}, same-brick {self_fwd}), rk4 steps {rk4_steps}")
-    per_job = 1.0 / args.steps
+    per_job = 1.0
     dom_ms = prof["domain_ms"] * per_job
     split_ms = prof["split_ms"] * per_job
     launches = prof["domain_calls"] * per_job
@@ -267,7 +270,6 @@ def ea_forward(dev, reps):
     torch.cuda.synchronize()
     kl, kf = r["klast"], r["kfirst"]
     samples = int((kl - kf).clamp(min=0).sum().item())
-    ctx.set_profiling(True)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record()
@@ -276,12 +278,14 @@ def ea_forward(dev, reps):
     t1.record()
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / reps
+    ctx.set_profiling(True)                 # breakdown from one more render
+    rafi.ea_render_job(ctx, job)
     p = ctx.profile()
     ctx.close()
     out = {"workload": "128^3 blobs, 4x4x4 domains, 64 views x 256^2 rays", "ms": round(ms, 4),
            "rounds": rounds, "samples": samples, "samples_per_s": samples / (ms * 1e-3),
-           "march_ms": round(p["domain_ms"] / reps, 4), "split_ms": round(p["split_ms"] / reps, 4),
-           "rays_forwarded_per_s": p["split_items"] / reps / (ms * 1e-3)}
+           "march_ms": round(p["domain_ms"], 4), "split_ms": round(p["split_ms"], 4),
+           "rays_forwarded_per_s": p["split_items"] / (ms * 1e-3)}
     log(f"ea forward: {ms:.3f} ms, {samples} samples, {out['samples_per_s']:.3g} samples/s")
     return out
 
@@ -307,7 +311,6 @@ def delta_tracking(dev, reps):
     rafi.dt_render_job(ctx, job)
     torch.cuda.synchronize()
     counters.zero_()
-    ctx.set_profiling(True)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record()
@@ -316,8 +319,11 @@ def delta_tracking(dev, reps):
     t1.record()
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / reps
-    p = ctx.profile()
     points, hits = (int(v) // reps for v in counters.cpu().tolist())
+    ctx.set_profiling(True)                 # breakdown from one more render
+    rafi.dt_render_job(ctx, job)
+    p = ctx.profile()
+    reps = 1
     n_paths = 16 * 256 * 256
     ctx.close()
     out = {"workload": "128^3 blobs, 4x4x4 domains, 16 views x 256^2 paths, kappa 0.5, albedo 0.8, "
@@ -475,9 +481,12 @@ def main():
     ap.add_argument("--refill-lanes", type=int, default=0,
                     help="persistent RK4 waves refill when this many lanes are idle (0: one thread per "
                          "particle); ignored when the schedule is autotuned")
-    ap.add_argument("--field-layout", default="auto", choices=["auto", "padded", "unpadded"],
+    ap.add_argument("--field-layout", default="unpadded", choices=["auto", "padded", "unpadded"],
                     help="RK4 field with 16-byte (padded) or 12-byte voxels; auto keeps the faster")
-    ap.add_argument("--steps-per-visit", type=int, default=-1,
+    ap.add_argument("--autotune", action="store_true",
+                    help="sweep (steps_per_visit, tail_items, refill_lanes) and the field layout before timing "
+                         "instead of using the defaults below (the measured best on MI355X)")
+    ap.add_argument("--steps-per-visit", type=int, default=64,
                     help="RK4 steps a particle takes per domain visit before it is forwarded to its own "
                          "brick (0 = until it leaves, -1 = autotune with the tail threshold); results do "
                          "not depend on it")
