@@ -55,6 +55,25 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# HBM-side bytes per launch of the RK4 kernel: FETCH_SIZE + WRITE_SIZE per
+# dispatch, scaled by a plain copy of known size (profiles/
+# rk4_advance_256cube_1Mseeds.md), for the source file and schedule below;
+# reported only while both still hold.
+RK4_TRAFFIC = {"kernel": "advance_kernel<3>", "bytes_per_launch": 386147774,
+               "source": "paper_2605_30294_amd/csrc/streamline.hip", "source_sha256_16": "3aa6d0f15bab2101",
+               "schedule": (64, 0, 0), "field_layout": "unpadded"}
+
+
+def rk4_traffic(schedule, layout):
+    import hashlib
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), RK4_TRAFFIC["source"])
+    h = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    if h != RK4_TRAFFIC["source_sha256_16"] or tuple(schedule) != RK4_TRAFFIC["schedule"] \
+            or layout != RK4_TRAFFIC["field_layout"]:
+        return None
+    return RK4_TRAFFIC["bytes_per_launch"]
+
+
 def streamline_job(args, dev):
     import numpy as np
     import torch
@@ -137,9 +156,11 @@ def streamline_job(args, dev):
                domain_ms=dom_ms, split_ms=split_ms,
                launches=launches, avg_launch_ms=avg_launch_ms,
                roofline={"kernel": ("advance_persistent_kernel" if job.refill_lanes else "advance_kernel")
-                         + " (RK4 brick march)", "bound": "alu",
+                         + ("<3>" if layout == "unpadded" else "<4>") + " (RK4 brick march)", "bound": "alu",
                          "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
-                         "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None,
+                         "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
+                         "traffic": rk4_traffic((job.steps_per_visit, job.tail_items, job.refill_lanes), layout),
+                         "traffic_unit": "bytes per launch (HBM side: FETCH_SIZE + WRITE_SIZE, calibrated)",
                          "per_launch_flops": flops_per_launch, "avg_launch_ms": round(avg_launch_ms, 4)})
     ctx.close()
     return out, seeds_np
