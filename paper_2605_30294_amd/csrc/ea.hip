@@ -276,16 +276,44 @@ __device__ inline void bwd_segment(const rafi_device_view &view, const rafi_ea_j
         float tau = it.tau, ctau = 0.0f, B = it.I;
         int32_t k = it.k;
         int32_t dest = RAFI_DONE;
-        int32_t cell = -1;
+        // acc[q]: this lane's pending gradient for corner q = (q&1, q>>1&1, q>>2)
+        // of the cell whose corner (0,0,0) is local voxel (cx, cy, cz)
+        int32_t cell = -1, cx = 0, cy = 0, cz = 0;
         float acc[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[q] = 0.0f;
+        const int32_t o[8] = {0, 1, ex, ex + 1, sxy, sxy + 1, sxy + ex, sxy + ex + 1};
         auto flush = [&]() {
             if (cell < 0) return;
-            const int32_t o[8] = {0, 1, ex, ex + 1, sxy, sxy + 1, sxy + ex, sxy + ex + 1};
 #pragma unroll
             for (int q = 0; q < 8; ++q)
                 if (acc[q] != 0.0f) atomicAdd(&gl[cell + o[q]], acc[q]);
+        };
+        // Move to the cell with corner (tx, ty, tz). Across one face the 4
+        // shared corners stay in registers (renumbered); only the other 4 are
+        // added to LDS. Any other move adds all 8.
+        auto move_to = [&](int32_t tx, int32_t ty, int32_t tz) {
+            const int32_t mx = tx - cx, my = ty - cy, mz = tz - cz;
+            const bool face = cell >= 0 && abs(mx) + abs(my) + abs(mz) == 1;
+            const int bit = mx ? 1 : (my ? 2 : 4);
+            const bool up = mx + my + mz > 0;
+            float keep[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                // a corner on the far side of the crossed face survives as corner q ^ bit
+                const bool kept = face && (((q & bit) != 0) == up);
+                if (!kept && cell >= 0 && acc[q] != 0.0f) atomicAdd(&gl[cell + o[q]], acc[q]);
+                keep[q] = kept ? acc[q] : 0.0f;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float from = bit == 1 ? keep[q ^ 1] : (bit == 2 ? keep[q ^ 2] : keep[q ^ 4]);
+                acc[q] = face ? from : 0.0f;
+            }
+            cx = tx;
+            cy = ty;
+            cz = tz;
+            cell = tx + ex * (ty + ey * tz);
         };
         for (; k >= 0; --k) {
             float p[3];
@@ -306,14 +334,9 @@ __device__ inline void bwd_segment(const rafi_device_view &view, const rafi_ea_j
             const float dIdrho = T * __fmaf_rn(c * (1.0f - a), rho - B, a);
             B = __fmaf_rn(a, rho - B, B);
             if (gI == 0.0f) continue;
-            // local cell of corner (i0, j0, k0)
-            const int32_t lc = (t.x - ox) + ex * ((t.y - oy) + ey * (t.z - oz));
-            if (lc != cell) {
-                flush();
-                cell = lc;
-#pragma unroll
-                for (int q = 0; q < 8; ++q) acc[q] = 0.0f;
-            }
+            // local corner (i0, j0, k0) of the sample's cell
+            const int32_t tx = t.x - ox, ty = t.y - oy, tz = t.z - oz;
+            if (cell < 0 || tx != cx || ty != cy || tz != cz) move_to(tx, ty, tz);
             const float s = gI * dIdrho;
             const float gx0 = 1.0f - t.f0, gy0 = 1.0f - t.f1, gz0 = 1.0f - t.f2;
             const float a00 = s * gz0 * gy0, a01 = s * gz0 * t.f1, a10 = s * t.f2 * gy0, a11 = s * t.f2 * t.f1;
