@@ -212,7 +212,7 @@ def split_microbench(dev, reps):
         ctx.emit_bulk(items, dest)
         # workgroup shape of the scatter: every shape gives the same bytes
         shapes = {}
-        for v in range(1, 14):
+        for v in range(1, 16):
             rafi.split_set_variant(v)
             shapes[v] = timed(3)[0]
         best = min(shapes, key=shapes.get)
@@ -253,7 +253,7 @@ def split_domain_sweep(dev, reps, domains=(16, 64, 256, 1024, 4096)):
         ctx.begin(N)
         ctx.emit_bulk(items, dest)
         best = None
-        for v in (0, 1, 12, 13):
+        for v in (0, 1, 12, 13, 14, 15):
             try:
                 rafi.split_set_variant(v)
                 ctx.round(counts=False)

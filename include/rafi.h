@@ -214,15 +214,20 @@ int rafi_multisplit_workspace(uint64_t n, int32_t n_domains, uint32_t item_bytes
                               uint64_t *bytes);
 
 /* Process-wide choice of the scatter pass's workgroup shape (chunk size,
- * waves per workgroup, workgroups per CU): 0 = automatic (shape 12 when a
- * tile holds at least one of its chunks, else the first of 1..4 that fits the
- * LDS); 1..4 stage items
+ * waves per workgroup, workgroups per CU): 0 = automatic (shape 15 when
+ * one workgroup per CU spans at least two tiles and 16384 slots, else
+ * shape 12 when a tile holds at least one of its chunks, else the first of
+ * 1..4 that fits the LDS); 1..4 stage items
  * in LDS; 5..7 stage only indices and read items in sorted order; 8..11 are
  * shapes 1..4 with the next chunk's loads issued before the current chunk is
  * ranked; 12..13 use one workgroup per CU with 4096-slot chunks (32-byte
- * items), 13 with the next chunk's loads issued early. For tuning. Every
- * shape gives the same bytes. Not synchronised: set it while no split is
- * being launched. Outside 0..13: RAFI_ERR_ARG. */
+ * items), 13 with the next chunk's loads issued early; 14..15 (16- and
+ * 32-byte items, 128-byte aligned output, else as 0) use one workgroup per
+ * CU over a group of tiles and write each destination's output in whole
+ * 128-byte lines, keeping a run's unfinished line for the next chunk; 15
+ * issues the next chunk's loads early. For tuning. Every shape gives the
+ * same bytes. Not synchronised: set it while no split is being launched.
+ * Outside 0..15: RAFI_ERR_ARG. */
 int rafi_split_set_variant(int32_t variant);
 int rafi_multisplit(const void *items, const int32_t *dest, uint64_t n, uint32_t item_bytes,
                     int32_t n_domains, void *out, uint64_t *offsets, uint64_t *summary,

@@ -456,6 +456,65 @@ bool try_wide(const SplitPlan &p, const uint32_t *items, const int32_t *dest, co
     return true;
 }
 
+// The line-aligned shape: one workgroup per CU, each over a group of
+// consecutive histogram tiles, so that only the two ends of a destination's
+// run per group are partial lines.
+template <int NW, int R, int W, int PMAX, bool DB>
+__global__ void __launch_bounds__(64 * W)
+scatter_line_kernel(const uint32_t *__restrict__ items, const int32_t *__restrict__ dest, uint64_t n,
+                    int32_t D, int nbits, uint32_t T, uint32_t n_tiles, uint32_t group,
+                    const uint32_t *__restrict__ table, uint32_t *__restrict__ out)
+{
+    extern __shared__ __align__(16) uint32_t lds[];
+    const uint32_t tile = blockIdx.x * group;
+    const uint64_t tstart = (uint64_t)tile * T;
+    const uint64_t tend = min(tstart + (uint64_t)group * T, n);
+    dev::line_scatter_tile<NW, R, W, PMAX, DB>(
+        items, dest, tstart, tend, D, nbits,
+        [&](int32_t e) { return table[(uint64_t)e * n_tiles + tile]; }, out, n, lds);
+}
+
+int g_cus = 0;
+
+int cu_count()
+{
+    if (g_cus == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v < 1)
+            v = 256;
+        g_cus = v;
+    }
+    return g_cus;
+}
+
+// Whether one workgroup per CU covers at least two histogram tiles and
+// 16384 slots: then the partial lines at the ends of each workgroup's runs
+// are few and the line-aligned shape pays.
+bool line_spans_tiles(const SplitPlan &p)
+{
+    const uint32_t cus = (uint32_t)cu_count();
+    const uint64_t group = (p.n_tiles + cus - 1) / cus;
+    return p.n_tiles >= 2u * cus && group * p.tile >= 16384;
+}
+
+template <int NW, int R, int W, int PMAX, bool DB>
+bool try_line(const SplitPlan &p, const uint32_t *items, const int32_t *dest, const uint32_t *table,
+              uint32_t *out, hipStream_t s)
+{
+    const size_t lds = dev::line_lds_bytes_c<NW, R, W, PMAX>(p.D) + 64;
+    if (p.D > dev::kStagedMaxD || lds > dev::kStagedLdsPerCu) return false;
+    if ((reinterpret_cast<uintptr_t>(out) & 127) != 0) return false;
+    const uint32_t cus = (uint32_t)cu_count();
+    const uint32_t group = (p.n_tiles + cus - 1) / cus;
+    const uint32_t grid = (p.n_tiles + group - 1) / group;
+    int nbits = 1;
+    while ((1 << nbits) < p.D) ++nbits;
+    hipLaunchKernelGGL((scatter_line_kernel<NW, R, W, PMAX, DB>), dim3(grid), dim3(64 * W), lds, s, items, dest,
+                       p.n, p.D, nbits, p.tile, p.n_tiles, group, table, out);
+    return true;
+}
+
 // Process-wide choice among the scatter shapes (0 = automatic).
 int g_split_variant = 0;
 
@@ -463,7 +522,17 @@ template <int NW>
 bool launch_staged(const SplitPlan &p, const uint32_t *items, const int32_t *dest, const uint32_t *table,
                    uint32_t *out, uint32_t *dummy, hipStream_t s)
 {
-    const int v = g_split_variant;
+    int v = g_split_variant;
+    if (v >= 14) {  // line-aligned writes, one workgroup per CU over a group of tiles
+        if constexpr (NW == 8) {
+            if (v == 14 && try_line<8, 4, 8, 1792, false>(p, items, dest, table, out, s)) return true;
+            if (v == 15 && try_line<8, 4, 8, 1792, true>(p, items, dest, table, out, s)) return true;
+        } else if constexpr (NW == 4) {
+            if (v == 14 && try_line<4, 6, 8, 3840, false>(p, items, dest, table, out, s)) return true;
+            if (v == 15 && try_line<4, 6, 8, 3840, true>(p, items, dest, table, out, s)) return true;
+        }
+        v = 0;  // item size or output alignment the line shapes do not take
+    }
     if (v >= 12) {  // one workgroup per CU, 4096-slot (32-byte) or 6144-slot (16-byte) chunks
         if constexpr (NW == 8) {
             if (v == 12) return try_wide<8, 8, 8, false>(p, items, dest, table, out, dummy, s);
@@ -474,7 +543,16 @@ bool launch_staged(const SplitPlan &p, const uint32_t *items, const int32_t *des
         }
         return false;
     }
-    if (v == 0) {  // automatic: the wide shape when a tile fills at least one of its chunks
+    if (v == 0) {
+        // automatic: line-aligned writes when each workgroup spans several
+        // tiles, else the wide shape when a tile fills at least one of its chunks
+        if (line_spans_tiles(p)) {
+            if constexpr (NW == 8) {
+                if (try_line<8, 4, 8, 1792, true>(p, items, dest, table, out, s)) return true;
+            } else if constexpr (NW == 4) {
+                if (try_line<4, 6, 8, 3840, true>(p, items, dest, table, out, s)) return true;
+            }
+        }
         if constexpr (NW == 8) {
             if (p.tile >= 8 * 8 * 64 && try_wide<8, 8, 8, false>(p, items, dest, table, out, dummy, s)) return true;
         } else if constexpr (NW == 4) {
@@ -564,7 +642,7 @@ void finish_plan(SplitPlan &p)
 
 int split_set_variant(int v)
 {
-    if (v < 0 || v > 13) return RAFI_ERR_ARG;
+    if (v < 0 || v > 15) return RAFI_ERR_ARG;
     g_split_variant = v;
     return RAFI_OK;
 }

@@ -464,6 +464,260 @@ __device__ inline void wide_scatter_tile(const uint32_t *__restrict__ items, con
     }
 }
 
+// ------------------------------------------------ line-aligned scatter ---
+// The wide shape, except that each destination's output run is written in
+// whole 128-byte lines only. Writes that cover part of a line cost about as
+// much as whole lines on this memory system, and a chunk's run for one
+// destination is a few items long and starts anywhere in a line, so the
+// wide shape spends most of its write time on partial lines. Here the items
+// of a run's last, unfinished line are not written: the thread that owns the
+// destination keeps them in registers and stages them again, in front of the
+// destination's new items, in the next chunk. Only the first and the last
+// line of a destination's run over [tstart, tend) can be partial writes.
+// [tstart, tend) may span several histogram tiles: a destination's runs of
+// consecutive tiles are adjacent in the output, so the cursor runs on.
+//
+// The stage holds a chunk of CH items plus the carried ones, and for each
+// stage slot the output slot it is written to (all ones while held back), so
+// that the write phase reads two independent LDS words per piece. When more
+// than PMAX items would be carried into the next chunk, every destination
+// writes its carried items as a partial line instead, so the stage never
+// holds more than CH + PMAX. Output lines are counted from item 0: `out`
+// must be 128-byte aligned and NW in {4, 8, 16}.
+template <int NW, int R, int W, int PMAX>
+constexpr size_t line_lds_bytes_c(int32_t D)
+{
+    constexpr int SC = W * 64 * R + PMAX;
+    return sizeof(uint32_t) * ((size_t)SC * (NW + 1) + 2 * (size_t)D) + sizeof(uint16_t) * ((size_t)W * D + 2);
+}
+
+template <int NW, int R, int W, int PMAX, bool DB, typename RunBase>
+__device__ inline void line_scatter_tile(const uint32_t *__restrict__ items, const int32_t *__restrict__ dest,
+                                         uint64_t tstart, uint64_t tend, int32_t D, int nbits, RunBase run_base,
+                                         uint32_t *__restrict__ out, uint64_t out_cap, uint32_t *lds)
+{
+    constexpr int NT = 64 * W, SEG = 64 * R, CH = W * SEG, SC = CH + PMAX;
+    static_assert(NW == 4 || NW == 8 || NW == 16, "items that tile a 128-byte line in 16-byte pieces");
+    static_assert(SC < 65536, "stage indices and the packed scan are 16-bit");
+    constexpr int L = 32 / NW;                           // items per 128-byte line
+    constexpr int LC = L - 1;                            // most items one destination carries
+    constexpr int PPI = NW / 4;                          // 16-byte pieces per item
+    constexpr int NPT = (SC * PPI + NT - 1) / NT;        // store pieces per thread per chunk
+    constexpr int EPT = (kStagedMaxD + NT - 1) / NT;     // max destinations per thread
+    static_assert((size_t)LC * kStagedMaxD < 65536, "carried count fits the packed scan");
+    static_assert(SC * (NW + 1) % 2 == 0, "8-byte aligned destination table");
+    constexpr uint32_t HELD = 0xffffffffu;
+    uint32_t *stage = lds;                               // [SC * NW]
+    uint32_t *gidx = stage + SC * NW;                    // [SC] output slot of stage slot j, or HELD
+    uint2 *rbw = reinterpret_cast<uint2 *>(gidx + SC);   // [D] {output slot of stage slot 0, first slot held}
+    uint16_t *cnt = reinterpret_cast<uint16_t *>(rbw + D);  // [W * D (+2)]
+    __shared__ uint32_t scan_lds[NT / 64 + 1];
+
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const int per = (D + NT - 1) / NT;
+    const int e0 = tid * per;
+
+    // per owned destination: output slot of its next new item, the items it
+    // carries (those of slots [cur - pend, cur)) and where they sit in the stage
+    uint32_t cur[EPT], pend[EPT], keep[EPT];
+    uint32_t carry[EPT][LC][NW];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        cur[k] = (k < per && e0 + k < D) ? run_base(e0 + k) : 0u;
+        pend[k] = 0;
+        keep[k] = 0;
+    }
+
+    typedef uint32_t Items[R][NW];
+    typedef int32_t Dests[R];
+    auto load_chunk = [&](Items &item, Dests &dd, uint64_t cbase) {
+        const uint64_t qbase = cbase + (uint64_t)w * SEG;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t i = qbase + 64 * r + lane;
+            const uint64_t ic = i < tend ? i : tend - 1;
+            const int32_t x = __builtin_nontemporal_load(dest + ic);
+            dd[r] = i < tend ? x : -1;
+            const uint32_t *src = items + ic * NW;
+#pragma unroll
+            for (int k = 0; k < NW / 4; ++k) {
+                const uint4 q = load_nt4(src + 4 * k);
+                item[r][4 * k] = q.x; item[r][4 * k + 1] = q.y;
+                item[r][4 * k + 2] = q.z; item[r][4 * k + 3] = q.w;
+            }
+        }
+        __asm__ __volatile__("" ::: "memory");
+    };
+
+    auto store_item = [&](uint32_t g, const uint32_t *v) {
+        if (g < out_cap) {
+            uint4 *dst = reinterpret_cast<uint4 *>(out + (uint64_t)g * NW);
+#pragma unroll
+            for (int k = 0; k < PPI; ++k) dst[k] = make_uint4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+        }
+    };
+
+    auto process = [&](Items &item, Dests &dd, auto after_place) {
+        uint16_t rank[R];
+        for (int k = tid; k < (W * D + 1) / 2; k += NT) reinterpret_cast<uint32_t *>(cnt)[k] = 0;
+        __syncthreads();
+
+        uint16_t *mycnt = cnt + w * D;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int32_t d = dd[r];
+            const bool ok = d >= 0 && d < D;
+            const uint64_t peers = match_peers((uint32_t)d, ok, nbits);
+            uint16_t before = 0;
+            if (ok) before = mycnt[d];
+            __builtin_amdgcn_wave_barrier();
+            rank[r] = (uint16_t)(before + __popcll(peers & lt));
+            if (ok && (peers & lt) == 0ull) mycnt[d] = (uint16_t)(before + __popcll(peers));
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+
+        // a destination's stage segment: its carried items, then its new ones;
+        // one scan gives the segment bases (low half) and the carried total
+        // of the next chunk (high half)
+        uint32_t tot_e[EPT];
+        uint32_t seg_sum = 0, carry_sum = 0;
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int32_t e = e0 + k;
+            uint32_t t = 0;
+            if (k < per && e < D) {
+#pragma unroll
+                for (int ww = 0; ww < W; ++ww) t += cnt[ww * D + e];
+                const uint32_t a = cur[k] - pend[k], end = cur[k] + t;
+                const uint32_t lend = end & ~(uint32_t)(L - 1);
+                const uint32_t wl = lend > a ? lend : a;
+                seg_sum += pend[k] + t;
+                carry_sum += end - wl;
+            }
+            tot_e[k] = t;
+        }
+        uint32_t packed_total;
+        const uint32_t packed = block_excl_scan<NT>(seg_sum | (carry_sum << 16), scan_lds, &packed_total);
+        uint32_t base = packed & 0xffffu;
+        const uint32_t staged = packed_total & 0xffffu, carried_next = packed_total >> 16;
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int32_t e = e0 + k;
+            if (k < per && e < D) {
+                const uint32_t a = cur[k] - pend[k], end = cur[k] + tot_e[k];
+                const uint32_t lend = end & ~(uint32_t)(L - 1);
+                const uint32_t wl = lend > a ? lend : a;
+                rbw[e] = make_uint2(a - base, wl);
+#pragma unroll
+                for (int i = 0; i < LC; ++i)
+                    if ((uint32_t)i < pend[k]) {
+                        uint4 *dst = reinterpret_cast<uint4 *>(stage + (base + i) * NW);
+#pragma unroll
+                        for (int q = 0; q < PPI; ++q)
+                            dst[q] = make_uint4(carry[k][i][4 * q], carry[k][i][4 * q + 1], carry[k][i][4 * q + 2],
+                                                carry[k][i][4 * q + 3]);
+                        gidx[base + i] = a + i < wl ? a + i : HELD;
+                    }
+                uint32_t b = base + pend[k];
+#pragma unroll
+                for (int ww = 0; ww < W; ++ww) {
+                    const uint32_t c = cnt[ww * D + e];
+                    cnt[ww * D + e] = (uint16_t)b;
+                    b += c;
+                }
+                keep[k] = base + (wl - a);  // stage slot of the first item carried on
+                base += pend[k] + tot_e[k];
+                pend[k] = end - wl;
+                cur[k] = end;
+            }
+        }
+        __syncthreads();
+
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int32_t d = dd[r];
+            if (d >= 0 && d < D) {
+                const uint32_t pos = (uint32_t)cnt[w * D + d] + rank[r];
+                const uint2 bw = rbw[d];
+                uint32_t *dst = stage + pos * NW;
+#pragma unroll
+                for (int k = 0; k < NW / 4; ++k)
+                    reinterpret_cast<uint4 *>(dst)[k] =
+                        make_uint4(item[r][4 * k], item[r][4 * k + 1], item[r][4 * k + 2], item[r][4 * k + 3]);
+                const uint32_t g = bw.x + pos;
+                gidx[pos] = g < bw.y ? g : HELD;
+            }
+        }
+        __syncthreads();
+
+        after_place();
+
+        // write every staged piece that lies in a finished line, WB pieces
+        // at a time with all their LDS reads issued together
+        const uint32_t n_pieces = staged * PPI;
+        constexpr int WB = 8;
+#pragma unroll
+        for (int u0 = 0; u0 < NPT; u0 += WB) {
+            uint32_t g[WB], col[WB];
+            uint4 v[WB];
+#pragma unroll
+            for (int b = 0; b < WB; ++b) {
+                const uint32_t q = (uint32_t)((u0 + b) * NT + tid);
+                const bool ok = u0 + b < NPT && q < n_pieces;
+                const uint32_t qq = ok ? q : 0u;
+                const uint32_t j = qq / PPI;
+                col[b] = qq - j * PPI;
+                g[b] = ok ? gidx[j] : HELD;
+                v[b] = *reinterpret_cast<const uint4 *>(stage + j * NW + col[b] * 4);
+            }
+#pragma unroll
+            for (int b = 0; b < WB; ++b)
+                if (g[b] < out_cap) *reinterpret_cast<uint4 *>(out + (uint64_t)g[b] * NW + col[b] * 4) = v[b];
+        }
+        // pick up the items carried into the next chunk; if there are too
+        // many for the stage, write them now (partial lines) instead
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+#pragma unroll
+            for (int i = 0; i < LC; ++i)
+                if ((uint32_t)i < pend[k]) {
+#pragma unroll
+                    for (int q = 0; q < NW; ++q) carry[k][i][q] = stage[(keep[k] + i) * NW + q];
+                    if (carried_next > (uint32_t)PMAX) store_item(cur[k] - pend[k] + i, carry[k][i]);
+                }
+            if (carried_next > (uint32_t)PMAX) pend[k] = 0;
+        }
+        __syncthreads();
+    };
+
+    if (tstart >= tend) return;
+    Items itemA;
+    Dests ddA;
+    load_chunk(itemA, ddA, tstart);
+    if constexpr (!DB) {
+        for (uint64_t cbase = tstart; cbase < tend; cbase += CH)
+            process(itemA, ddA, [&] { load_chunk(itemA, ddA, cbase + CH); });
+    } else {
+        Items itemB;
+        Dests ddB;
+        for (uint64_t cbase = tstart; cbase < tend; cbase += 2 * CH) {
+            load_chunk(itemB, ddB, cbase + CH);
+            process(itemA, ddA, [] {});
+            if (cbase + CH >= tend) break;
+            load_chunk(itemA, ddA, cbase + 2 * CH);
+            process(itemB, ddB, [] {});
+        }
+    }
+    // the last line of every run
+#pragma unroll
+    for (int k = 0; k < EPT; ++k)
+#pragma unroll
+        for (int i = 0; i < LC; ++i)
+            if ((uint32_t)i < pend[k]) store_item(cur[k] - pend[k] + i, carry[k][i]);
+}
+
 // ------------------------------------- gather-read, coalesced-write scatter ---
 // Same ranking as staged_scatter_tile, but LDS keeps only, per chunk-sorted
 // slot, the chunk-local source index and the output slot (6 bytes instead of

@@ -58,7 +58,7 @@ def test_argument_validation_without_device():
     assert L.rafi_dt_raygen(None, None) == rafi.ERR_ARG
     assert L.rafi_dt_trace(None, None) == rafi.ERR_ARG
     assert L.rafi_dt_render(None, None, 10, None) == rafi.ERR_ARG
-    assert L.rafi_split_set_variant(14) == rafi.ERR_ARG
+    assert L.rafi_split_set_variant(16) == rafi.ERR_ARG
     assert L.rafi_split_set_variant(-1) == rafi.ERR_ARG
 
 

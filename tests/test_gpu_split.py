@@ -21,6 +21,8 @@ def _run_split(orc, n, D, words, seed, dist="mixed"):
     rng = np.random.default_rng(seed)
     if dist == "mixed":
         dest = rng.integers(-2, D + 1, n).astype(np.int32)        # done, bad and valid
+    elif dist == "cyclic":
+        dest = (np.arange(n) % D).astype(np.int32)                # every destination in every chunk
     else:
         dest = W.split_dest(n, D, dist, seed=seed)
     items = rng.integers(0, 2**32, (n, words), dtype=np.uint64).astype(np.uint32)
@@ -90,12 +92,27 @@ def test_context_round_and_error_paths(orc):
     ctx.close()
 
 
-@pytest.mark.parametrize("variant", list(range(1, 14)))
+@pytest.mark.parametrize("variant", list(range(1, 16)))
 @pytest.mark.parametrize("n,D,words", [(300_001, 1024, 8), (200_003, 64, 4), (77_777, 1000, 8), (150_000, 7, 4)])
 def test_split_shapes_identical(orc, variant, n, D, words):
     """Every workgroup shape of the staged scatter gives the oracle's bytes."""
     try:
         rafi.split_set_variant(variant)
         _run_split(orc, n, D, words, seed=variant * 1000 + n)
+    finally:
+        rafi.split_set_variant(0)
+
+
+@pytest.mark.parametrize("variant", [0, 12, 14, 15])
+@pytest.mark.parametrize("n,D,words,dist", [
+    (1_000_003, 64, 8, "mixed"), (2_500_000, 1024, 8, "mixed"), (600_000, 1024, 4, "mixed"),
+    (4_096_000, 1024, 8, "cyclic"), (3_072_005, 1024, 4, "cyclic"), (2_000_000, 1000, 8, "zipf")])
+def test_split_line_aligned_shapes(orc, variant, n, D, words, dist):
+    """Sizes where one workgroup of the line-aligned shapes spans several
+    histogram tiles, and cyclic destinations, which leave more unfinished
+    lines after a chunk than the stage keeps (those are written at once)."""
+    try:
+        rafi.split_set_variant(variant)
+        _run_split(orc, n, D, words, seed=variant * 1000 + n + 1, dist=dist)
     finally:
         rafi.split_set_variant(0)
