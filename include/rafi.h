@@ -222,7 +222,8 @@ int rafi_multisplit_workspace(uint64_t n, int32_t n_domains, uint32_t item_bytes
  * shapes 1..4 with the next chunk's loads issued before the current chunk is
  * ranked; 12..13 use one workgroup per CU with 4096-slot chunks (32-byte
  * items), 13 with the next chunk's loads issued early; 14..15 (16- and
- * 32-byte items, 128-byte aligned output, else as 0) use one workgroup per
+ * 32-byte items, 128-byte aligned output of at most 0xfffffff0 bytes, else
+ * as 0) use one workgroup per
  * CU over a group of tiles and write each destination's output in whole
  * 128-byte lines, keeping a run's unfinished line for the next chunk; 15
  * issues the next chunk's loads early. For tuning. Every shape gives the

@@ -505,6 +505,7 @@ bool try_line(const SplitPlan &p, const uint32_t *items, const int32_t *dest, co
     const size_t lds = dev::line_lds_bytes_c<NW, R, W, PMAX>(p.D) + 64;
     if (p.D > dev::kStagedMaxD || lds > dev::kStagedLdsPerCu) return false;
     if ((reinterpret_cast<uintptr_t>(out) & 127) != 0) return false;
+    if (p.n * (uint64_t)p.S > 0xfffffff0ull) return false;  // 32-bit buffer offsets
     const uint32_t cus = (uint32_t)cu_count();
     const uint32_t group = (p.n_tiles + cus - 1) / cus;
     const uint32_t grid = (p.n_tiles + group - 1) / group;

@@ -12,15 +12,21 @@
 namespace rafi {
 namespace dev {
 
+// Inclusive scan over the 64 lanes of a wave (all lanes active): a
+// Hillis-Steele scan inside each row of 16 lanes with DPP row shifts (lanes
+// shifted in from outside the row read 0), then the totals of rows 0..2
+// (lanes 15, 31, 47) added to the rows after them.
 __device__ inline uint32_t wave_incl_scan(uint32_t v)
 {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t t = __shfl_up(v, o, 64);
-        if (lane >= o) v += t;
-    }
-    return v;
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    const uint32_t row = (threadIdx.x & 63) >> 4;
+    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 15);
+    const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
+    const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)v, 47);
+    return v + (row >= 1 ? r0 : 0u) + (row >= 2 ? r1 : 0u) + (row >= 3 ? r2 : 0u);
 }
 
 // Exclusive block scan; lds needs NT/64 + 1 words. Returns the exclusive
@@ -483,7 +489,9 @@ __device__ inline void wide_scatter_tile(const uint32_t *__restrict__ items, con
 // than PMAX items would be carried into the next chunk, every destination
 // writes its carried items as a partial line instead, so the stage never
 // holds more than CH + PMAX. Output lines are counted from item 0: `out`
-// must be 128-byte aligned and NW in {4, 8, 16}.
+// must be 128-byte aligned, NW in {4, 8, 16}, and the output at most
+// 0xfffffff0 bytes (it is written through a buffer resource with 32-bit
+// offsets).
 template <int NW, int R, int W, int PMAX>
 constexpr size_t line_lds_bytes_c(int32_t D)
 {
@@ -506,6 +514,7 @@ __device__ inline void line_scatter_tile(const uint32_t *__restrict__ items, con
     constexpr int EPT = (kStagedMaxD + NT - 1) / NT;     // max destinations per thread
     static_assert((size_t)LC * kStagedMaxD < 65536, "carried count fits the packed scan");
     static_assert(SC * (NW + 1) % 2 == 0, "8-byte aligned destination table");
+    static_assert(W % 4 == 0, "the count table is cleared in 8-byte words");
     constexpr uint32_t HELD = 0xffffffffu;
     uint32_t *stage = lds;                               // [SC * NW]
     uint32_t *gidx = stage + SC * NW;                    // [SC] output slot of stage slot j, or HELD
@@ -560,7 +569,7 @@ __device__ inline void line_scatter_tile(const uint32_t *__restrict__ items, con
 
     auto process = [&](Items &item, Dests &dd, auto after_place) {
         uint16_t rank[R];
-        for (int k = tid; k < (W * D + 1) / 2; k += NT) reinterpret_cast<uint32_t *>(cnt)[k] = 0;
+        for (int k = tid; k < W * D / 4; k += NT) reinterpret_cast<uint64_t *>(cnt)[k] = 0ull;
         __syncthreads();
 
         uint16_t *mycnt = cnt + w * D;
@@ -581,6 +590,25 @@ __device__ inline void line_scatter_tile(const uint32_t *__restrict__ items, con
         // a destination's stage segment: its carried items, then its new ones;
         // one scan gives the segment bases (low half) and the carried total
         // of the next chunk (high half)
+        // per-wave counts of the owned destinations, kept for the rewrite
+        // below; two adjacent 16-bit counts are one 32-bit word when a
+        // thread owns an even-aligned pair
+        uint32_t cv[EPT][W];
+        uint32_t *cnt32 = reinterpret_cast<uint32_t *>(cnt);
+        const bool pairs = EPT == 2 && per == 2 && (D & 1) == 0;
+        if (pairs) {
+#pragma unroll
+            for (int ww = 0; ww < W; ++ww) {
+                const uint32_t pr = e0 < D ? cnt32[(ww * D + e0) >> 1] : 0u;
+                cv[0][ww] = pr & 0xffffu;
+                cv[EPT - 1][ww] = pr >> 16;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < EPT; ++k)
+#pragma unroll
+                for (int ww = 0; ww < W; ++ww) cv[k][ww] = (k < per && e0 + k < D) ? cnt[ww * D + e0 + k] : 0u;
+        }
         uint32_t tot_e[EPT];
         uint32_t seg_sum = 0, carry_sum = 0;
 #pragma unroll
@@ -589,7 +617,7 @@ __device__ inline void line_scatter_tile(const uint32_t *__restrict__ items, con
             uint32_t t = 0;
             if (k < per && e < D) {
 #pragma unroll
-                for (int ww = 0; ww < W; ++ww) t += cnt[ww * D + e];
+                for (int ww = 0; ww < W; ++ww) t += cv[k][ww];
                 const uint32_t a = cur[k] - pend[k], end = cur[k] + t;
                 const uint32_t lend = end & ~(uint32_t)(L - 1);
                 const uint32_t wl = lend > a ? lend : a;
@@ -623,15 +651,23 @@ __device__ inline void line_scatter_tile(const uint32_t *__restrict__ items, con
                 uint32_t b = base + pend[k];
 #pragma unroll
                 for (int ww = 0; ww < W; ++ww) {
-                    const uint32_t c = cnt[ww * D + e];
-                    cnt[ww * D + e] = (uint16_t)b;
+                    const uint32_t c = cv[k][ww];
+                    cv[k][ww] = b;
                     b += c;
+                }
+                if (!pairs) {
+#pragma unroll
+                    for (int ww = 0; ww < W; ++ww) cnt[ww * D + e] = (uint16_t)cv[k][ww];
                 }
                 keep[k] = base + (wl - a);  // stage slot of the first item carried on
                 base += pend[k] + tot_e[k];
                 pend[k] = end - wl;
                 cur[k] = end;
             }
+        }
+        if (pairs && e0 < D) {
+#pragma unroll
+            for (int ww = 0; ww < W; ++ww) cnt32[(ww * D + e0) >> 1] = cv[0][ww] | (cv[EPT - 1][ww] << 16);
         }
         __syncthreads();
 
@@ -658,6 +694,8 @@ __device__ inline void line_scatter_tile(const uint32_t *__restrict__ items, con
         // at a time with all their LDS reads issued together
         const uint32_t n_pieces = staged * PPI;
         constexpr int WB = 8;
+        const __amdgpu_buffer_rsrc_t orsrc =
+            __builtin_amdgcn_make_buffer_rsrc(out, (short)0, (int)(uint32_t)(out_cap * (uint64_t)(NW * 4)), 0x00020000);
 #pragma unroll
         for (int u0 = 0; u0 < NPT; u0 += WB) {
             uint32_t g[WB], col[WB];
@@ -672,9 +710,16 @@ __device__ inline void line_scatter_tile(const uint32_t *__restrict__ items, con
                 g[b] = ok ? gidx[j] : HELD;
                 v[b] = *reinterpret_cast<const uint4 *>(stage + j * NW + col[b] * 4);
             }
+            // every lane issues its store; a held piece gets an offset past
+            // the buffer's end, which the hardware drops. Stores issued in
+            // every case let the compiler count outstanding memory
+            // operations, so the next chunk's loads are not held behind them.
 #pragma unroll
-            for (int b = 0; b < WB; ++b)
-                if (g[b] < out_cap) *reinterpret_cast<uint4 *>(out + (uint64_t)g[b] * NW + col[b] * 4) = v[b];
+            for (int b = 0; b < WB; ++b) {
+                const uint32_t off = g[b] < out_cap ? g[b] * (uint32_t)(NW * 4) + col[b] * 16u : 0xfffffff0u;
+                const u32x4_t x = {v[b].x, v[b].y, v[b].z, v[b].w};
+                __builtin_amdgcn_raw_buffer_store_b128(x, orsrc, (int)off, 0, 0);
+            }
         }
         // pick up the items carried into the next chunk; if there are too
         // many for the stage, write them now (partial lines) instead
@@ -684,7 +729,11 @@ __device__ inline void line_scatter_tile(const uint32_t *__restrict__ items, con
             for (int i = 0; i < LC; ++i)
                 if ((uint32_t)i < pend[k]) {
 #pragma unroll
-                    for (int q = 0; q < NW; ++q) carry[k][i][q] = stage[(keep[k] + i) * NW + q];
+                    for (int q = 0; q < PPI; ++q) {
+                        const uint4 x = *reinterpret_cast<const uint4 *>(stage + (keep[k] + i) * NW + 4 * q);
+                        carry[k][i][4 * q] = x.x; carry[k][i][4 * q + 1] = x.y;
+                        carry[k][i][4 * q + 2] = x.z; carry[k][i][4 * q + 3] = x.w;
+                    }
                     if (carried_next > (uint32_t)PMAX) store_item(cur[k] - pend[k] + i, carry[k][i]);
                 }
             if (carried_next > (uint32_t)PMAX) pend[k] = 0;
