@@ -214,7 +214,7 @@ int rafi_multisplit_workspace(uint64_t n, int32_t n_domains, uint32_t item_bytes
                               uint64_t *bytes);
 
 /* Process-wide choice of the scatter pass's workgroup shape (chunk size,
- * waves per workgroup, workgroups per CU): 0 = automatic (shape 15 when
+ * waves per workgroup, workgroups per CU): 0 = automatic (shape 14 when
  * one workgroup per CU spans at least two tiles and 16384 slots, else
  * shape 12 when a tile holds at least one of its chunks, else the first of
  * 1..4 that fits the LDS); 1..4 stage items

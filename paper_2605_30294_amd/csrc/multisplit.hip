@@ -549,9 +549,9 @@ bool launch_staged(const SplitPlan &p, const uint32_t *items, const int32_t *des
         // tiles, else the wide shape when a tile fills at least one of its chunks
         if (line_spans_tiles(p)) {
             if constexpr (NW == 8) {
-                if (try_line<8, 4, 8, 1792, true>(p, items, dest, table, out, s)) return true;
+                if (try_line<8, 4, 8, 1792, false>(p, items, dest, table, out, s)) return true;
             } else if constexpr (NW == 4) {
-                if (try_line<4, 6, 8, 3840, true>(p, items, dest, table, out, s)) return true;
+                if (try_line<4, 6, 8, 3840, false>(p, items, dest, table, out, s)) return true;
             }
         }
         if constexpr (NW == 8) {
