@@ -62,10 +62,28 @@ class DTParams(C.Structure):
                 ("max_bounce", C.c_int32), ("seed", C.c_uint32)]
 
 
+class NBParams(C.Structure):
+    _fields_ = [("n_domains", C.c_int32), ("cell_level", C.c_int32), ("dt", C.c_float), ("theta", C.c_float),
+                ("eps", C.c_float)]
+
+
+# record layouts of the three N-body item types (see the C file, O8)
+NB_PARTICLE = np.dtype([("pos", "<f4", 3), ("vel", "<f4", 3), ("acc", "<f4", 3), ("mass", "<f4")])
+NB_VP = np.dtype([("pos", "<f4", 3), ("mass", "<f4"), ("smax", "<f4"), ("src", "<i4")])
+
 _p = C.c_void_p
 
 
 def _declare(L):
+    L.oracle_morton30.argtypes = [C.c_float, C.c_float, C.c_float]
+    L.oracle_morton30.restype = C.c_uint32
+    L.oracle_nb_splitters.argtypes = [_p, C.c_int64, C.c_int32, _p]
+    L.oracle_nb_splitters.restype = C.c_int
+    L.oracle_nb_seed.argtypes = [C.POINTER(NBParams), _p, _p, C.c_int64, _p, _p]
+    L.oracle_nb_seed.restype = C.c_int
+    L.oracle_nb_step.argtypes = [C.POINTER(NBParams), _p, _p, C.c_int64, _p, _p, C.c_uint64, _p, C.c_uint64, _p,
+                                 C.c_uint64, _p]
+    L.oracle_nb_step.restype = C.c_int
     L.oracle_philox4x32_10.argtypes = [_p, _p, _p]
     L.oracle_philox4x32_10.restype = None
     L.oracle_dt_logf.argtypes = [C.c_float]
@@ -319,3 +337,62 @@ def dt_render(volume, grid, views, kappa, smax, albedo, light, radiance, max_bou
         out["weights"] = wl[:m]
         out["queue_len"] = qlen.value
     return out
+
+
+# ---------------------------------------------------------------- O8 ---
+
+def morton30(x, y, z) -> int:
+    return int(lib().oracle_morton30(float(x), float(y), float(z)))
+
+
+def nb_splitters(particles, n_domains: int) -> np.ndarray:
+    """Morton splitters K[0..D] of a particle set (O8)."""
+    pos = np.ascontiguousarray(np.asarray(particles)["pos"], dtype=np.float32)
+    K = np.zeros(n_domains + 1, dtype=np.uint32)
+    rc = lib().oracle_nb_splitters(_ptr(pos), pos.shape[0], n_domains, _ptr(K))
+    if rc != 0:
+        raise RuntimeError(f"oracle_nb_splitters failed: {rc}")
+    return K
+
+
+def _nb_params(n_domains, cell_level, dt, theta, eps):
+    return NBParams(int(n_domains), int(cell_level), float(dt), float(theta), float(eps))
+
+
+def nb_seed(particles, K, cell_level=4, theta=0.5, eps=1e-3):
+    """Round 0 of the particle context: the input in any order to the owning
+    domains. Returns (queue, counts)."""
+    src = np.ascontiguousarray(particles, dtype=NB_PARTICLE)
+    D = len(K) - 1
+    q = np.zeros_like(src)
+    counts = np.zeros(D, dtype=np.uint64)
+    P = _nb_params(D, cell_level, 0.0, theta, eps)
+    K = np.ascontiguousarray(K, dtype=np.uint32)
+    rc = lib().oracle_nb_seed(C.byref(P), _ptr(K), _ptr(src), src.shape[0], _ptr(q), _ptr(counts))
+    if rc != 0:
+        raise RuntimeError(f"oracle_nb_seed failed: {rc}")
+    return q, counts
+
+
+def nb_step(queue, K, dt, cell_level=4, theta=0.5, eps=1e-3, log_cap=1 << 22):
+    """One step of O8 on a particle queue. Returns the new queue, the four
+    rounds' per-domain counts (particle, virtual 1, request, virtual 2) and
+    the three exchange queues."""
+    q = np.array(queue, dtype=NB_PARTICLE, copy=True)
+    D = len(K) - 1
+    P = _nb_params(D, cell_level, dt, theta, eps)
+    K = np.ascontiguousarray(K, dtype=np.uint32)
+    rc_counts = np.zeros((4, D), dtype=np.uint64)
+    cap1 = D * max(D - 1, 1)
+    vp1 = np.zeros(cap1, dtype=NB_VP)
+    rr = np.zeros(cap1, dtype=np.int32)
+    vp2 = np.zeros(log_cap, dtype=NB_VP)
+    lens = np.zeros(3, dtype=np.uint64)
+    rc = lib().oracle_nb_step(C.byref(P), _ptr(K), _ptr(q), q.shape[0], _ptr(rc_counts), _ptr(vp1), cap1,
+                              _ptr(rr), cap1, _ptr(vp2), log_cap, _ptr(lens))
+    if rc != 0:
+        raise RuntimeError(f"oracle_nb_step failed: {rc}")
+    n1, nr, n2 = (int(x) for x in lens)
+    if n2 > log_cap:
+        raise RuntimeError("second virtual-particle queue longer than log_cap")
+    return dict(queue=q, round_counts=rc_counts, vp1=vp1[:n1], rr=rr[:nr], vp2=vp2[:n2])

@@ -1036,3 +1036,360 @@ int oracle_dt_render(const float *vol, const orc_dt_params *P, const orc_view *v
     free(slots); free(queue); free(sdest); free(counts); free(offs);
     return rounds;
 }
+
+/* ======================================================================
+ * O8. Multi-context, multi-phase forwarding: one step of the distributed
+ * Barnes-Hut N-body code of Sec. 5.5, with the three item types of that
+ * section's listing, each in its own context:
+ *   Particle         {pos[3], vel[3], force[3], mass}          40 bytes
+ *   VirtualParticle  {pos[3], mass, smax, sourceRank}          24 bytes
+ *   RefinementReq    {senderRank}                               4 bytes
+ *
+ * Readings (the section describes the protocol, not its arithmetic):
+ *   - Domains are ranges of 30-bit Morton keys (10 bits per axis over the
+ *     unit box; Sec. 5.5 uses a Morton-order decomposition so that the owner
+ *     of any position is computed on the device). The D+1 splitters are the
+ *     keys of ranks floor(d N / D) of the sorted initial keys, K[0] = 0,
+ *     K[D] = 2^30; owner(key) = the largest d with K[d] <= key.
+ *   - The force slot of a Particle holds the acceleration (G = 1); the
+ *     integrator is kick-drift-kick leapfrog, positions wrap periodically
+ *     into [0, 1) and gravity is the open-boundary Plummer-softened sum.
+ *   - The per-domain hierarchy is the domain root and one level of Morton
+ *     cells (level L: key >> (30 - 3L)), in key order; cuBQL's BVH is not
+ *     rebuilt here. A node's mass is the float32 sum of its particles'
+ *     masses in key order and its centre of mass the fmaf-accumulated
+ *     first moment divided by that mass. A cell's size is its edge 2^-L;
+ *     the root's is the largest edge of the domain's particle bounding box.
+ *   - Acceptance (the multipole acceptance criterion of Barnes-Hut, tested
+ *     against the receiving domain's bounding box): size^2 < theta^2 d^2,
+ *     d the distance from the node's centre of mass to the box.
+ *   - Essential-tree exchange: every domain sends its root to every other
+ *     non-empty domain; a receiver that does not accept it returns a
+ *     RefinementReq; the owner answers with its cells that the requester
+ *     accepts, and with the particles (size 0) of those it does not. The
+ *     received nodes, in queue order, are the requester's remote list.
+ *   - Force on a particle: its domain's other particles in key order, then
+ *     the remote list in order, each as a softened point mass.
+ *   - Slots: the forward step keeps slot order within a destination (O1),
+ *     and fan-out uses fixed slots: root s -> r at s (D-1) + k; a request at
+ *     the slot of the root it answers; answers after the n1 slots of the
+ *     first VirtualParticle round, at n1 + the exclusive prefix of the
+ *     answer sizes in request-queue order.
+ * ====================================================================== */
+typedef struct {
+    int32_t n_domains, cell_level;
+    float dt, theta, eps;
+} orc_nb_params;
+
+typedef struct {
+    float pos[3], vel[3], acc[3], mass;
+} orc_nb_particle;
+
+typedef struct {
+    float pos[3], mass, smax;
+    int32_t src;
+} orc_nb_vp;
+
+uint32_t oracle_morton30(float x, float y, float z)
+{
+    const float c[3] = {x, y, z};
+    uint32_t key = 0;
+    for (int a = 0; a < 3; ++a) {
+        int32_t q = (int32_t)(c[a] * 1024.0f);
+        if (q < 0) q = 0;
+        if (q > 1023) q = 1023;
+        for (int b = 0; b < 10; ++b) key |= (uint32_t)((q >> b) & 1) << (3 * b + a);
+    }
+    return key;
+}
+
+static int32_t nb_owner(const uint32_t *K, int32_t D, uint32_t key)
+{
+    int32_t d = 0;
+    while (d + 1 < D && K[d + 1] <= key) ++d;
+    return d;
+}
+
+static int cmp_u32(const void *a, const void *b)
+{
+    const uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+int oracle_nb_splitters(const float *pos, int64_t n, int32_t D, uint32_t *K)
+{
+    if (D < 1 || n < 1) return -1;
+    uint32_t *keys = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+    if (!keys) return -2;
+    for (int64_t i = 0; i < n; ++i) keys[i] = oracle_morton30(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]);
+    qsort(keys, (size_t)n, sizeof(uint32_t), cmp_u32);
+    K[0] = 0;
+    for (int32_t d = 1; d < D; ++d) K[d] = keys[(int64_t)d * n / D];
+    K[D] = 1u << 30;
+    free(keys);
+    return 0;
+}
+
+static float nb_wrap(float x)
+{
+    x = x - floorf(x);
+    return x < 1.0f ? x : 0.0f;
+}
+
+static uint32_t nb_key(const orc_nb_particle *p) { return oracle_morton30(p->pos[0], p->pos[1], p->pos[2]); }
+
+/* a += m (q - p) / (|q - p|^2 + eps^2)^(3/2), in this operation order */
+static void nb_term(const float p[3], const float q[3], float m, float eps2, float a[3])
+{
+    const float dx = q[0] - p[0], dy = q[1] - p[1], dz = q[2] - p[2];
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+    const float inv = 1.0f / sqrtf(r2);
+    const float s = m * (inv * inv * inv);
+    a[0] = fmaf(s, dx, a[0]);
+    a[1] = fmaf(s, dy, a[1]);
+    a[2] = fmaf(s, dz, a[2]);
+}
+
+/* size^2 < theta^2 d^2, d = distance from c to the box [lo, hi] */
+static int nb_accept(const float c[3], float size, const float lo[3], const float hi[3], float theta)
+{
+    float d[3];
+    for (int a = 0; a < 3; ++a) d[a] = fmaxf(fmaxf(lo[a] - c[a], c[a] - hi[a]), 0.0f);
+    const float d2 = fmaf(d[2], d[2], fmaf(d[1], d[1], d[0] * d[0]));
+    return size * size < (theta * theta) * d2;
+}
+
+typedef struct {
+    int64_t first, count;   /* particle range in the sorted queue */
+    float com[3], mass;
+} nb_node;
+
+static void nb_moments(const orc_nb_particle *q, int64_t first, int64_t count, nb_node *nd)
+{
+    float m = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
+    for (int64_t i = first; i < first + count; ++i) {
+        m = m + q[i].mass;
+        mx = fmaf(q[i].mass, q[i].pos[0], mx);
+        my = fmaf(q[i].mass, q[i].pos[1], my);
+        mz = fmaf(q[i].mass, q[i].pos[2], mz);
+    }
+    nd->first = first;
+    nd->count = count;
+    nd->mass = m;
+    nd->com[0] = mx / m;
+    nd->com[1] = my / m;
+    nd->com[2] = mz / m;
+}
+
+/* Round 0: every particle of the input (any order) to the domain owning it. */
+int oracle_nb_seed(const orc_nb_params *P, const uint32_t *K, const orc_nb_particle *in, int64_t n,
+                   orc_nb_particle *queue, uint64_t *counts)
+{
+    const int32_t D = P->n_domains;
+    int32_t *dest = (int32_t *)calloc((size_t)(n ? n : 1), sizeof(int32_t));
+    uint64_t *offs = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(D + 1));
+    if (!dest || !offs) return -2;
+    for (int64_t i = 0; i < n; ++i) dest[i] = nb_owner(K, D, nb_key(&in[i]));
+    oracle_multisplit((uint64_t)n, sizeof(orc_nb_particle), (const uint8_t *)in, dest, D, (uint8_t *)queue,
+                      counts, offs, NULL, NULL);
+    free(dest); free(offs);
+    return 0;
+}
+
+/* order by key, then by position in the queue (a stable sort by key) */
+static const uint32_t *nb_cmp_keys;
+static int cmp_key_index(const void *a, const void *b)
+{
+    const int64_t i = *(const int64_t *)a, j = *(const int64_t *)b;
+    if (nb_cmp_keys[i] != nb_cmp_keys[j]) return nb_cmp_keys[i] < nb_cmp_keys[j] ? -1 : 1;
+    return i < j ? -1 : (i > j ? 1 : 0);
+}
+
+/*
+ * One step. queue: in, the particle queue the previous step (or the seed)
+ * left, grouped by domain; out, the new queue (grouped by domain, each
+ * domain in key order), with positions drifted and velocities and
+ * accelerations updated. Logs (any may be NULL): counts per domain of the
+ * four forward rounds in the order particle, virtual 1, request, virtual 2
+ * (round_counts[4][D]); the three exchange queues (vp1 [cap_vp1], rr
+ * [cap_rr], vp2 [cap_vp2]) and their lengths (lens[3]).
+ */
+int oracle_nb_step(const orc_nb_params *P, const uint32_t *K, orc_nb_particle *queue, int64_t n,
+                   uint64_t *round_counts, orc_nb_vp *vp1_log, uint64_t cap_vp1, int32_t *rr_log,
+                   uint64_t cap_rr, orc_nb_vp *vp2_log, uint64_t cap_vp2, uint64_t *lens)
+{
+    const int32_t D = P->n_domains, L = P->cell_level;
+    const float dt = P->dt, hdt = 0.5f * P->dt, eps2 = P->eps * P->eps;
+    const size_t nn = (size_t)(n ? n : 1);
+    orc_nb_particle *tmp = (orc_nb_particle *)malloc(sizeof(orc_nb_particle) * nn);
+    int32_t *dest = (int32_t *)calloc(nn, sizeof(int32_t));
+    uint64_t *counts = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)D);
+    uint64_t *offs = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(D + 1));
+    uint32_t *keys = (uint32_t *)malloc(sizeof(uint32_t) * nn);
+    int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * nn);
+    nb_node *cells = (nb_node *)malloc(sizeof(nb_node) * nn);
+    int64_t *cell_first = (int64_t *)malloc(sizeof(int64_t) * (size_t)(D + 1));
+    nb_node *root = (nb_node *)malloc(sizeof(nb_node) * (size_t)D);
+    float *lo = (float *)malloc(sizeof(float) * 3 * (size_t)D), *hi = (float *)malloc(sizeof(float) * 3 * (size_t)D);
+    float *rsize = (float *)malloc(sizeof(float) * (size_t)D);
+    if (!tmp || !dest || !counts || !offs || !keys || !idx || !cells || !cell_first || !root || !lo || !hi || !rsize)
+        return -2;
+
+    /* 1. kick (half), drift, wrap, owner: the Particle context's forward */
+    for (int64_t i = 0; i < n; ++i) {
+        orc_nb_particle *p = &queue[i];
+        for (int a = 0; a < 3; ++a) {
+            p->vel[a] = fmaf(hdt, p->acc[a], p->vel[a]);
+            p->pos[a] = nb_wrap(fmaf(dt, p->vel[a], p->pos[a]));
+        }
+        dest[i] = nb_owner(K, D, nb_key(p));
+    }
+    oracle_multisplit((uint64_t)n, sizeof(orc_nb_particle), (const uint8_t *)queue, dest, D, (uint8_t *)tmp,
+                      counts, offs, NULL, NULL);
+    if (round_counts) for (int32_t d = 0; d < D; ++d) round_counts[d] = counts[d];
+
+    /* 2. each domain in key order (stable): one sort of the whole queue by
+     * key, since a domain is a key range */
+    for (int64_t i = 0; i < n; ++i) { keys[i] = nb_key(&tmp[i]); idx[i] = i; }
+    nb_cmp_keys = keys;
+    qsort(idx, (size_t)n, sizeof(int64_t), cmp_key_index);
+    for (int64_t i = 0; i < n; ++i) queue[i] = tmp[idx[i]];
+    for (int64_t i = 0; i < n; ++i) keys[i] = nb_key(&queue[i]);
+
+    /* 3. cells (runs of one level-L prefix within a domain), roots, boxes */
+    const int sh = 30 - 3 * L;
+    const float csize = ldexpf(1.0f, -L);
+    int64_t nc = 0;
+    for (int32_t d = 0; d < D; ++d) {
+        cell_first[d] = nc;
+        int64_t i = (int64_t)offs[d];
+        const int64_t e = (int64_t)offs[d + 1];
+        while (i < e) {
+            int64_t j = i + 1;
+            while (j < e && (keys[j] >> sh) == (keys[i] >> sh)) ++j;
+            nb_moments(queue, i, j - i, &cells[nc++]);
+            i = j;
+        }
+        if (e > (int64_t)offs[d]) {
+            nb_moments(queue, (int64_t)offs[d], e - (int64_t)offs[d], &root[d]);
+            for (int a = 0; a < 3; ++a) { lo[3 * d + a] = queue[offs[d]].pos[a]; hi[3 * d + a] = queue[offs[d]].pos[a]; }
+            for (int64_t k = (int64_t)offs[d]; k < e; ++k)
+                for (int a = 0; a < 3; ++a) {
+                    lo[3 * d + a] = fminf(lo[3 * d + a], queue[k].pos[a]);
+                    hi[3 * d + a] = fmaxf(hi[3 * d + a], queue[k].pos[a]);
+                }
+            rsize[d] = fmaxf(fmaxf(hi[3 * d] - lo[3 * d], hi[3 * d + 1] - lo[3 * d + 1]), hi[3 * d + 2] - lo[3 * d + 2]);
+        } else {
+            root[d].count = 0;
+        }
+    }
+    cell_first[D] = nc;
+
+    /* 4. VirtualParticle round 1: every root to every other non-empty domain */
+    const int64_t n_r1 = (int64_t)D * (D - 1);
+    orc_nb_vp *vo = (orc_nb_vp *)malloc(sizeof(orc_nb_vp) * (size_t)(n_r1 ? n_r1 : 1));
+    orc_nb_vp *v1 = (orc_nb_vp *)malloc(sizeof(orc_nb_vp) * (size_t)(n_r1 ? n_r1 : 1));
+    int32_t *vdest = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_r1 ? n_r1 : 1));
+    uint64_t *o1 = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(D + 1));
+    if (!vo || !v1 || !vdest || !o1) return -2;
+    for (int32_t s = 0; s < D; ++s)
+        for (int32_t k = 0; k < D - 1; ++k) {
+            const int32_t r = k < s ? k : k + 1;
+            const int64_t slot = (int64_t)s * (D - 1) + k;
+            memset(&vo[slot], 0, sizeof(orc_nb_vp));
+            vdest[slot] = ORC_DONE;
+            if (root[s].count > 0 && counts[r] > 0) {
+                for (int a = 0; a < 3; ++a) vo[slot].pos[a] = root[s].com[a];
+                vo[slot].mass = root[s].mass;
+                vo[slot].smax = rsize[s];
+                vo[slot].src = s;
+                vdest[slot] = r;
+            }
+        }
+    oracle_multisplit((uint64_t)n_r1, sizeof(orc_nb_vp), (const uint8_t *)vo, vdest, D, (uint8_t *)v1, counts, o1,
+                      NULL, NULL);
+    const int64_t n1 = (int64_t)o1[D];
+    if (round_counts) for (int32_t d = 0; d < D; ++d) round_counts[D + d] = counts[d];
+    if (vp1_log) for (int64_t i = 0; i < n1 && (uint64_t)i < cap_vp1; ++i) vp1_log[i] = v1[i];
+
+    /* 5. accept a root, or return a RefinementReq to its owner */
+    int32_t *acc = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n1 ? n1 : 1));
+    int32_t *ro = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n1 ? n1 : 1));
+    int32_t *rq = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n1 ? n1 : 1));
+    int32_t *rdest = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n1 ? n1 : 1));
+    uint64_t *orr = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(D + 1));
+    if (!acc || !ro || !rq || !rdest || !orr) return -2;
+    for (int32_t r = 0; r < D; ++r)
+        for (int64_t i = (int64_t)o1[r]; i < (int64_t)o1[r + 1]; ++i) {
+            acc[i] = nb_accept(v1[i].pos, v1[i].smax, &lo[3 * r], &hi[3 * r], P->theta);
+            ro[i] = r;
+            rdest[i] = acc[i] ? ORC_DONE : v1[i].src;
+        }
+    oracle_multisplit((uint64_t)n1, sizeof(int32_t), (const uint8_t *)ro, rdest, D, (uint8_t *)rq, counts, orr,
+                      NULL, NULL);
+    const int64_t nr = (int64_t)orr[D];
+    if (round_counts) for (int32_t d = 0; d < D; ++d) round_counts[2 * D + d] = counts[d];
+    if (rr_log) for (int64_t i = 0; i < nr && (uint64_t)i < cap_rr; ++i) rr_log[i] = rq[i];
+
+    /* 6. answers: sizes, prefix, then the nodes */
+    int64_t *aoff = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nr + 1));
+    if (!aoff) return -2;
+    aoff[0] = 0;
+    for (int32_t s = 0; s < D; ++s)
+        for (int64_t j = (int64_t)orr[s]; j < (int64_t)orr[s + 1]; ++j) {
+            const int32_t r = rq[j];
+            int64_t c = 0;
+            for (int64_t k = cell_first[s]; k < cell_first[s + 1]; ++k)
+                c += nb_accept(cells[k].com, csize, &lo[3 * r], &hi[3 * r], P->theta) ? 1 : cells[k].count;
+            aoff[j + 1] = aoff[j] + c;
+        }
+    const int64_t n2 = n1 + aoff[nr];
+    orc_nb_vp *wo = (orc_nb_vp *)malloc(sizeof(orc_nb_vp) * (size_t)(n2 ? n2 : 1));
+    orc_nb_vp *v2 = (orc_nb_vp *)malloc(sizeof(orc_nb_vp) * (size_t)(n2 ? n2 : 1));
+    int32_t *wdest = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n2 ? n2 : 1));
+    uint64_t *o2 = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(D + 1));
+    if (!wo || !v2 || !wdest || !o2) return -2;
+    for (int64_t i = 0; i < n1; ++i) { wo[i] = v1[i]; wdest[i] = acc[i] ? ro[i] : ORC_DONE; }
+    for (int32_t s = 0; s < D; ++s)
+        for (int64_t j = (int64_t)orr[s]; j < (int64_t)orr[s + 1]; ++j) {
+            const int32_t r = rq[j];
+            int64_t slot = n1 + aoff[j];
+            for (int64_t k = cell_first[s]; k < cell_first[s + 1]; ++k) {
+                if (nb_accept(cells[k].com, csize, &lo[3 * r], &hi[3 * r], P->theta)) {
+                    orc_nb_vp *v = &wo[slot];
+                    for (int a = 0; a < 3; ++a) v->pos[a] = cells[k].com[a];
+                    v->mass = cells[k].mass; v->smax = csize; v->src = s;
+                    wdest[slot++] = r;
+                } else {
+                    for (int64_t q = cells[k].first; q < cells[k].first + cells[k].count; ++q) {
+                        orc_nb_vp *v = &wo[slot];
+                        for (int a = 0; a < 3; ++a) v->pos[a] = queue[q].pos[a];
+                        v->mass = queue[q].mass; v->smax = 0.0f; v->src = s;
+                        wdest[slot++] = r;
+                    }
+                }
+            }
+        }
+    oracle_multisplit((uint64_t)n2, sizeof(orc_nb_vp), (const uint8_t *)wo, wdest, D, (uint8_t *)v2, counts, o2,
+                      NULL, NULL);
+    if (round_counts) for (int32_t d = 0; d < D; ++d) round_counts[3 * D + d] = counts[d];
+    if (vp2_log) for (int64_t i = 0; i < (int64_t)o2[D] && (uint64_t)i < cap_vp2; ++i) vp2_log[i] = v2[i];
+    if (lens) { lens[0] = (uint64_t)n1; lens[1] = (uint64_t)nr; lens[2] = o2[D]; }
+
+    /* 7. forces (own domain, then the remote list) and the second half-kick */
+    for (int32_t r = 0; r < D; ++r)
+        for (int64_t i = (int64_t)offs[r]; i < (int64_t)offs[r + 1]; ++i) {
+            float a[3] = {0.0f, 0.0f, 0.0f};
+            for (int64_t j = (int64_t)offs[r]; j < (int64_t)offs[r + 1]; ++j)
+                if (j != i) nb_term(queue[i].pos, queue[j].pos, queue[j].mass, eps2, a);
+            for (int64_t k = (int64_t)o2[r]; k < (int64_t)o2[r + 1]; ++k) nb_term(queue[i].pos, v2[k].pos, v2[k].mass, eps2, a);
+            for (int c = 0; c < 3; ++c) {
+                queue[i].acc[c] = a[c];
+                queue[i].vel[c] = fmaf(hdt, a[c], queue[i].vel[c]);
+            }
+        }
+    free(tmp); free(dest); free(counts); free(offs); free(keys); free(idx); free(cells); free(cell_first); free(root);
+    free(lo); free(hi); free(rsize); free(vo); free(v1); free(vdest); free(o1); free(acc); free(ro); free(rq);
+    free(rdest); free(orr); free(aoff); free(wo); free(v2); free(wdest); free(o2);
+    return 0;
+}

@@ -46,6 +46,7 @@ SEED_ADJ_VOLUME = 6
 SEED_ADJ_TARGET = 7
 SEED_ADJ_VIEWS = 8
 SEED_ADJ_FD = 9
+SEED_NBODY = 10
 
 
 # ---------------------------------------------------------------- volumes ---
@@ -170,6 +171,35 @@ def streamline_seeds(n_seeds: int, n: int, seed: int = SEED_CFG1_SEEDS) -> np.nd
     below = np.nextafter(np.float32(n), np.float32(0))
     np.minimum(p, below, out=p)
     return p
+
+
+# ------------------------------------------------------ N-body particles ---
+
+# One particle record as the N-body contexts carry it (40 bytes): position,
+# velocity, acceleration (the item's force slot), mass.
+NB_PARTICLE_DTYPE = np.dtype([("pos", "<f4", 3), ("vel", "<f4", 3), ("acc", "<f4", 3), ("mass", "<f4")])
+assert NB_PARTICLE_DTYPE.itemsize == 40
+
+
+def nbody_particles(n: int, seed: int = SEED_NBODY, n_clumps: int = 8, sigma: float = 0.06,
+                    vel_sigma: float = 0.02) -> np.ndarray:
+    """Clustered particles in the unit box: n_clumps Gaussian clumps (centres
+    U[0,1)^3, spread sigma per axis), wrapped periodically into [0, 1),
+    Gaussian velocities (vel_sigma per axis), zero acceleration, equal masses
+    1/n. Draw order: centres, clump of each particle, offsets, velocities."""
+    rng = np.random.default_rng(seed)
+    centres = rng.random((n_clumps, 3))
+    which = rng.integers(0, n_clumps, n)
+    pos = centres[which] + rng.normal(0.0, sigma, (n, 3))
+    pos = pos - np.floor(pos)
+    vel = rng.normal(0.0, vel_sigma, (n, 3))
+    out = np.zeros(n, dtype=NB_PARTICLE_DTYPE)
+    p32 = pos.astype(np.float32)
+    p32[p32 >= np.float32(1.0)] = np.float32(0.0)
+    out["pos"] = p32
+    out["vel"] = vel.astype(np.float32)
+    out["mass"] = np.float32(1.0 / n)
+    return out
 
 
 # ------------------------------------------------------------ split draws ---
