@@ -502,6 +502,80 @@ int rafi_dt_trace(rafi_ctx *ctx, const rafi_dt_job *job);
  * left; then image (if set). *rounds receives the number of forward steps. */
 int rafi_dt_render(rafi_ctx *ctx, const rafi_dt_job *job, int32_t max_rounds, int32_t *rounds);
 
+/* ======================================================================
+ * Multi-context, multi-phase forwarding: the N-body essential-tree exchange
+ * (Sec. 5.5). Three contexts with the three item types of that section's
+ * listing, on one stream, with the same n_domains:
+ *   particles  Particle {float pos[3], vel[3], force[3], mass}   40 bytes
+ *   virtuals   VirtualParticle {float pos[3], mass, smax;
+ *                               int32 sourceRank}                 24 bytes
+ *   requests   RefinementReq {int32 senderRank}                    4 bytes
+ * The force slot holds the acceleration (G = 1). Domains are ranges of
+ * 30-bit Morton keys over the unit box (10 bits per axis, the cell of a
+ * coordinate c being min(1023, (int)(c * 1024))); owner(key) = the largest
+ * d with splitters[d] <= key.
+ * ====================================================================== */
+#define RAFI_NB_PARTICLE_BYTES 40
+#define RAFI_NB_VIRTUAL_BYTES 24
+#define RAFI_NB_REQUEST_BYTES 4
+
+typedef struct rafi_nb_job {
+    int32_t n_domains;            /* 1..1024, the three contexts' n_domains */
+    int32_t cell_level;           /* 1..10: the hierarchy's cells are Morton cells of edge 2^-cell_level */
+    float dt;                     /* leapfrog step (kick-drift-kick) */
+    float theta;                  /* acceptance: node size^2 < theta^2 distance^2 to the receiver's box */
+    float eps;                    /* Plummer softening length */
+    const uint32_t *splitters;    /* device [n_domains + 1], from rafi_nb_splitters */
+    void *workspace;              /* device, rafi_nb_workspace(capacity, n_domains) bytes */
+    uint64_t capacity;            /* particles the workspace was sized for */
+    void *log_vp1;                /* device, optional: receives the first virtual-particle queue */
+    uint64_t log_vp1_cap;         /* items log_vp1 holds */
+} rafi_nb_job;
+
+/* Workspace bytes for up to n_particles particles (< 2^31) over n_domains. */
+int rafi_nb_workspace(uint64_t n_particles, int32_t n_domains, uint64_t *bytes);
+
+/* Morton-order decomposition: splitters[0] = 0, splitters[d] = the key of
+ * rank floor(d n / D) among the n particles' keys, splitters[D] = 2^30.
+ * particles: device [n] Particle records; splitters: device [D + 1];
+ * workspace as for rafi_nb_workspace(n, D). Enqueued on hip_stream. */
+int rafi_nb_splitters(const void *particles, uint64_t n, int32_t n_domains, uint32_t *splitters,
+                      void *workspace, void *hip_stream);
+
+/* Round 0 of the particle context: every particle (device [n], any order)
+ * to the domain owning its position, then one rafi_round. */
+int rafi_nb_seed(rafi_ctx *particles, const rafi_nb_job *job, const void *in, uint64_t n);
+
+/* One step on the particle queue the last seed or step left:
+ *   1. half-kick, drift, periodic wrap into [0, 1); forward to the owner
+ *      (particle round);
+ *   2. each domain's particles in Morton-key order (stable);
+ *   3. per domain: cells (runs of one level-cell_level key prefix) and a
+ *      root, each with its mass and centre of mass (float32 sums in key
+ *      order); the particles' bounding box (root size = its largest edge,
+ *      cell size = 2^-cell_level);
+ *   4. virtual round 1: root s to every other non-empty domain r at slot
+ *      s (D - 1) + (r < s ? r : r - 1);
+ *   5. request round: receiver r keeps a root it accepts, else sends
+ *      RefinementReq{r} to its owner from the root's slot;
+ *   6. virtual round 2: kept roots at their slots, then each request's
+ *      answer (the owner's cells r accepts, the particles of the others,
+ *      in key order) after the n1 round-1 slots, at the exclusive prefix of
+ *      the answer sizes in request-queue order;
+ *   7. forces: for each particle the softened sum over its domain's other
+ *      particles in key order, then its remote list in queue order; then
+ *      the second half-kick.
+ * Afterwards the particle context's queue holds the particles (domain
+ * grouped, key ordered within a domain), the request context's the
+ * requests and the virtual context's the remote lists. round_counts (host
+ * [4][D], optional): per-domain counts of the particle, virtual 1, request
+ * and virtual 2 rounds; sizes (host [3], optional): the lengths of the
+ * virtual 1, request and virtual 2 queues. RAFI_ERR_OVERFLOW if the
+ * answers do not fit the virtual context (nothing of round 2 is emitted);
+ * RAFI_ERR_ARG for mismatched contexts, streams or sizes. */
+int rafi_nb_step(rafi_ctx *particles, rafi_ctx *virtuals, rafi_ctx *requests, const rafi_nb_job *job,
+                 uint64_t *round_counts, uint64_t *sizes);
+
 #ifdef __cplusplus
 }
 #endif

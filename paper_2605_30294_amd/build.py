@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librafi.so")
 
-SOURCES = ["context.hip", "multisplit.hip", "ea.hip", "streamline.hip", "batched.hip", "dt.hip"]
+SOURCES = ["context.hip", "multisplit.hip", "ea.hip", "streamline.hip", "batched.hip", "dt.hip", "nbody.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -1,0 +1,734 @@
+// Multi-context, multi-phase forwarding: one step of the distributed
+// Barnes-Hut N-body code of Sec. 5.5, with the three item types of that
+// section's listing in three contexts of their own (particles 40 bytes,
+// virtual particles 24 bytes, refinement requests 4 bytes).
+//
+// A step, all on one stream:
+//   1. particle context: half-kick, drift, periodic wrap, and a forward to
+//      the domain owning the new position (a range of 30-bit Morton keys);
+//   2. each domain's particles put in key order (three stable 10-bit splits
+//      of the whole queue by key digit: a domain is a key range);
+//   3. the domain hierarchy: Morton cells of level L (runs of one key prefix
+//      within a domain) and the domain root, with mass and centre of mass;
+//      the domain's bounding box;
+//   4. virtual-particle context, round 1: every root to every other
+//      non-empty domain;
+//   5. request context: a receiver keeps a root it accepts (Barnes-Hut
+//      acceptance against its own box) and sends a refinement request to
+//      the owner of one it does not;
+//   6. virtual-particle context, round 2: the accepted roots, and each
+//      owner's answer to each request: its cells that the requester
+//      accepts, and the particles of those it does not. Answers take fixed
+//      slots after a prefix sum of their sizes, so the queues are the same
+//      on every run;
+//   7. forces (the domain's own particles, then its remote list) and the
+//      second half-kick.
+#include "internal.h"
+#include "ea_device.h"
+#include "rafi_device.h"
+#include "split_device.h"
+
+namespace rafi {
+namespace {
+
+struct NBParticle {
+    float pos[3], vel[3], acc[3], mass;
+};
+struct NBVirtual {
+    float pos[3], mass, smax;
+    int32_t src;
+};
+struct NBRequest {
+    int32_t sender;
+};
+static_assert(sizeof(NBParticle) == RAFI_NB_PARTICLE_BYTES, "particle layout");
+static_assert(sizeof(NBVirtual) == RAFI_NB_VIRTUAL_BYTES, "virtual particle layout");
+static_assert(sizeof(NBRequest) == RAFI_NB_REQUEST_BYTES, "request layout");
+
+struct NBNode {
+    float com[3], mass;
+    uint32_t first, count;
+};
+struct NBBox {
+    float lo[3], hi[3], size;
+};
+
+constexpr int kNBThreads = 256;
+constexpr uint32_t kDigitBuckets = 1024;  // 10-bit key digits
+
+// Spread the low 10 bits of v to every third bit.
+__device__ inline uint32_t spread3(uint32_t v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__device__ inline uint32_t cell_coord(float c)
+{
+    const int32_t q = (int32_t)(c * 1024.0f);
+    return (uint32_t)min(max(q, 0), 1023);
+}
+
+__device__ inline uint32_t morton_key(const float p[3])
+{
+    return spread3(cell_coord(p[0])) | (spread3(cell_coord(p[1])) << 1) | (spread3(cell_coord(p[2])) << 2);
+}
+
+// The largest d in [0, D) with K[d] <= key (K[0] = 0).
+__device__ inline int32_t key_owner(const uint32_t *__restrict__ K, int32_t D, uint32_t key)
+{
+    int32_t lo = 0, hi = D - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (K[mid] <= key) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline float wrap_unit(float x)
+{
+    x = x - floorf(x);
+    return x < 1.0f ? x : 0.0f;
+}
+
+// size^2 < theta^2 d^2, d = distance from c to the box
+__device__ inline bool accepts(const float c[3], float size, const NBBox &b, float theta)
+{
+    float d[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d[a] = fmaxf(fmaxf(b.lo[a] - c[a], c[a] - b.hi[a]), 0.0f);
+    const float d2 = __fmaf_rn(d[2], d[2], __fmaf_rn(d[1], d[1], d[0] * d[0]));
+    return size * size < (theta * theta) * d2;
+}
+
+// a += m (q - p) / (|q - p|^2 + eps^2)^(3/2), in this operation order
+__device__ inline void gravity(const float p[3], const float q[3], float m, float eps2, float a[3])
+{
+    const float dx = q[0] - p[0], dy = q[1] - p[1], dz = q[2] - p[2];
+    const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmaf_rn(dx, dx, eps2)));
+    const float inv = 1.0f / sqrtf(r2);
+    const float s = m * (inv * inv * inv);
+    a[0] = __fmaf_rn(s, dx, a[0]);
+    a[1] = __fmaf_rn(s, dy, a[1]);
+    a[2] = __fmaf_rn(s, dz, a[2]);
+}
+
+// Mass and centre of mass of particles [first, first + count), summed in order.
+__device__ inline NBNode moments(const NBParticle *__restrict__ q, uint32_t first, uint32_t count)
+{
+    float m = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
+    for (uint32_t i = first; i < first + count; ++i) {
+        const NBParticle p = q[i];
+        m = m + p.mass;
+        mx = __fmaf_rn(p.mass, p.pos[0], mx);
+        my = __fmaf_rn(p.mass, p.pos[1], my);
+        mz = __fmaf_rn(p.mass, p.pos[2], mz);
+    }
+    NBNode nd;
+    nd.com[0] = mx / m;
+    nd.com[1] = my / m;
+    nd.com[2] = mz / m;
+    nd.mass = m;
+    nd.first = first;
+    nd.count = count;
+    return nd;
+}
+
+// ----------------------------------------------------------- workspace ---
+struct NBLayout {
+    uint64_t off_tmp, off_digit, off_split, off_offsets, off_summary, off_flags, off_cell_of, off_cell_start,
+        off_cells, off_roots, off_boxes, off_dcell, off_acc, off_cnt, off_aoff, off_part, off_counters, bytes;
+};
+
+constexpr uint32_t kScanTile = 1024;  // elements per block of the scan helper
+
+NBLayout nb_layout(uint64_t n, int32_t D)
+{
+    NBLayout L;
+    const uint64_t n1 = std::max<uint64_t>(n, 1);
+    const uint64_t nr = std::max<uint64_t>((uint64_t)D * (uint64_t)(D > 1 ? D - 1 : 1), 1);
+    const uint64_t scan_n = std::max(n1, nr);
+    // every split of up to n1 slots fits the bound plan's workspace
+    const uint64_t split_bytes = std::max(split_plan_bound(n1, (int32_t)kDigitBuckets, RAFI_NB_PARTICLE_BYTES).bytes,
+                                          split_plan_bound(n1, (int32_t)kDigitBuckets, 4).bytes);
+    uint64_t o = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t at = o;
+        o += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    L.off_tmp = take(n1 * sizeof(NBParticle));
+    L.off_digit = take(n1 * sizeof(int32_t));
+    L.off_split = take(split_bytes);
+    L.off_offsets = take((kDigitBuckets + 1) * sizeof(uint64_t));
+    L.off_summary = take(8 * sizeof(uint64_t));
+    L.off_flags = take(n1 * sizeof(uint32_t));
+    L.off_cell_of = take(n1 * sizeof(uint32_t));
+    L.off_cell_start = take(n1 * sizeof(uint32_t));
+    L.off_cells = take(n1 * sizeof(NBNode));
+    L.off_roots = take((uint64_t)D * sizeof(NBNode));
+    L.off_boxes = take((uint64_t)D * sizeof(NBBox));
+    L.off_dcell = take((uint64_t)D * 2 * sizeof(uint32_t));
+    L.off_acc = take(nr * sizeof(int32_t));
+    L.off_cnt = take(nr * sizeof(uint32_t));
+    L.off_aoff = take(nr * sizeof(uint32_t));
+    L.off_part = take(((scan_n + kScanTile - 1) / kScanTile + 1) * sizeof(uint32_t));
+    L.off_counters = take(4 * sizeof(uint32_t));
+    L.bytes = o;
+    return L;
+}
+
+template <typename T>
+T *at(void *ws, uint64_t off)
+{
+    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+// ------------------------------------------------- exclusive scan, u32 ---
+// out[i] = sum of in[0..i); *total = the sum of all n. Blocks of kScanTile
+// elements scan locally, one block scans the block sums, a last pass adds
+// them. n < 2^32 and the sum fits 32 bits.
+__global__ void __launch_bounds__(256) scan_tiles_kernel(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                                        uint64_t n, uint32_t *__restrict__ part)
+{
+    __shared__ uint32_t lds[256 / 64 + 1];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + threadIdx.x * 4;
+    uint32_t v[4], s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = dev::block_excl_scan<256>(s, lds, &tot);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024) scan_parts_kernel(uint32_t *__restrict__ part, uint32_t nb,
+                                                         uint32_t *__restrict__ total)
+{
+    __shared__ uint32_t lds[1024 / 64 + 1];
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < nb; b0 += 1024) {
+        const uint32_t b = b0 + threadIdx.x;
+        const uint32_t v = b < nb ? part[b] : 0u;
+        uint32_t tot;
+        const uint32_t run = dev::block_excl_scan<1024>(v, lds, &tot);
+        if (b < nb) part[b] = carry + run;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void __launch_bounds__(256) scan_add_kernel(uint32_t *__restrict__ out, uint64_t n,
+                                                      const uint32_t *__restrict__ part)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] += part[i / kScanTile];
+}
+
+int scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *part, uint32_t *total, hipStream_t s)
+{
+    const uint32_t nb = (uint32_t)std::max<uint64_t>(1, (n + kScanTile - 1) / kScanTile);
+    hipLaunchKernelGGL(scan_tiles_kernel, dim3(nb), dim3(256), 0, s, in, out, n, part);
+    hipLaunchKernelGGL(scan_parts_kernel, dim3(1), dim3(1024), 0, s, part, nb, total);
+    if (n) hipLaunchKernelGGL(scan_add_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, out, n, part);
+    RAFI_LAUNCH_CHECK();
+    return RAFI_OK;
+}
+
+// ------------------------------------------------------------- kernels ---
+__global__ void __launch_bounds__(kNBThreads) nb_seed_kernel(rafi_device_view P, const uint32_t *__restrict__ K,
+                                                            const NBParticle *__restrict__ in, uint64_t n)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kNBThreads + threadIdx.x;
+    if (i >= n) return;
+    const NBParticle p = in[i];
+    rafi_forward_t(P, i, p, key_owner(K, P.n_domains, morton_key(p.pos)));
+}
+
+__global__ void __launch_bounds__(kNBThreads) nb_drift_kernel(rafi_device_view P, const uint32_t *__restrict__ K,
+                                                             float dt, float hdt)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kNBThreads + threadIdx.x;
+    if (i >= P.n_in) return;
+    NBParticle p = static_cast<const NBParticle *>(P.in_items)[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        p.vel[a] = __fmaf_rn(hdt, p.acc[a], p.vel[a]);
+        p.pos[a] = wrap_unit(__fmaf_rn(dt, p.vel[a], p.pos[a]));
+    }
+    rafi_forward_t(P, i, p, key_owner(K, P.n_domains, morton_key(p.pos)));
+}
+
+__global__ void __launch_bounds__(kNBThreads) nb_key_kernel(const NBParticle *__restrict__ q, uint64_t n,
+                                                           uint32_t *__restrict__ key)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kNBThreads + threadIdx.x;
+    if (i < n) key[i] = morton_key(q[i].pos);
+}
+
+__global__ void __launch_bounds__(kNBThreads) nb_key_digit_kernel(const uint32_t *__restrict__ key, uint64_t n,
+                                                                 int shift, int32_t *__restrict__ digit)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kNBThreads + threadIdx.x;
+    if (i < n) digit[i] = (int32_t)((key[i] >> shift) & (kDigitBuckets - 1));
+}
+
+// K[0] = 0, K[d] = sorted[d n / D], K[D] = 2^30
+__global__ void __launch_bounds__(kNBThreads) nb_pick_kernel(const uint32_t *__restrict__ sorted, uint64_t n,
+                                                            int32_t D, uint32_t *__restrict__ K)
+{
+    const int32_t d = blockIdx.x * kNBThreads + threadIdx.x;
+    if (d > D) return;
+    K[d] = d == 0 ? 0u : (d == D ? (1u << 30) : sorted[(uint64_t)d * n / (uint64_t)D]);
+}
+
+__global__ void __launch_bounds__(kNBThreads) nb_digit_kernel(const NBParticle *__restrict__ q, uint64_t n,
+                                                             int shift, int32_t *__restrict__ digit)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kNBThreads + threadIdx.x;
+    if (i < n) digit[i] = (int32_t)((morton_key(q[i].pos) >> shift) & (kDigitBuckets - 1));
+}
+
+// flags[i] = 1 where a new cell starts: a new level-L key prefix or a new domain
+__global__ void __launch_bounds__(kNBThreads) nb_flag_kernel(const NBParticle *__restrict__ q, uint64_t n,
+                                                            const uint32_t *__restrict__ K, int32_t D, int shift,
+                                                            uint32_t *__restrict__ flags)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kNBThreads + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t k = morton_key(q[i].pos);
+    uint32_t f = 1;
+    if (i > 0) {
+        const uint32_t kp = morton_key(q[i - 1].pos);
+        f = ((k >> shift) != (kp >> shift) || key_owner(K, D, k) != key_owner(K, D, kp)) ? 1u : 0u;
+    }
+    flags[i] = f;
+}
+
+__global__ void __launch_bounds__(kNBThreads) nb_cell_start_kernel(const uint32_t *__restrict__ flags,
+                                                                  const uint32_t *__restrict__ cell_of, uint64_t n,
+                                                                  uint32_t *__restrict__ cell_start)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kNBThreads + threadIdx.x;
+    if (i < n && flags[i]) cell_start[cell_of[i]] = (uint32_t)i;
+}
+
+__global__ void __launch_bounds__(kNBThreads) nb_cells_kernel(const NBParticle *__restrict__ q, uint64_t n,
+                                                             const uint32_t *__restrict__ n_cells,
+                                                             const uint32_t *__restrict__ cell_start,
+                                                             NBNode *__restrict__ cells)
+{
+    const uint32_t c = blockIdx.x * kNBThreads + threadIdx.x;
+    const uint32_t nc = *n_cells;
+    if (c >= nc) return;
+    const uint32_t first = cell_start[c];
+    const uint32_t end = c + 1 < nc ? cell_start[c + 1] : (uint32_t)n;
+    cells[c] = moments(q, first, end - first);
+}
+
+// One thread per domain: root moments, bounding box, root size, cell range.
+// cell_of is the exclusive prefix of the cell-start flags: at a cell's
+// first particle it is that cell's index, so a domain's cells run from
+// cell_of[its first particle] to cell_of[the next domain's first particle]
+// (the cell count n_cells after the last particle).
+__global__ void __launch_bounds__(64) nb_domain_kernel(const NBParticle *__restrict__ q,
+                                                      const uint64_t *__restrict__ off, int32_t D, uint64_t n,
+                                                      const uint32_t *__restrict__ cell_of,
+                                                      const uint32_t *__restrict__ n_cells, NBNode *__restrict__ roots,
+                                                      NBBox *__restrict__ boxes, uint32_t *__restrict__ dcell)
+{
+    const int32_t d = blockIdx.x * 64 + threadIdx.x;
+    if (d >= D) return;
+    const uint32_t first = (uint32_t)off[d], count = (uint32_t)(off[d + 1] - off[d]);
+    NBNode r{};
+    NBBox b{};
+    if (count) {
+        r = moments(q, first, count);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) b.lo[a] = b.hi[a] = q[first].pos[a];
+        for (uint32_t i = first; i < first + count; ++i)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                b.lo[a] = fminf(b.lo[a], q[i].pos[a]);
+                b.hi[a] = fmaxf(b.hi[a], q[i].pos[a]);
+            }
+        b.size = fmaxf(fmaxf(b.hi[0] - b.lo[0], b.hi[1] - b.lo[1]), b.hi[2] - b.lo[2]);
+        dcell[2 * d] = cell_of[first];
+        dcell[2 * d + 1] = (uint64_t)first + count < n ? cell_of[first + count] : *n_cells;
+    } else {
+        dcell[2 * d] = dcell[2 * d + 1] = 0;
+    }
+    r.count = count;
+    roots[d] = r;
+    boxes[d] = b;
+}
+
+// Virtual-particle round 1: slot s (D - 1) + k carries root s to domain
+// r = k (+1 from s on), if both domains hold particles.
+__global__ void __launch_bounds__(kNBThreads) nb_roots_kernel(rafi_device_view V, const NBNode *__restrict__ roots,
+                                                             const NBBox *__restrict__ boxes, int32_t D)
+{
+    const uint64_t slot = (uint64_t)blockIdx.x * kNBThreads + threadIdx.x;
+    const uint64_t n = (uint64_t)D * (uint64_t)(D - 1);
+    if (slot >= n) return;
+    const int32_t s = (int32_t)(slot / (uint64_t)(D - 1)), k = (int32_t)(slot % (uint64_t)(D - 1));
+    const int32_t r = k < s ? k : k + 1;
+    if (roots[s].count == 0 || roots[r].count == 0) {
+        rafi_done(V, slot);
+        return;
+    }
+    NBVirtual v;
+    v.pos[0] = roots[s].com[0];
+    v.pos[1] = roots[s].com[1];
+    v.pos[2] = roots[s].com[2];
+    v.mass = roots[s].mass;
+    v.smax = boxes[s].size;
+    v.src = s;
+    rafi_forward_t(V, slot, v, r);
+}
+
+// A receiver accepts a root or asks its owner for more (request at the same slot).
+__global__ void __launch_bounds__(kNBThreads) nb_accept_kernel(rafi_device_view V, rafi_device_view Rq,
+                                                              const NBBox *__restrict__ boxes, float theta,
+                                                              int32_t *__restrict__ acc)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kNBThreads + threadIdx.x;
+    if (i >= V.n_in) return;
+    const int32_t r = ea::find_domain(V.in_offsets, V.n_domains, i);
+    const NBVirtual v = static_cast<const NBVirtual *>(V.in_items)[i];
+    const bool a = accepts(v.pos, v.smax, boxes[r], theta);
+    acc[i] = a ? 1 : 0;
+    if (a) {
+        rafi_done(Rq, i);
+    } else {
+        rafi_forward_t(Rq, i, NBRequest{r}, v.src);
+    }
+}
+
+// Size of the answer to request j: one node per accepted cell, else its particles.
+__global__ void __launch_bounds__(kNBThreads) nb_answer_size_kernel(rafi_device_view Rq, const NBNode *__restrict__ cells,
+                                                                   const uint32_t *__restrict__ dcell,
+                                                                   const NBBox *__restrict__ boxes, float theta,
+                                                                   float csize, uint32_t *__restrict__ cnt)
+{
+    const uint64_t j = (uint64_t)blockIdx.x * kNBThreads + threadIdx.x;
+    if (j >= Rq.n_in) return;
+    const int32_t s = ea::find_domain(Rq.in_offsets, Rq.n_domains, j);
+    const int32_t r = static_cast<const NBRequest *>(Rq.in_items)[j].sender;
+    const NBBox b = boxes[r];
+    uint32_t c = 0;
+    for (uint32_t k = dcell[2 * s]; k < dcell[2 * s + 1]; ++k)
+        c += accepts(cells[k].com, csize, b, theta) ? 1u : cells[k].count;
+    cnt[j] = c;
+}
+
+// Virtual-particle round 2, first n1 slots: the accepted roots stay with their receiver.
+__global__ void __launch_bounds__(kNBThreads) nb_keep_kernel(rafi_device_view V, const int32_t *__restrict__ acc)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kNBThreads + threadIdx.x;
+    if (i >= V.n_in) return;
+    if (acc[i]) {
+        const int32_t r = ea::find_domain(V.in_offsets, V.n_domains, i);
+        rafi_forward_t(V, i, static_cast<const NBVirtual *>(V.in_items)[i], r);
+    } else {
+        rafi_done(V, i);
+    }
+}
+
+// Virtual-particle round 2, the answers: request j fills slots n1 + aoff[j] + ...
+__global__ void __launch_bounds__(kNBThreads) nb_answer_kernel(rafi_device_view V, rafi_device_view Rq,
+                                                              const NBParticle *__restrict__ q,
+                                                              const NBNode *__restrict__ cells,
+                                                              const uint32_t *__restrict__ dcell,
+                                                              const NBBox *__restrict__ boxes, float theta,
+                                                              float csize, const uint32_t *__restrict__ aoff,
+                                                              uint64_t n1)
+{
+    const uint64_t j = (uint64_t)blockIdx.x * kNBThreads + threadIdx.x;
+    if (j >= Rq.n_in) return;
+    const int32_t s = ea::find_domain(Rq.in_offsets, Rq.n_domains, j);
+    const int32_t r = static_cast<const NBRequest *>(Rq.in_items)[j].sender;
+    const NBBox b = boxes[r];
+    uint64_t slot = n1 + aoff[j];
+    for (uint32_t k = dcell[2 * s]; k < dcell[2 * s + 1]; ++k) {
+        const NBNode c = cells[k];
+        if (accepts(c.com, csize, b, theta)) {
+            NBVirtual v;
+            v.pos[0] = c.com[0];
+            v.pos[1] = c.com[1];
+            v.pos[2] = c.com[2];
+            v.mass = c.mass;
+            v.smax = csize;
+            v.src = s;
+            rafi_forward_t(V, slot++, v, r);
+        } else {
+            for (uint32_t i = c.first; i < c.first + c.count; ++i) {
+                NBVirtual v;
+                v.pos[0] = q[i].pos[0];
+                v.pos[1] = q[i].pos[1];
+                v.pos[2] = q[i].pos[2];
+                v.mass = q[i].mass;
+                v.smax = 0.0f;
+                v.src = s;
+                rafi_forward_t(V, slot++, v, r);
+            }
+        }
+    }
+}
+
+// Forces: the domain's other particles in key order, then its remote list;
+// then the second half-kick. Writes only velocity and acceleration, so the
+// positions other threads read do not change.
+__global__ void __launch_bounds__(kNBThreads) nb_force_kernel(NBParticle *__restrict__ q, const uint64_t *__restrict__ off,
+                                                             int32_t D, uint64_t n, rafi_device_view V, float eps2,
+                                                             float hdt)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kNBThreads + threadIdx.x;
+    if (i >= n) return;
+    const int32_t r = ea::find_domain(off, D, i);
+    float p[3] = {q[i].pos[0], q[i].pos[1], q[i].pos[2]};
+    float a[3] = {0.0f, 0.0f, 0.0f};
+    for (uint64_t j = off[r]; j < off[r + 1]; ++j) {
+        if (j == i) continue;
+        const float o[3] = {q[j].pos[0], q[j].pos[1], q[j].pos[2]};
+        gravity(p, o, q[j].mass, eps2, a);
+    }
+    const NBVirtual *rem = static_cast<const NBVirtual *>(V.in_items);
+    for (uint64_t k = V.in_offsets[r]; k < V.in_offsets[r + 1]; ++k) {
+        const NBVirtual v = rem[k];
+        gravity(p, v.pos, v.mass, eps2, a);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        q[i].acc[c] = a[c];
+        q[i].vel[c] = __fmaf_rn(hdt, a[c], q[i].vel[c]);
+    }
+}
+
+uint32_t blocks_for(uint64_t n) { return (uint32_t)std::max<uint64_t>(1, (n + kNBThreads - 1) / kNBThreads); }
+
+bool job_ok(const rafi_nb_job *j)
+{
+    return j && j->n_domains >= 1 && j->n_domains <= 1024 && j->cell_level >= 1 && j->cell_level <= 10 &&
+           j->splitters && j->workspace && j->theta >= 0.0f && j->eps >= 0.0f;
+}
+
+}  // namespace
+}  // namespace rafi
+
+using namespace rafi;
+
+extern "C" {
+
+int rafi_nb_workspace(uint64_t n_particles, int32_t n_domains, uint64_t *bytes)
+{
+    if (!bytes || n_domains < 1 || n_domains > 1024 || n_particles >= (1ull << 31)) return RAFI_ERR_ARG;
+    *bytes = nb_layout(n_particles, n_domains).bytes;
+    return RAFI_OK;
+}
+
+int rafi_nb_splitters(const void *particles, uint64_t n, int32_t n_domains, uint32_t *splitters, void *workspace,
+                      void *hip_stream)
+{
+    if (!particles || !splitters || !workspace || n == 0 || n_domains < 1 || n_domains > 1024 ||
+        n >= (1ull << 31))
+        return RAFI_ERR_ARG;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const NBLayout L = nb_layout(n, n_domains);
+    // the keys, in two arrays inside the particle staging area (8 <= 40 bytes per particle)
+    uint32_t *ka = at<uint32_t>(workspace, L.off_tmp), *kb = ka + n;
+    int32_t *digit = at<int32_t>(workspace, L.off_digit);
+    hipLaunchKernelGGL(nb_key_kernel, dim3(blocks_for(n)), dim3(kNBThreads), 0, s,
+                       static_cast<const NBParticle *>(particles), n, ka);
+    RAFI_LAUNCH_CHECK();
+    const SplitPlan plan = split_plan(n, (int32_t)kDigitBuckets, 4);
+    uint32_t *src = ka, *dst = kb;
+    for (int pass = 0; pass < 3; ++pass) {
+        hipLaunchKernelGGL(nb_key_digit_kernel, dim3(blocks_for(n)), dim3(kNBThreads), 0, s, src, n, 10 * pass,
+                           digit);
+        RAFI_LAUNCH_CHECK();
+        const int rc = split_run(plan, src, digit, dst, at<uint64_t>(workspace, L.off_offsets),
+                                 at<uint64_t>(workspace, L.off_summary), nullptr, 0,
+                                 at<void>(workspace, L.off_split), s);
+        if (rc != RAFI_OK) return rc;
+        std::swap(src, dst);
+    }
+    hipLaunchKernelGGL(nb_pick_kernel, dim3(blocks_for((uint64_t)n_domains + 1)), dim3(kNBThreads), 0, s, src, n,
+                       n_domains, splitters);
+    RAFI_LAUNCH_CHECK();
+    return RAFI_OK;
+}
+
+int rafi_nb_seed(rafi_ctx *P, const rafi_nb_job *job, const void *particles, uint64_t n)
+{
+    if (!P || !job_ok(job) || P->S != RAFI_NB_PARTICLE_BYTES || P->D != job->n_domains || n > P->cap ||
+        (n && !particles) || n >= (1ull << 31))
+        return RAFI_ERR_ARG;
+    int rc = rafi_begin(P, n);
+    if (rc != RAFI_OK) return rc;
+    rafi_device_view v;
+    rafi_view(P, &v);
+    if (n)
+        hipLaunchKernelGGL(nb_seed_kernel, dim3(blocks_for(n)), dim3(kNBThreads), 0, P->stream, v, job->splitters,
+                           static_cast<const NBParticle *>(particles), n);
+    RAFI_LAUNCH_CHECK();
+    uint64_t total = 0;
+    return rafi_round(P, nullptr, &total);
+}
+
+int rafi_nb_step(rafi_ctx *P, rafi_ctx *V, rafi_ctx *Rq, const rafi_nb_job *job, uint64_t *round_counts,
+                 uint64_t *sizes)
+{
+    if (!P || !V || !Rq || !job_ok(job) || P->S != RAFI_NB_PARTICLE_BYTES || V->S != RAFI_NB_VIRTUAL_BYTES ||
+        Rq->S != RAFI_NB_REQUEST_BYTES || P->D != job->n_domains || V->D != job->n_domains ||
+        Rq->D != job->n_domains || P->stream != V->stream || P->stream != Rq->stream || P->n_in > job->capacity)
+        return RAFI_ERR_ARG;
+    const int32_t D = job->n_domains;
+    const uint64_t n1_slots = (uint64_t)D * (uint64_t)(D - 1);
+    if (V->cap < n1_slots || Rq->cap < n1_slots) return RAFI_ERR_ARG;
+    hipStream_t s = P->stream;
+    const NBLayout L = nb_layout(job->capacity, D);
+    void *ws = job->workspace;
+    const float dt = job->dt, hdt = 0.5f * job->dt, eps2 = job->eps * job->eps, theta = job->theta;
+    const float csize = ldexpf(1.0f, -job->cell_level);
+    const uint64_t n = P->n_in;
+    auto counts_at = [&](int k) { return round_counts ? round_counts + (size_t)k * D : nullptr; };
+
+    // 1. kick, drift, wrap; forward each particle to its owner
+    int rc = rafi_open(P, n, RAFI_SLOTS_ORDERED);
+    if (rc != RAFI_OK) return rc;
+    rafi_device_view pv;
+    rafi_view(P, &pv);
+    if (n)
+        hipLaunchKernelGGL(nb_drift_kernel, dim3(blocks_for(n)), dim3(kNBThreads), 0, s, pv, job->splitters, dt, hdt);
+    RAFI_LAUNCH_CHECK();
+    uint64_t total = 0;
+    rc = rafi_round(P, counts_at(0), &total);
+    if (rc != RAFI_OK) return rc;
+    if (total != n) return RAFI_ERR_BAD_DEST;  // every particle has an owner
+    rafi_view(P, &pv);
+    NBParticle *q = static_cast<NBParticle *>(const_cast<void *>(pv.in_items));
+
+    // 2. key order within each domain: three stable passes over 10-bit digits
+    NBParticle *tmp = at<NBParticle>(ws, L.off_tmp);
+    int32_t *digit = at<int32_t>(ws, L.off_digit);
+    if (n) {
+        const SplitPlan plan = split_plan(n, (int32_t)kDigitBuckets, RAFI_NB_PARTICLE_BYTES);
+        NBParticle *src = q, *dst = tmp;
+        for (int pass = 0; pass < 3; ++pass) {
+            hipLaunchKernelGGL(nb_digit_kernel, dim3(blocks_for(n)), dim3(kNBThreads), 0, s, src, n, 10 * pass,
+                               digit);
+            RAFI_LAUNCH_CHECK();
+            rc = split_run(plan, src, digit, dst, at<uint64_t>(ws, L.off_offsets), at<uint64_t>(ws, L.off_summary),
+                           nullptr, 0, at<void>(ws, L.off_split), s);
+            if (rc != RAFI_OK) return rc;
+            std::swap(src, dst);
+        }
+        RAFI_HIP_CHECK(hipMemcpyAsync(q, src, n * sizeof(NBParticle), hipMemcpyDeviceToDevice, s));
+    }
+
+    // 3. cells, roots, boxes
+    uint32_t *flags = at<uint32_t>(ws, L.off_flags), *cell_of = at<uint32_t>(ws, L.off_cell_of);
+    uint32_t *cell_start = at<uint32_t>(ws, L.off_cell_start), *counters = at<uint32_t>(ws, L.off_counters);
+    uint32_t *part = at<uint32_t>(ws, L.off_part);
+    NBNode *cells = at<NBNode>(ws, L.off_cells), *roots = at<NBNode>(ws, L.off_roots);
+    NBBox *boxes = at<NBBox>(ws, L.off_boxes);
+    uint32_t *dcell = at<uint32_t>(ws, L.off_dcell);
+    if (n) {
+        hipLaunchKernelGGL(nb_flag_kernel, dim3(blocks_for(n)), dim3(kNBThreads), 0, s, q, n, job->splitters, D,
+                           30 - 3 * job->cell_level, flags);
+        RAFI_LAUNCH_CHECK();
+        rc = scan_u32(flags, cell_of, n, part, counters, s);
+        if (rc != RAFI_OK) return rc;
+        hipLaunchKernelGGL(nb_cell_start_kernel, dim3(blocks_for(n)), dim3(kNBThreads), 0, s, flags, cell_of, n,
+                           cell_start);
+        hipLaunchKernelGGL(nb_cells_kernel, dim3(blocks_for(n)), dim3(kNBThreads), 0, s, q, n, counters, cell_start,
+                           cells);
+        RAFI_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(nb_domain_kernel, dim3((uint32_t)((D + 63) / 64)), dim3(64), 0, s, q, pv.in_offsets, D, n,
+                       cell_of, counters, roots, boxes, dcell);
+    RAFI_LAUNCH_CHECK();
+
+    // 4. virtual particles, round 1: the roots
+    rc = rafi_open(V, n1_slots, RAFI_SLOTS_ORDERED);
+    if (rc != RAFI_OK) return rc;
+    rafi_device_view vv;
+    rafi_view(V, &vv);
+    if (n1_slots)
+        hipLaunchKernelGGL(nb_roots_kernel, dim3(blocks_for(n1_slots)), dim3(kNBThreads), 0, s, vv, roots, boxes, D);
+    RAFI_LAUNCH_CHECK();
+    uint64_t n1 = 0;
+    rc = rafi_round(V, counts_at(1), &n1);
+    if (rc != RAFI_OK) return rc;
+    rafi_view(V, &vv);
+    if (job->log_vp1 && n1)
+        RAFI_HIP_CHECK(hipMemcpyAsync(job->log_vp1, vv.in_items, std::min<uint64_t>(n1, job->log_vp1_cap) *
+                                      RAFI_NB_VIRTUAL_BYTES, hipMemcpyDeviceToDevice, s));
+
+    // 5. accept, or request refinement from the root's owner
+    int32_t *acc = at<int32_t>(ws, L.off_acc);
+    rc = rafi_open(Rq, n1, RAFI_SLOTS_ORDERED);
+    if (rc != RAFI_OK) return rc;
+    rafi_device_view rv;
+    rafi_view(Rq, &rv);
+    if (n1)
+        hipLaunchKernelGGL(nb_accept_kernel, dim3(blocks_for(n1)), dim3(kNBThreads), 0, s, vv, rv, boxes, theta, acc);
+    RAFI_LAUNCH_CHECK();
+    uint64_t nr = 0;
+    rc = rafi_round(Rq, counts_at(2), &nr);
+    if (rc != RAFI_OK) return rc;
+    rafi_view(Rq, &rv);
+
+    // 6. answer sizes, their prefix, then round 2
+    uint32_t *cnt = at<uint32_t>(ws, L.off_cnt), *aoff = at<uint32_t>(ws, L.off_aoff);
+    uint32_t answers = 0;
+    if (nr) {
+        hipLaunchKernelGGL(nb_answer_size_kernel, dim3(blocks_for(nr)), dim3(kNBThreads), 0, s, rv, cells, dcell,
+                           boxes, theta, csize, cnt);
+        RAFI_LAUNCH_CHECK();
+        rc = scan_u32(cnt, aoff, nr, part, counters + 1, s);
+        if (rc != RAFI_OK) return rc;
+        RAFI_HIP_CHECK(hipMemcpyAsync(&answers, counters + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        RAFI_HIP_CHECK(hipStreamSynchronize(s));
+    }
+    const uint64_t n2_slots = n1 + answers;
+    if (n2_slots > V->cap) return RAFI_ERR_OVERFLOW;
+    rc = rafi_open(V, n2_slots, RAFI_SLOTS_ORDERED);
+    if (rc != RAFI_OK) return rc;
+    rafi_view(V, &vv);
+    if (n1) hipLaunchKernelGGL(nb_keep_kernel, dim3(blocks_for(n1)), dim3(kNBThreads), 0, s, vv, acc);
+    if (nr)
+        hipLaunchKernelGGL(nb_answer_kernel, dim3(blocks_for(nr)), dim3(kNBThreads), 0, s, vv, rv, q, cells, dcell,
+                           boxes, theta, csize, aoff, n1);
+    RAFI_LAUNCH_CHECK();
+    uint64_t n2 = 0;
+    rc = rafi_round(V, counts_at(3), &n2);
+    if (rc != RAFI_OK) return rc;
+    rafi_view(V, &vv);
+
+    // 7. forces and the second half-kick
+    if (n)
+        hipLaunchKernelGGL(nb_force_kernel, dim3(blocks_for(n)), dim3(kNBThreads), 0, s, q, pv.in_offsets, D, n, vv,
+                           eps2, hdt);
+    RAFI_LAUNCH_CHECK();
+    if (sizes) {
+        sizes[0] = n1;
+        sizes[1] = nr;
+        sizes[2] = n2;
+    }
+    return RAFI_OK;
+}
+
+}  // extern "C"

@@ -72,6 +72,12 @@ class SLJob(C.Structure):
                 ("refill_lanes", C.c_int32), ("field_stride", C.c_int32)]
 
 
+class NBJob(C.Structure):
+    _fields_ = [("n_domains", C.c_int32), ("cell_level", C.c_int32), ("dt", C.c_float), ("theta", C.c_float),
+                ("eps", C.c_float), ("splitters", C.c_void_p), ("workspace", C.c_void_p), ("capacity", C.c_uint64),
+                ("log_vp1", C.c_void_p), ("log_vp1_cap", C.c_uint64)]
+
+
 class DTJob(C.Structure):
     _fields_ = [("volume", C.c_void_p), ("views", C.c_void_p), ("contrib", C.c_void_p), ("image", C.c_void_p),
                 ("n", C.c_int32), ("grid", C.c_int32 * 3), ("n_views", C.c_int32), ("width", C.c_int32),
@@ -137,6 +143,10 @@ _SIGS = {
     "rafi_dt_raygen": ([_P, _P], C.c_int),
     "rafi_dt_trace": ([_P, _P], C.c_int),
     "rafi_dt_render": ([_P, _P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
+    "rafi_nb_workspace": ([C.c_uint64, C.c_int32, C.POINTER(C.c_uint64)], C.c_int),
+    "rafi_nb_splitters": ([_P, C.c_uint64, C.c_int32, _P, _P, _P], C.c_int),
+    "rafi_nb_seed": ([_P, _P, _P, C.c_uint64], C.c_int),
+    "rafi_nb_step": ([_P, _P, _P, _P, _P, _P], C.c_int),
 }
 
 _lib = None
@@ -568,3 +578,80 @@ def dt_render(volume: torch.Tensor, grid, views: np.ndarray, kappa=0.05, smax=No
                  seed)
     rounds = dt_render_job(ctx, job, max_rounds)
     return dict(image=image, contrib=contrib, rounds=rounds, ctx=ctx, job=job, views_dev=vdev)
+
+
+# ------------------------------------------- multi-context N-body exchange ---
+NB_PARTICLE_BYTES, NB_VIRTUAL_BYTES, NB_REQUEST_BYTES = 40, 24, 4
+# record layouts, for reading queues back
+NB_PARTICLE_DTYPE = W.NB_PARTICLE_DTYPE
+NB_VIRTUAL_DTYPE = np.dtype([("pos", "<f4", 3), ("mass", "<f4"), ("smax", "<f4"), ("src", "<i4")])
+
+
+def nb_workspace_bytes(n: int, n_domains: int) -> int:
+    b = C.c_uint64(0)
+    _check(lib().rafi_nb_workspace(n, n_domains, C.byref(b)), "rafi_nb_workspace")
+    return b.value
+
+
+def nb_to_device(particles: np.ndarray, device) -> torch.Tensor:
+    """Particle records -> float32 device tensor [n, 10] (40-byte rows)."""
+    a = np.ascontiguousarray(particles, dtype=W.NB_PARTICLE_DTYPE)
+    return torch.from_numpy(a.view(np.float32).reshape(-1, 10).copy()).to(device)
+
+
+def nb_from_bytes(items: torch.Tensor, dtype) -> np.ndarray:
+    """A queue copied out as bytes -> numpy records."""
+    return items.cpu().numpy().reshape(-1).view(dtype)
+
+
+class NBody:
+    """The three contexts, workspace and splitters of the essential-tree
+    exchange (rafi_nb_step), for one particle set. Only allocation and
+    argument marshalling happen here; every step runs in the library."""
+
+    def __init__(self, particles: torch.Tensor, n_domains: int, cell_level: int = 4, theta: float = 0.5,
+                 eps: float = 1e-3, dt: float = 1e-3, virtual_capacity: int | None = None, debug: bool = False,
+                 log_vp1: bool = False):
+        assert particles.dtype == torch.float32 and particles.dim() == 2 and particles.shape[1] == 10
+        dev = particles.device
+        n, D = particles.shape[0], n_domains
+        self.n, self.D = n, D
+        self.workspace = torch.empty(max(nb_workspace_bytes(n, D), 1), dtype=torch.uint8, device=dev)
+        self.splitters = torch.empty(D + 1, dtype=torch.int32, device=dev)
+        _check(lib().rafi_nb_splitters(_dptr(particles), n, D, _dptr(self.splitters), _dptr(self.workspace),
+                                       _stream()), "rafi_nb_splitters")
+        vcap = virtual_capacity if virtual_capacity is not None else D * max(D - 1, 1) + n * max(D - 1, 1)
+        self.P = Context(D, NB_PARTICLE_BYTES, max(n, 1), debug=debug)
+        self.V = Context(D, NB_VIRTUAL_BYTES, max(vcap, 1), debug=debug)
+        self.R = Context(D, NB_REQUEST_BYTES, max(D * max(D - 1, 1), 1), debug=debug)
+        self.vp1 = (torch.empty((D * max(D - 1, 1), NB_VIRTUAL_BYTES), dtype=torch.uint8, device=dev)
+                    if log_vp1 else None)
+        self.job = NBJob(D, cell_level, dt, theta, eps, self.splitters.data_ptr(), self.workspace.data_ptr(), n,
+                         self.vp1.data_ptr() if log_vp1 else None, self.vp1.shape[0] if log_vp1 else 0)
+        _check(lib().rafi_nb_seed(self.P.handle, C.byref(self.job), _dptr(particles), n), "rafi_nb_seed")
+
+    def step(self, dt: float | None = None):
+        """One step; returns (round counts [4, D], queue sizes [3])."""
+        if dt is not None:
+            self.job.dt = dt
+        rc = np.zeros((4, self.D), dtype=np.uint64)
+        sz = np.zeros(3, dtype=np.uint64)
+        _check(lib().rafi_nb_step(self.P.handle, self.V.handle, self.R.handle, C.byref(self.job),
+                                  rc.ctypes.data_as(C.c_void_p), sz.ctypes.data_as(C.c_void_p)), "rafi_nb_step")
+        return rc, sz
+
+    def particles(self) -> np.ndarray:
+        q, _ = self.P.copy_queue()
+        return nb_from_bytes(q, W.NB_PARTICLE_DTYPE)
+
+    def remote_lists(self) -> np.ndarray:
+        q, _ = self.V.copy_queue()
+        return nb_from_bytes(q, NB_VIRTUAL_DTYPE)
+
+    def requests(self) -> np.ndarray:
+        q, _ = self.R.copy_queue()
+        return q.cpu().numpy().reshape(-1).view(np.int32)
+
+    def close(self):
+        for c in (self.P, self.V, self.R):
+            c.close()

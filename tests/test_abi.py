@@ -58,6 +58,12 @@ def test_argument_validation_without_device():
     assert L.rafi_dt_raygen(None, None) == rafi.ERR_ARG
     assert L.rafi_dt_trace(None, None) == rafi.ERR_ARG
     assert L.rafi_dt_render(None, None, 10, None) == rafi.ERR_ARG
+    assert L.rafi_nb_workspace(1000, 0, C.byref(b)) == rafi.ERR_ARG
+    assert L.rafi_nb_workspace(1000, 2048, C.byref(b)) == rafi.ERR_ARG
+    assert L.rafi_nb_workspace(1000, 64, C.byref(b)) == rafi.RAFI_OK and b.value > 1000 * 40
+    assert L.rafi_nb_splitters(None, 10, 4, None, None, None) == rafi.ERR_ARG
+    assert L.rafi_nb_seed(None, None, None, 0) == rafi.ERR_ARG
+    assert L.rafi_nb_step(None, None, None, None, None, None) == rafi.ERR_ARG
     assert L.rafi_split_set_variant(16) == rafi.ERR_ARG
     assert L.rafi_split_set_variant(-1) == rafi.ERR_ARG
 
@@ -77,7 +83,7 @@ def test_struct_layouts_match_header(tmp_path):
     C compiler gives the header's struct (compiled here with gcc)."""
     import subprocess
     structs = {"rafi_device_view": rafi.DeviceView, "rafi_ea_job": rafi.EAJob, "rafi_sl_job": rafi.SLJob,
-               "rafi_dt_job": rafi.DTJob, "rafi_ortho_view": rafi.ViewRec, "rafi_ea_scene": rafi.SceneRec,
+               "rafi_dt_job": rafi.DTJob, "rafi_nb_job": rafi.NBJob, "rafi_ortho_view": rafi.ViewRec, "rafi_ea_scene": rafi.SceneRec,
                "rafi_batch_tuning": rafi.BatchTuning, "rafi_stats": rafi.Stats, "rafi_profile": rafi.Profile}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "rafi.h"', "int main(void) {"]
     for cname, cls in structs.items():
