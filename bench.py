@@ -358,6 +358,47 @@ def delta_tracking(dev, reps):
     return out
 
 
+def nbody_exchange(dev, reps):
+    """Multi-context, multi-phase forwarding: the N-body essential-tree
+    exchange, 2^16 clustered particles in 64 Morton domains, cells of level
+    4, theta 0.5, softening 1e-3, dt 1e-3. A step = migration round, key
+    sort, hierarchy, two virtual-particle rounds and a request round, forces."""
+    import time
+
+    import numpy as np
+    import torch
+
+    from paper_2605_30294_amd import rafi
+    from paper_2605_30294_amd import workloads as W
+
+    n, D = 1 << 16, 64
+    nb = rafi.NBody(rafi.nb_to_device(W.nbody_particles(n), dev), D, cell_level=4, theta=0.5, eps=1e-3, dt=1e-3)
+    nb.step(0.0)                      # accelerations at t = 0
+    nb.step()
+    torch.cuda.synchronize()
+    items = interactions = 0
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        rc, sz = nb.step()
+        items += int(rc.sum())
+        npd = rc[0].astype(np.int64)
+        interactions += int((npd * (npd - 1)).sum() + (npd * rc[3].astype(np.int64)).sum())
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    nb.close()
+    out = {"workload": "N-body essential-tree exchange: 2^16 clustered particles, 64 Morton domains, "
+                       "level-4 cells, theta 0.5, three contexts (40/24/4-byte items)",
+           "ms_per_step": round(ms, 4), "forwarded_items_per_step": items // reps,
+           "forwarded_items_per_s": items / reps / (ms * 1e-3),
+           "round_items": {"particles": int(rc[0].sum()), "virtual_1": int(rc[1].sum()),
+                           "requests": int(rc[2].sum()), "virtual_2": int(rc[3].sum())},
+           "interactions_per_step": interactions // reps,
+           "interactions_per_s": interactions / reps / (ms * 1e-3)}
+    log(f"nbody: {ms:.3f} ms/step, {out['forwarded_items_per_step']} forwarded items, "
+        f"{out['interactions_per_step']} interactions ({out['interactions_per_s']:.3g}/s)")
+    return out
+
+
 def ea_adjoint(dev, reps):
     """128^3 / 64 bricks / 64 views x 256^2: forward render, then the
     reverse-replay backward of the L2 image loss against a second volume."""
@@ -495,7 +536,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seeds", type=int, default=262144)
     ap.add_argument("--only", default=None,
-                    choices=["streamlines", "split", "split-domains", "ea", "adjoint", "batched", "dt", "copy"],
+                    choices=["streamlines", "split", "split-domains", "ea", "adjoint", "batched", "dt", "nbody",
+                             "copy"],
                     help="run one leg alone (for profilers) and print its result")
     ap.add_argument("--tail-items", type=int, default=0,
                     help="launches with at most this many particles integrate uncapped")
@@ -541,6 +583,8 @@ def main():
             res = batched(dev, reps=args.steps)
         elif args.only == "dt":
             res = delta_tracking(dev, reps=args.steps)
+        elif args.only == "nbody":
+            res = nbody_exchange(dev, reps=args.steps)
         else:
             res = plain_copy(dev, reps=args.steps)
         print(json.dumps({"only": args.only, "result": res}, default=str), flush=True)
@@ -554,6 +598,7 @@ def main():
         extras["adjoint_vs_forward"] = ea_adjoint(dev, reps=3)
         extras["batched_vs_plain"] = batched(dev, reps=2)
         extras["delta_tracking"] = delta_tracking(dev, reps=3)
+        extras["nbody_exchange"] = nbody_exchange(dev, reps=3)
     cpu = None if args.no_cpu else cpu_baseline(seeds_np, args.cpu_seeds)
 
     value = sl["forwarded"] / (sl["ms"] * 1e-3)

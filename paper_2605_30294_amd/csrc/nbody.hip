@@ -516,7 +516,207 @@ __global__ void __launch_bounds__(kNBThreads) nb_force_kernel(NBParticle *__rest
     }
 }
 
+// The same sums with domain-pure workgroups (one tile of the particle
+// context's tile table each, kNBThreads particles) and the sources staged
+// through LDS a tile at a time; every thread still adds its terms in source
+// order, the self term being skipped by a select.
+__global__ void __launch_bounds__(kNBThreads) nb_force_tiled_kernel(NBParticle *__restrict__ q, rafi_device_view P,
+                                                                   rafi_device_view V, float eps2, float hdt)
+{
+    __shared__ float4 src[kNBThreads];
+    uint64_t begin, end;
+    const int32_t r = rafi_tile(P, blockIdx.x, &begin, &end);
+    const uint64_t i = begin + threadIdx.x;
+    const bool mine = i < end;
+    const uint64_t ii = mine ? i : begin;
+    const float p[3] = {q[ii].pos[0], q[ii].pos[1], q[ii].pos[2]};
+    float a[3] = {0.0f, 0.0f, 0.0f};
+    auto sweep = [&](uint64_t j0, uint64_t j1, auto load, bool own) {
+        for (uint64_t t = j0; t < j1; t += kNBThreads) {
+            const uint64_t j = t + threadIdx.x;
+            __syncthreads();
+            if (j < j1) src[threadIdx.x] = load(j);
+            __syncthreads();
+            const int cnt = (int)min<uint64_t>(kNBThreads, j1 - t);
+            const int self = own ? (int)((int64_t)i - (int64_t)t) : -1;
+#pragma unroll 4
+            for (int k = 0; k < cnt; ++k) {
+                const float4 sv = src[k];
+                const float o[3] = {sv.x, sv.y, sv.z};
+                float b[3] = {a[0], a[1], a[2]};
+                gravity(p, o, sv.w, eps2, b);
+                if (k != self) {
+                    a[0] = b[0];
+                    a[1] = b[1];
+                    a[2] = b[2];
+                }
+            }
+        }
+    };
+    sweep(P.in_offsets[r], P.in_offsets[r + 1],
+          [&](uint64_t j) { return make_float4(q[j].pos[0], q[j].pos[1], q[j].pos[2], q[j].mass); }, true);
+    const NBVirtual *rem = static_cast<const NBVirtual *>(V.in_items);
+    sweep(V.in_offsets[r], V.in_offsets[r + 1],
+          [&](uint64_t j) { return make_float4(rem[j].pos[0], rem[j].pos[1], rem[j].pos[2], rem[j].mass); }, false);
+    if (mine) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            q[i].acc[c] = a[c];
+            q[i].vel[c] = __fmaf_rn(hdt, a[c], q[i].vel[c]);
+        }
+    }
+}
+
+// ------------------------------------------- one wave per item forms ---
+// Wave w handles request w; each lane takes one of the owner's cells, and a
+// wave scan of the cells' answer sizes gives every cell its slots, in cell
+// order (the same slots as one thread walking the cells).
+__device__ inline int32_t wave_id() { return (int32_t)((blockIdx.x * kNBThreads + threadIdx.x) >> 6); }
+
+__global__ void __launch_bounds__(kNBThreads) nb_answer_size_wave_kernel(rafi_device_view Rq,
+                                                                        const NBNode *__restrict__ cells,
+                                                                        const uint32_t *__restrict__ dcell,
+                                                                        const NBBox *__restrict__ boxes, float theta,
+                                                                        float csize, uint32_t *__restrict__ cnt)
+{
+    const uint64_t j = (uint64_t)wave_id();
+    if (j >= Rq.n_in) return;  // whole waves
+    const int lane = threadIdx.x & 63;
+    const int32_t s = ea::find_domain(Rq.in_offsets, Rq.n_domains, j);
+    const NBBox b = boxes[static_cast<const NBRequest *>(Rq.in_items)[j].sender];
+    uint32_t c = 0;
+    for (uint32_t k0 = dcell[2 * s]; k0 < dcell[2 * s + 1]; k0 += 64) {
+        const uint32_t k = k0 + lane;
+        if (k < dcell[2 * s + 1]) c += accepts(cells[k].com, csize, b, theta) ? 1u : cells[k].count;
+    }
+    const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)dev::wave_incl_scan(c), 63);
+    if (lane == 0) cnt[j] = tot;
+}
+
+__global__ void __launch_bounds__(kNBThreads) nb_answer_wave_kernel(rafi_device_view V, rafi_device_view Rq,
+                                                                   const NBParticle *__restrict__ q,
+                                                                   const NBNode *__restrict__ cells,
+                                                                   const uint32_t *__restrict__ dcell,
+                                                                   const NBBox *__restrict__ boxes, float theta,
+                                                                   float csize, const uint32_t *__restrict__ aoff,
+                                                                   uint64_t n1)
+{
+    const uint64_t j = (uint64_t)wave_id();
+    if (j >= Rq.n_in) return;  // whole waves
+    const int lane = threadIdx.x & 63;
+    const int32_t s = ea::find_domain(Rq.in_offsets, Rq.n_domains, j);
+    const int32_t r = static_cast<const NBRequest *>(Rq.in_items)[j].sender;
+    const NBBox b = boxes[r];
+    uint64_t base = n1 + aoff[j];
+    const uint32_t kend = dcell[2 * s + 1];
+    for (uint32_t k0 = dcell[2 * s]; k0 < kend; k0 += 64) {
+        const uint32_t k = k0 + lane;
+        const bool valid = k < kend;
+        NBNode c{};
+        if (valid) c = cells[k];
+        const bool a = valid && accepts(c.com, csize, b, theta);
+        const uint32_t sz = valid ? (a ? 1u : c.count) : 0u;
+        const uint32_t incl = dev::wave_incl_scan(sz);
+        uint64_t slot = base + (incl - sz);
+        base += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+        if (!valid) continue;
+        if (a) {
+            NBVirtual v;
+            v.pos[0] = c.com[0];
+            v.pos[1] = c.com[1];
+            v.pos[2] = c.com[2];
+            v.mass = c.mass;
+            v.smax = csize;
+            v.src = s;
+            rafi_forward_t(V, slot, v, r);
+        } else {
+            for (uint32_t i = c.first; i < c.first + c.count; ++i) {
+                NBVirtual v;
+                v.pos[0] = q[i].pos[0];
+                v.pos[1] = q[i].pos[1];
+                v.pos[2] = q[i].pos[2];
+                v.mass = q[i].mass;
+                v.smax = 0.0f;
+                v.src = s;
+                rafi_forward_t(V, slot++, v, r);
+            }
+        }
+    }
+}
+
+// Wave d handles domain d: coalesced loads of 64 particles at a time; the
+// box is a wave min/max (exact in any order); the moments are added in key
+// order, every lane taking the same values from the lane holding them.
+__global__ void __launch_bounds__(kNBThreads) nb_domain_wave_kernel(const NBParticle *__restrict__ q,
+                                                                   const uint64_t *__restrict__ off, int32_t D,
+                                                                   uint64_t n, const uint32_t *__restrict__ cell_of,
+                                                                   const uint32_t *__restrict__ n_cells,
+                                                                   NBNode *__restrict__ roots,
+                                                                   NBBox *__restrict__ boxes,
+                                                                   uint32_t *__restrict__ dcell)
+{
+    const int32_t d = wave_id();
+    if (d >= D) return;  // whole waves
+    const int lane = threadIdx.x & 63;
+    const uint32_t first = (uint32_t)off[d], count = (uint32_t)(off[d + 1] - off[d]);
+    float m = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (uint32_t c0 = 0; c0 < count; c0 += 64) {
+        const bool valid = c0 + lane < count;
+        NBParticle p{};
+        if (valid) p = q[first + c0 + lane];
+        if (valid)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = fminf(lo[a], p.pos[a]);
+                hi[a] = fmaxf(hi[a], p.pos[a]);
+            }
+        const uint32_t nk = min(64u, count - c0);
+        for (uint32_t t = 0; t < nk; ++t) {
+            const float w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.mass), t));
+            const float x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.pos[0]), t));
+            const float y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.pos[1]), t));
+            const float z = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.pos[2]), t));
+            m = m + w;
+            mx = __fmaf_rn(w, x, mx);
+            my = __fmaf_rn(w, y, my);
+            mz = __fmaf_rn(w, z, mz);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        for (int o = 32; o > 0; o >>= 1) {
+            lo[a] = fminf(lo[a], __shfl_xor(lo[a], o, 64));
+            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o, 64));
+        }
+    if (lane != 0) return;
+    NBNode r{};
+    NBBox b{};
+    if (count) {
+        r.com[0] = mx / m;
+        r.com[1] = my / m;
+        r.com[2] = mz / m;
+        r.mass = m;
+        r.first = first;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            b.lo[a] = lo[a];
+            b.hi[a] = hi[a];
+        }
+        b.size = fmaxf(fmaxf(b.hi[0] - b.lo[0], b.hi[1] - b.lo[1]), b.hi[2] - b.lo[2]);
+        dcell[2 * d] = cell_of[first];
+        dcell[2 * d + 1] = (uint64_t)first + count < n ? cell_of[first + count] : *n_cells;
+    } else {
+        dcell[2 * d] = dcell[2 * d + 1] = 0;
+    }
+    r.count = count;
+    roots[d] = r;
+    boxes[d] = b;
+}
+
 uint32_t blocks_for(uint64_t n) { return (uint32_t)std::max<uint64_t>(1, (n + kNBThreads - 1) / kNBThreads); }
+// blocks that give every one of n items a wave of its own
+uint32_t waves_blocks(uint64_t n) { return (uint32_t)std::max<uint64_t>(1, (n + kNBThreads / 64 - 1) / (kNBThreads / 64)); }
 
 bool job_ok(const rafi_nb_job *j)
 {
@@ -657,7 +857,7 @@ int rafi_nb_step(rafi_ctx *P, rafi_ctx *V, rafi_ctx *Rq, const rafi_nb_job *job,
                            cells);
         RAFI_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(nb_domain_kernel, dim3((uint32_t)((D + 63) / 64)), dim3(64), 0, s, q, pv.in_offsets, D, n,
+    hipLaunchKernelGGL(nb_domain_wave_kernel, dim3(waves_blocks(D)), dim3(kNBThreads), 0, s, q, pv.in_offsets, D, n,
                        cell_of, counters, roots, boxes, dcell);
     RAFI_LAUNCH_CHECK();
 
@@ -695,8 +895,8 @@ int rafi_nb_step(rafi_ctx *P, rafi_ctx *V, rafi_ctx *Rq, const rafi_nb_job *job,
     uint32_t *cnt = at<uint32_t>(ws, L.off_cnt), *aoff = at<uint32_t>(ws, L.off_aoff);
     uint32_t answers = 0;
     if (nr) {
-        hipLaunchKernelGGL(nb_answer_size_kernel, dim3(blocks_for(nr)), dim3(kNBThreads), 0, s, rv, cells, dcell,
-                           boxes, theta, csize, cnt);
+        hipLaunchKernelGGL(nb_answer_size_wave_kernel, dim3(waves_blocks(nr)), dim3(kNBThreads), 0, s, rv, cells,
+                           dcell, boxes, theta, csize, cnt);
         RAFI_LAUNCH_CHECK();
         rc = scan_u32(cnt, aoff, nr, part, counters + 1, s);
         if (rc != RAFI_OK) return rc;
@@ -710,16 +910,19 @@ int rafi_nb_step(rafi_ctx *P, rafi_ctx *V, rafi_ctx *Rq, const rafi_nb_job *job,
     rafi_view(V, &vv);
     if (n1) hipLaunchKernelGGL(nb_keep_kernel, dim3(blocks_for(n1)), dim3(kNBThreads), 0, s, vv, acc);
     if (nr)
-        hipLaunchKernelGGL(nb_answer_kernel, dim3(blocks_for(nr)), dim3(kNBThreads), 0, s, vv, rv, q, cells, dcell,
-                           boxes, theta, csize, aoff, n1);
+        hipLaunchKernelGGL(nb_answer_wave_kernel, dim3(waves_blocks(nr)), dim3(kNBThreads), 0, s, vv, rv, q, cells,
+                           dcell, boxes, theta, csize, aoff, n1);
     RAFI_LAUNCH_CHECK();
     uint64_t n2 = 0;
     rc = rafi_round(V, counts_at(3), &n2);
     if (rc != RAFI_OK) return rc;
     rafi_view(V, &vv);
 
-    // 7. forces and the second half-kick
-    if (n)
+    // 7. forces and the second half-kick: a workgroup per tile of the
+    // particle context when its tiles are workgroup-sized
+    if (n && pv.tile_items == (uint32_t)kNBThreads && pv.n_tiles)
+        hipLaunchKernelGGL(nb_force_tiled_kernel, dim3(pv.n_tiles), dim3(kNBThreads), 0, s, q, pv, vv, eps2, hdt);
+    else if (n)
         hipLaunchKernelGGL(nb_force_kernel, dim3(blocks_for(n)), dim3(kNBThreads), 0, s, q, pv.in_offsets, D, n, vv,
                            eps2, hdt);
     RAFI_LAUNCH_CHECK();
