@@ -1068,8 +1068,11 @@ int oracle_dt_render(const float *vol, const orc_dt_params *P, const orc_view *v
  *     RefinementReq; the owner answers with its cells that the requester
  *     accepts, and with the particles (size 0) of those it does not. The
  *     received nodes, in queue order, are the requester's remote list.
- *   - Force on a particle: its domain's other particles in key order, then
- *     the remote list in order, each as a softened point mass.
+ *   - Force on a particle: the softened point-mass terms of its domain's
+ *     other particles in key order, then of its remote list in order. This
+ *     source sequence is cut into chunks of NB_CHUNK sources (the particle
+ *     itself keeps its position in the sequence); each chunk's terms are
+ *     added in order from zero, and the chunk sums are added in chunk order.
  *   - Slots: the forward step keeps slot order within a destination (O1),
  *     and fan-out uses fixed slots: root s -> r at s (D-1) + k; a request at
  *     the slot of the root it answers; answers after the n1 slots of the
@@ -1080,6 +1083,8 @@ typedef struct {
     int32_t n_domains, cell_level;
     float dt, theta, eps;
 } orc_nb_params;
+
+#define NB_CHUNK 4096   /* sources per chunk of a particle's force sum */
 
 typedef struct {
     float pos[3], vel[3], acc[3], mass;
@@ -1376,18 +1381,30 @@ int oracle_nb_step(const orc_nb_params *P, const uint32_t *K, orc_nb_particle *q
     if (vp2_log) for (int64_t i = 0; i < (int64_t)o2[D] && (uint64_t)i < cap_vp2; ++i) vp2_log[i] = v2[i];
     if (lens) { lens[0] = (uint64_t)n1; lens[1] = (uint64_t)nr; lens[2] = o2[D]; }
 
-    /* 7. forces (own domain, then the remote list) and the second half-kick */
-    for (int32_t r = 0; r < D; ++r)
+    /* 7. forces (own domain, then the remote list, in chunks) and the second half-kick */
+    for (int32_t r = 0; r < D; ++r) {
+        const int64_t nloc = (int64_t)(offs[r + 1] - offs[r]), len = nloc + (int64_t)(o2[r + 1] - o2[r]);
         for (int64_t i = (int64_t)offs[r]; i < (int64_t)offs[r + 1]; ++i) {
             float a[3] = {0.0f, 0.0f, 0.0f};
-            for (int64_t j = (int64_t)offs[r]; j < (int64_t)offs[r + 1]; ++j)
-                if (j != i) nb_term(queue[i].pos, queue[j].pos, queue[j].mass, eps2, a);
-            for (int64_t k = (int64_t)o2[r]; k < (int64_t)o2[r + 1]; ++k) nb_term(queue[i].pos, v2[k].pos, v2[k].mass, eps2, a);
+            for (int64_t c0 = 0; c0 < len; c0 += NB_CHUNK) {
+                float A[3] = {0.0f, 0.0f, 0.0f};
+                for (int64_t k = c0; k < c0 + NB_CHUNK && k < len; ++k) {
+                    if (k < nloc) {
+                        const int64_t j = (int64_t)offs[r] + k;
+                        if (j != i) nb_term(queue[i].pos, queue[j].pos, queue[j].mass, eps2, A);
+                    } else {
+                        const int64_t v = (int64_t)o2[r] + (k - nloc);
+                        nb_term(queue[i].pos, v2[v].pos, v2[v].mass, eps2, A);
+                    }
+                }
+                for (int c = 0; c < 3; ++c) a[c] = a[c] + A[c];
+            }
             for (int c = 0; c < 3; ++c) {
                 queue[i].acc[c] = a[c];
                 queue[i].vel[c] = fmaf(hdt, a[c], queue[i].vel[c]);
             }
         }
+    }
     free(tmp); free(dest); free(counts); free(offs); free(keys); free(idx); free(cells); free(cell_first); free(root);
     free(lo); free(hi); free(rsize); free(vo); free(v1); free(vdest); free(o1); free(acc); free(ro); free(rq);
     free(rdest); free(orr); free(aoff); free(wo); free(v2); free(wdest); free(o2);

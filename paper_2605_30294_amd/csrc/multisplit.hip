@@ -724,6 +724,7 @@ int split_run(const SplitPlan &p, const void *items, const int32_t *dest, void *
     case 4: launch_scatter<4>(p, it, dest, table, o, dummy, s); break;
     case 6: launch_scatter<6>(p, it, dest, table, o, dummy, s); break;
     case 8: launch_scatter<8>(p, it, dest, table, o, dummy, s); break;
+    case 10: launch_scatter<10>(p, it, dest, table, o, dummy, s); break;
     case 11: launch_scatter<11>(p, it, dest, table, o, dummy, s); break;
     case 12: launch_scatter<12>(p, it, dest, table, o, dummy, s); break;
     case 16: launch_scatter<16>(p, it, dest, table, o, dummy, s); break;

@@ -23,6 +23,8 @@
 //      on every run;
 //   7. forces (the domain's own particles, then its remote list) and the
 //      second half-kick.
+#include <vector>
+
 #include "internal.h"
 #include "ea_device.h"
 #include "rafi_device.h"
@@ -103,39 +105,6 @@ __device__ inline bool accepts(const float c[3], float size, const NBBox &b, flo
     for (int a = 0; a < 3; ++a) d[a] = fmaxf(fmaxf(b.lo[a] - c[a], c[a] - b.hi[a]), 0.0f);
     const float d2 = __fmaf_rn(d[2], d[2], __fmaf_rn(d[1], d[1], d[0] * d[0]));
     return size * size < (theta * theta) * d2;
-}
-
-// a += m (q - p) / (|q - p|^2 + eps^2)^(3/2), in this operation order
-__device__ inline void gravity(const float p[3], const float q[3], float m, float eps2, float a[3])
-{
-    const float dx = q[0] - p[0], dy = q[1] - p[1], dz = q[2] - p[2];
-    const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmaf_rn(dx, dx, eps2)));
-    const float inv = 1.0f / sqrtf(r2);
-    const float s = m * (inv * inv * inv);
-    a[0] = __fmaf_rn(s, dx, a[0]);
-    a[1] = __fmaf_rn(s, dy, a[1]);
-    a[2] = __fmaf_rn(s, dz, a[2]);
-}
-
-// Mass and centre of mass of particles [first, first + count), summed in order.
-__device__ inline NBNode moments(const NBParticle *__restrict__ q, uint32_t first, uint32_t count)
-{
-    float m = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
-    for (uint32_t i = first; i < first + count; ++i) {
-        const NBParticle p = q[i];
-        m = m + p.mass;
-        mx = __fmaf_rn(p.mass, p.pos[0], mx);
-        my = __fmaf_rn(p.mass, p.pos[1], my);
-        mz = __fmaf_rn(p.mass, p.pos[2], mz);
-    }
-    NBNode nd;
-    nd.com[0] = mx / m;
-    nd.com[1] = my / m;
-    nd.com[2] = mz / m;
-    nd.mass = m;
-    nd.first = first;
-    nd.count = count;
-    return nd;
 }
 
 // ----------------------------------------------------------- workspace ---
@@ -324,56 +293,6 @@ __global__ void __launch_bounds__(kNBThreads) nb_cell_start_kernel(const uint32_
     if (i < n && flags[i]) cell_start[cell_of[i]] = (uint32_t)i;
 }
 
-__global__ void __launch_bounds__(kNBThreads) nb_cells_kernel(const NBParticle *__restrict__ q, uint64_t n,
-                                                             const uint32_t *__restrict__ n_cells,
-                                                             const uint32_t *__restrict__ cell_start,
-                                                             NBNode *__restrict__ cells)
-{
-    const uint32_t c = blockIdx.x * kNBThreads + threadIdx.x;
-    const uint32_t nc = *n_cells;
-    if (c >= nc) return;
-    const uint32_t first = cell_start[c];
-    const uint32_t end = c + 1 < nc ? cell_start[c + 1] : (uint32_t)n;
-    cells[c] = moments(q, first, end - first);
-}
-
-// One thread per domain: root moments, bounding box, root size, cell range.
-// cell_of is the exclusive prefix of the cell-start flags: at a cell's
-// first particle it is that cell's index, so a domain's cells run from
-// cell_of[its first particle] to cell_of[the next domain's first particle]
-// (the cell count n_cells after the last particle).
-__global__ void __launch_bounds__(64) nb_domain_kernel(const NBParticle *__restrict__ q,
-                                                      const uint64_t *__restrict__ off, int32_t D, uint64_t n,
-                                                      const uint32_t *__restrict__ cell_of,
-                                                      const uint32_t *__restrict__ n_cells, NBNode *__restrict__ roots,
-                                                      NBBox *__restrict__ boxes, uint32_t *__restrict__ dcell)
-{
-    const int32_t d = blockIdx.x * 64 + threadIdx.x;
-    if (d >= D) return;
-    const uint32_t first = (uint32_t)off[d], count = (uint32_t)(off[d + 1] - off[d]);
-    NBNode r{};
-    NBBox b{};
-    if (count) {
-        r = moments(q, first, count);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) b.lo[a] = b.hi[a] = q[first].pos[a];
-        for (uint32_t i = first; i < first + count; ++i)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                b.lo[a] = fminf(b.lo[a], q[i].pos[a]);
-                b.hi[a] = fmaxf(b.hi[a], q[i].pos[a]);
-            }
-        b.size = fmaxf(fmaxf(b.hi[0] - b.lo[0], b.hi[1] - b.lo[1]), b.hi[2] - b.lo[2]);
-        dcell[2 * d] = cell_of[first];
-        dcell[2 * d + 1] = (uint64_t)first + count < n ? cell_of[first + count] : *n_cells;
-    } else {
-        dcell[2 * d] = dcell[2 * d + 1] = 0;
-    }
-    r.count = count;
-    roots[d] = r;
-    boxes[d] = b;
-}
-
 // Virtual-particle round 1: slot s (D - 1) + k carries root s to domain
 // r = k (+1 from s on), if both domains hold particles.
 __global__ void __launch_bounds__(kNBThreads) nb_roots_kernel(rafi_device_view V, const NBNode *__restrict__ roots,
@@ -416,23 +335,6 @@ __global__ void __launch_bounds__(kNBThreads) nb_accept_kernel(rafi_device_view 
     }
 }
 
-// Size of the answer to request j: one node per accepted cell, else its particles.
-__global__ void __launch_bounds__(kNBThreads) nb_answer_size_kernel(rafi_device_view Rq, const NBNode *__restrict__ cells,
-                                                                   const uint32_t *__restrict__ dcell,
-                                                                   const NBBox *__restrict__ boxes, float theta,
-                                                                   float csize, uint32_t *__restrict__ cnt)
-{
-    const uint64_t j = (uint64_t)blockIdx.x * kNBThreads + threadIdx.x;
-    if (j >= Rq.n_in) return;
-    const int32_t s = ea::find_domain(Rq.in_offsets, Rq.n_domains, j);
-    const int32_t r = static_cast<const NBRequest *>(Rq.in_items)[j].sender;
-    const NBBox b = boxes[r];
-    uint32_t c = 0;
-    for (uint32_t k = dcell[2 * s]; k < dcell[2 * s + 1]; ++k)
-        c += accepts(cells[k].com, csize, b, theta) ? 1u : cells[k].count;
-    cnt[j] = c;
-}
-
 // Virtual-particle round 2, first n1 slots: the accepted roots stay with their receiver.
 __global__ void __launch_bounds__(kNBThreads) nb_keep_kernel(rafi_device_view V, const int32_t *__restrict__ acc)
 {
@@ -443,127 +345,6 @@ __global__ void __launch_bounds__(kNBThreads) nb_keep_kernel(rafi_device_view V,
         rafi_forward_t(V, i, static_cast<const NBVirtual *>(V.in_items)[i], r);
     } else {
         rafi_done(V, i);
-    }
-}
-
-// Virtual-particle round 2, the answers: request j fills slots n1 + aoff[j] + ...
-__global__ void __launch_bounds__(kNBThreads) nb_answer_kernel(rafi_device_view V, rafi_device_view Rq,
-                                                              const NBParticle *__restrict__ q,
-                                                              const NBNode *__restrict__ cells,
-                                                              const uint32_t *__restrict__ dcell,
-                                                              const NBBox *__restrict__ boxes, float theta,
-                                                              float csize, const uint32_t *__restrict__ aoff,
-                                                              uint64_t n1)
-{
-    const uint64_t j = (uint64_t)blockIdx.x * kNBThreads + threadIdx.x;
-    if (j >= Rq.n_in) return;
-    const int32_t s = ea::find_domain(Rq.in_offsets, Rq.n_domains, j);
-    const int32_t r = static_cast<const NBRequest *>(Rq.in_items)[j].sender;
-    const NBBox b = boxes[r];
-    uint64_t slot = n1 + aoff[j];
-    for (uint32_t k = dcell[2 * s]; k < dcell[2 * s + 1]; ++k) {
-        const NBNode c = cells[k];
-        if (accepts(c.com, csize, b, theta)) {
-            NBVirtual v;
-            v.pos[0] = c.com[0];
-            v.pos[1] = c.com[1];
-            v.pos[2] = c.com[2];
-            v.mass = c.mass;
-            v.smax = csize;
-            v.src = s;
-            rafi_forward_t(V, slot++, v, r);
-        } else {
-            for (uint32_t i = c.first; i < c.first + c.count; ++i) {
-                NBVirtual v;
-                v.pos[0] = q[i].pos[0];
-                v.pos[1] = q[i].pos[1];
-                v.pos[2] = q[i].pos[2];
-                v.mass = q[i].mass;
-                v.smax = 0.0f;
-                v.src = s;
-                rafi_forward_t(V, slot++, v, r);
-            }
-        }
-    }
-}
-
-// Forces: the domain's other particles in key order, then its remote list;
-// then the second half-kick. Writes only velocity and acceleration, so the
-// positions other threads read do not change.
-__global__ void __launch_bounds__(kNBThreads) nb_force_kernel(NBParticle *__restrict__ q, const uint64_t *__restrict__ off,
-                                                             int32_t D, uint64_t n, rafi_device_view V, float eps2,
-                                                             float hdt)
-{
-    const uint64_t i = (uint64_t)blockIdx.x * kNBThreads + threadIdx.x;
-    if (i >= n) return;
-    const int32_t r = ea::find_domain(off, D, i);
-    float p[3] = {q[i].pos[0], q[i].pos[1], q[i].pos[2]};
-    float a[3] = {0.0f, 0.0f, 0.0f};
-    for (uint64_t j = off[r]; j < off[r + 1]; ++j) {
-        if (j == i) continue;
-        const float o[3] = {q[j].pos[0], q[j].pos[1], q[j].pos[2]};
-        gravity(p, o, q[j].mass, eps2, a);
-    }
-    const NBVirtual *rem = static_cast<const NBVirtual *>(V.in_items);
-    for (uint64_t k = V.in_offsets[r]; k < V.in_offsets[r + 1]; ++k) {
-        const NBVirtual v = rem[k];
-        gravity(p, v.pos, v.mass, eps2, a);
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        q[i].acc[c] = a[c];
-        q[i].vel[c] = __fmaf_rn(hdt, a[c], q[i].vel[c]);
-    }
-}
-
-// The same sums with domain-pure workgroups (one tile of the particle
-// context's tile table each, kNBThreads particles) and the sources staged
-// through LDS a tile at a time; every thread still adds its terms in source
-// order, the self term being skipped by a select.
-__global__ void __launch_bounds__(kNBThreads) nb_force_tiled_kernel(NBParticle *__restrict__ q, rafi_device_view P,
-                                                                   rafi_device_view V, float eps2, float hdt)
-{
-    __shared__ float4 src[kNBThreads];
-    uint64_t begin, end;
-    const int32_t r = rafi_tile(P, blockIdx.x, &begin, &end);
-    const uint64_t i = begin + threadIdx.x;
-    const bool mine = i < end;
-    const uint64_t ii = mine ? i : begin;
-    const float p[3] = {q[ii].pos[0], q[ii].pos[1], q[ii].pos[2]};
-    float a[3] = {0.0f, 0.0f, 0.0f};
-    auto sweep = [&](uint64_t j0, uint64_t j1, auto load, bool own) {
-        for (uint64_t t = j0; t < j1; t += kNBThreads) {
-            const uint64_t j = t + threadIdx.x;
-            __syncthreads();
-            if (j < j1) src[threadIdx.x] = load(j);
-            __syncthreads();
-            const int cnt = (int)min<uint64_t>(kNBThreads, j1 - t);
-            const int self = own ? (int)((int64_t)i - (int64_t)t) : -1;
-#pragma unroll 4
-            for (int k = 0; k < cnt; ++k) {
-                const float4 sv = src[k];
-                const float o[3] = {sv.x, sv.y, sv.z};
-                float b[3] = {a[0], a[1], a[2]};
-                gravity(p, o, sv.w, eps2, b);
-                if (k != self) {
-                    a[0] = b[0];
-                    a[1] = b[1];
-                    a[2] = b[2];
-                }
-            }
-        }
-    };
-    sweep(P.in_offsets[r], P.in_offsets[r + 1],
-          [&](uint64_t j) { return make_float4(q[j].pos[0], q[j].pos[1], q[j].pos[2], q[j].mass); }, true);
-    const NBVirtual *rem = static_cast<const NBVirtual *>(V.in_items);
-    sweep(V.in_offsets[r], V.in_offsets[r + 1],
-          [&](uint64_t j) { return make_float4(rem[j].pos[0], rem[j].pos[1], rem[j].pos[2], rem[j].mass); }, false);
-    if (mine) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            q[i].acc[c] = a[c];
-            q[i].vel[c] = __fmaf_rn(hdt, a[c], q[i].vel[c]);
-        }
     }
 }
 
@@ -714,6 +495,133 @@ __global__ void __launch_bounds__(kNBThreads) nb_domain_wave_kernel(const NBPart
     boxes[d] = b;
 }
 
+// Chunked force sums. A particle's sources (its domain's particles in key
+// order, then its remote list) are cut into chunks of kForceChunk; workgroup
+// (tile, chunk) adds one chunk's terms in order from zero for the tile's
+// particles (the self term masked, as above) and stores the chunk sum;
+// nb_fold_kernel then adds a particle's chunk sums in chunk order.
+constexpr uint32_t kForceChunk = 4096;
+
+__global__ void __launch_bounds__(kNBThreads) nb_force_chunk_kernel(const NBParticle *__restrict__ q,
+                                                                   rafi_device_view P, rafi_device_view V,
+                                                                   float eps2, uint64_t n,
+                                                                   float *__restrict__ part)
+{
+    __shared__ float4 src[kNBThreads];
+    uint64_t begin, end;
+    const int32_t r = rafi_tile(P, blockIdx.x, &begin, &end);
+    const uint64_t l0 = P.in_offsets[r], nloc = P.in_offsets[r + 1] - l0;
+    const uint64_t v0 = V.in_offsets[r], len = nloc + (V.in_offsets[r + 1] - v0);
+    const uint64_t c0 = (uint64_t)blockIdx.y * kForceChunk;
+    if (c0 >= len) return;  // whole workgroup
+    const uint64_t c1 = min<uint64_t>(c0 + kForceChunk, len);
+    const uint64_t i = begin + threadIdx.x;
+    const bool mine = i < end;
+    const uint64_t ii = mine ? i : begin;
+    const float p[3] = {q[ii].pos[0], q[ii].pos[1], q[ii].pos[2]};
+    const NBVirtual *rem = static_cast<const NBVirtual *>(V.in_items);
+    const int64_t self_k = (int64_t)(i - l0);  // position of the particle itself in the sequence
+    float A[3] = {0.0f, 0.0f, 0.0f};
+    for (uint64_t t = c0; t < c1; t += kNBThreads) {
+        const uint64_t k = t + threadIdx.x;
+        __syncthreads();
+        if (k < c1) {
+            if (k < nloc) {
+                const NBParticle &o = q[l0 + k];
+                src[threadIdx.x] = make_float4(o.pos[0], o.pos[1], o.pos[2], o.mass);
+            } else {
+                const NBVirtual &o = rem[v0 + (k - nloc)];
+                src[threadIdx.x] = make_float4(o.pos[0], o.pos[1], o.pos[2], o.mass);
+            }
+        }
+        __syncthreads();
+        const int cnt = (int)min<uint64_t>(kNBThreads, c1 - t);
+        const int self = (int)(self_k - (int64_t)t);
+#pragma unroll 4
+        for (int k2 = 0; k2 < cnt; ++k2) {
+            const float4 sv = src[k2];
+            const float dx = sv.x - p[0], dy = sv.y - p[1], dz = sv.z - p[2];
+            const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmaf_rn(dx, dx, eps2)));
+            const float inv = 1.0f / sqrtf(r2);
+            const float f = sv.w * (inv * inv * inv);
+            const float sc = __int_as_float(__float_as_int(f) & -(int32_t)(k2 != self));
+            A[0] = __fmaf_rn(sc, dx, A[0]);
+            A[1] = __fmaf_rn(sc, dy, A[1]);
+            A[2] = __fmaf_rn(sc, dz, A[2]);
+        }
+    }
+    if (mine) {
+        float *o = part + ((uint64_t)blockIdx.y * n + i) * 3;
+        o[0] = A[0];
+        o[1] = A[1];
+        o[2] = A[2];
+    }
+}
+
+__global__ void __launch_bounds__(kNBThreads) nb_fold_kernel(NBParticle *__restrict__ q, const uint64_t *__restrict__ off,
+                                                            int32_t D, uint64_t n, rafi_device_view V,
+                                                            const float *__restrict__ part, float hdt)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kNBThreads + threadIdx.x;
+    if (i >= n) return;
+    const int32_t r = ea::find_domain(off, D, i);
+    const uint64_t len = (off[r + 1] - off[r]) + (V.in_offsets[r + 1] - V.in_offsets[r]);
+    float a[3] = {0.0f, 0.0f, 0.0f};
+    for (uint64_t c = 0; c * kForceChunk < len; ++c) {
+        const float *o = part + (c * n + i) * 3;
+        a[0] = a[0] + o[0];
+        a[1] = a[1] + o[1];
+        a[2] = a[2] + o[2];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        q[i].acc[k] = a[k];
+        q[i].vel[k] = __fmaf_rn(hdt, a[k], q[i].vel[k]);
+    }
+}
+
+// Wave c handles cell c: the cell's particles are loaded 64 at a time and
+// their mass and first moments added in key order from zero (lane
+// broadcasts), then the centre of mass is the first moment over the mass.
+__global__ void __launch_bounds__(kNBThreads) nb_cells_wave_kernel(const NBParticle *__restrict__ q, uint64_t n,
+                                                                  const uint32_t *__restrict__ n_cells,
+                                                                  const uint32_t *__restrict__ cell_start,
+                                                                  NBNode *__restrict__ cells)
+{
+    const uint32_t c = (uint32_t)wave_id();
+    const uint32_t nc = *n_cells;
+    if (c >= nc) return;  // whole waves
+    const int lane = threadIdx.x & 63;
+    const uint32_t first = cell_start[c];
+    const uint32_t count = (c + 1 < nc ? cell_start[c + 1] : (uint32_t)n) - first;
+    float m = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
+    for (uint32_t c0 = 0; c0 < count; c0 += 64) {
+        NBParticle p{};
+        if (c0 + lane < count) p = q[first + c0 + lane];
+        const uint32_t nk = min(64u, count - c0);
+        for (uint32_t t = 0; t < nk; ++t) {
+            const float w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.mass), t));
+            const float x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.pos[0]), t));
+            const float y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.pos[1]), t));
+            const float z = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.pos[2]), t));
+            m = m + w;
+            mx = __fmaf_rn(w, x, mx);
+            my = __fmaf_rn(w, y, my);
+            mz = __fmaf_rn(w, z, mz);
+        }
+    }
+    if (lane == 0) {
+        NBNode nd;
+        nd.com[0] = mx / m;
+        nd.com[1] = my / m;
+        nd.com[2] = mz / m;
+        nd.mass = m;
+        nd.first = first;
+        nd.count = count;
+        cells[c] = nd;
+    }
+}
+
 uint32_t blocks_for(uint64_t n) { return (uint32_t)std::max<uint64_t>(1, (n + kNBThreads - 1) / kNBThreads); }
 // blocks that give every one of n items a wave of its own
 uint32_t waves_blocks(uint64_t n) { return (uint32_t)std::max<uint64_t>(1, (n + kNBThreads / 64 - 1) / (kNBThreads / 64)); }
@@ -803,7 +711,10 @@ int rafi_nb_step(rafi_ctx *P, rafi_ctx *V, rafi_ctx *Rq, const rafi_nb_job *job,
     const float dt = job->dt, hdt = 0.5f * job->dt, eps2 = job->eps * job->eps, theta = job->theta;
     const float csize = ldexpf(1.0f, -job->cell_level);
     const uint64_t n = P->n_in;
-    auto counts_at = [&](int k) { return round_counts ? round_counts + (size_t)k * D : nullptr; };
+    std::vector<uint64_t> own_counts(round_counts ? 0 : (size_t)4 * D);
+    uint64_t *counts4 = round_counts ? round_counts : own_counts.data();
+    auto counts_at = [&](int k) { return counts4 + (size_t)k * D; };
+    const uint64_t *pcount = counts_at(0), *vcount = counts_at(3);
 
     // 1. kick, drift, wrap; forward each particle to its owner
     int rc = rafi_open(P, n, RAFI_SLOTS_ORDERED);
@@ -853,8 +764,8 @@ int rafi_nb_step(rafi_ctx *P, rafi_ctx *V, rafi_ctx *Rq, const rafi_nb_job *job,
         if (rc != RAFI_OK) return rc;
         hipLaunchKernelGGL(nb_cell_start_kernel, dim3(blocks_for(n)), dim3(kNBThreads), 0, s, flags, cell_of, n,
                            cell_start);
-        hipLaunchKernelGGL(nb_cells_kernel, dim3(blocks_for(n)), dim3(kNBThreads), 0, s, q, n, counters, cell_start,
-                           cells);
+        hipLaunchKernelGGL(nb_cells_wave_kernel, dim3(waves_blocks(n)), dim3(kNBThreads), 0, s, q, n, counters,
+                           cell_start, cells);
         RAFI_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(nb_domain_wave_kernel, dim3(waves_blocks(D)), dim3(kNBThreads), 0, s, q, pv.in_offsets, D, n,
@@ -918,14 +829,24 @@ int rafi_nb_step(rafi_ctx *P, rafi_ctx *V, rafi_ctx *Rq, const rafi_nb_job *job,
     if (rc != RAFI_OK) return rc;
     rafi_view(V, &vv);
 
-    // 7. forces and the second half-kick: a workgroup per tile of the
-    // particle context when its tiles are workgroup-sized
-    if (n && pv.tile_items == (uint32_t)kNBThreads && pv.n_tiles)
-        hipLaunchKernelGGL(nb_force_tiled_kernel, dim3(pv.n_tiles), dim3(kNBThreads), 0, s, q, pv, vv, eps2, hdt);
-    else if (n)
-        hipLaunchKernelGGL(nb_force_kernel, dim3(blocks_for(n)), dim3(kNBThreads), 0, s, q, pv.in_offsets, D, n, vv,
-                           eps2, hdt);
-    RAFI_LAUNCH_CHECK();
+    // 7. forces in chunks (a workgroup per particle tile and chunk), then
+    // the ordered sum of the chunk sums and the second half-kick
+    if (n) {
+        if (pv.tile_items != (uint32_t)kNBThreads || !pv.n_tiles) return RAFI_ERR_STATE;
+        uint64_t chunks = 0;
+        for (int32_t d = 0; d < D; ++d)
+            chunks = std::max<uint64_t>(chunks, (pcount[d] + vcount[d] + kForceChunk - 1) / kForceChunk);
+        float *part = nullptr;
+        RAFI_HIP_CHECK(hipMallocAsync(reinterpret_cast<void **>(&part), std::max<uint64_t>(chunks, 1) * n * 3 *
+                                      sizeof(float), s));
+        if (chunks)
+            hipLaunchKernelGGL(nb_force_chunk_kernel, dim3(pv.n_tiles, (uint32_t)chunks), dim3(kNBThreads), 0, s, q,
+                               pv, vv, eps2, n, part);
+        hipLaunchKernelGGL(nb_fold_kernel, dim3(blocks_for(n)), dim3(kNBThreads), 0, s, q, pv.in_offsets, D, n, vv,
+                           part, hdt);
+        RAFI_LAUNCH_CHECK();
+        RAFI_HIP_CHECK(hipFreeAsync(part, s));
+    }
     if (sizes) {
         sizes[0] = n1;
         sizes[1] = nr;

@@ -125,10 +125,12 @@ def _direct(pos, mass, eps):
     return (m[None, :, None] * d / r2[..., None] ** 1.5).sum(1)
 
 
-def test_theta_zero_is_the_direct_sum():
+@pytest.mark.parametrize("n,D", [(1500, 6), (9000, 2)])
+def test_theta_zero_is_the_direct_sum(n, D):
     """theta = 0 accepts nothing: every particle reaches every other domain as
-    a leaf, so each force is the direct softened sum (float64 reference)."""
-    n, D, eps = 1500, 6, 1e-2
+    a leaf, so each force is the direct softened sum (float64 reference);
+    9000 particles give every sum several 4096-source chunks."""
+    eps = 1e-2
     p = _unique_masses(W.nbody_particles(n, seed=21))
     K = O.nb_splitters(p, D)
     q, _ = O.nb_seed(p, K)
