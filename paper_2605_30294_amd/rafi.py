@@ -655,3 +655,9 @@ class NBody:
     def close(self):
         for c in (self.P, self.V, self.R):
             c.close()
+
+
+# Short names of the Python layer: the differentiable emission-absorption
+# render (a torch.autograd.Function underneath) and the streamline trace.
+render = ea_render_differentiable
+trace_streamlines = sl_trace

@@ -103,3 +103,13 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(cname, "size")] == C.sizeof(cls), cname
         for fname, _ in cls._fields_:
             assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_python_layer_names():
+    """The Python layer's entry points: a context with round(), the
+    differentiable render, the streamline trace and the stateless split."""
+    assert callable(rafi.Context.round)
+    assert rafi.render is rafi.ea_render_differentiable
+    assert rafi.trace_streamlines is rafi.sl_trace
+    assert callable(rafi.multisplit)
+    assert issubclass(rafi.EARender, __import__("torch").autograd.Function)
