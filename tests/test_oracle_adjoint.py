@@ -51,3 +51,32 @@ def test_uniform_medium_gradient_sum(orc):
     dI = -math.expm1(-K * s) + r0 * K * C32 * math.exp(-K * s)
     assert g.sum() == __import__("pytest").approx(36 * dI, rel=1e-12)
     assert L == __import__("pytest").approx(36 * 0.25, rel=1e-12)
+
+
+def test_gradcheck_float64_small_volume(orc):
+    """torch.autograd.gradcheck of the oracle's render and its adjoint as a
+    float64 autograd function: 8^3 volume, 2x2x2 domains, two views. The
+    adjoint gives vector-Jacobian products through the loss gradient: with
+    target I* = I - g/2, dL/dI = 2 (I - I*) = g."""
+    import torch
+
+    n, grid = 8, (2, 2, 2)
+    views = W.random_views(2, n, 6, 6, seed=41)
+
+    class OracleRender(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, vol):
+            img = orc.ea_render(vol.detach().numpy(), grid, views, c=C32)["image"]
+            ctx.save_for_backward(vol)
+            ctx.img = img
+            return torch.from_numpy(img)
+
+        @staticmethod
+        def backward(ctx, g):
+            (vol,) = ctx.saved_tensors
+            target = ctx.img - 0.5 * g.detach().numpy()
+            _, grad, _ = orc.ea_loss_grad(vol.detach().numpy(), grid, views, target, c=C32)
+            return torch.from_numpy(grad)
+
+    vol = torch.from_numpy(W.blob_volume(n, 40).astype(np.float64)).requires_grad_(True)
+    assert torch.autograd.gradcheck(OracleRender.apply, (vol,), eps=1e-6, atol=1e-8, rtol=1e-6)
