@@ -1084,7 +1084,7 @@ typedef struct {
     float dt, theta, eps;
 } orc_nb_params;
 
-#define NB_CHUNK 4096   /* sources per chunk of a particle's force sum */
+#define NB_CHUNK 1024   /* sources per chunk of a particle's force sum */
 
 typedef struct {
     float pos[3], vel[3], acc[3], mass;

@@ -500,7 +500,7 @@ __global__ void __launch_bounds__(kNBThreads) nb_domain_wave_kernel(const NBPart
 // (tile, chunk) adds one chunk's terms in order from zero for the tile's
 // particles (the self term masked, as above) and stores the chunk sum;
 // nb_fold_kernel then adds a particle's chunk sums in chunk order.
-constexpr uint32_t kForceChunk = 4096;
+constexpr uint32_t kForceChunk = 1024;
 
 __global__ void __launch_bounds__(kNBThreads) nb_force_chunk_kernel(const NBParticle *__restrict__ q,
                                                                    rafi_device_view P, rafi_device_view V,

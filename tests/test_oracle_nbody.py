@@ -129,7 +129,7 @@ def _direct(pos, mass, eps):
 def test_theta_zero_is_the_direct_sum(n, D):
     """theta = 0 accepts nothing: every particle reaches every other domain as
     a leaf, so each force is the direct softened sum (float64 reference);
-    9000 particles give every sum several 4096-source chunks."""
+    1500 and 9000 particles give every sum several 1024-source chunks."""
     eps = 1e-2
     p = _unique_masses(W.nbody_particles(n, seed=21))
     K = O.nb_splitters(p, D)
