@@ -554,11 +554,11 @@ int rafi_nb_seed(rafi_ctx *particles, const rafi_nb_job *job, const void *in, ui
  *      root, each with its mass and centre of mass (float32 sums in key
  *      order); the particles' bounding box (root size = its largest edge,
  *      cell size = 2^-cell_level);
- *   4. virtual round 1: root s to every other non-empty domain r at slot
+ *   4. first virtual round: root s to every other non-empty domain r at slot
  *      s (D - 1) + (r < s ? r : r - 1);
  *   5. request round: receiver r keeps a root it accepts, else sends
  *      RefinementReq{r} to its owner from the root's slot;
- *   6. virtual round 2: kept roots at their slots, then each request's
+ *   6. second virtual round: kept roots at their slots, then each request's
  *      answer (the owner's cells r accepts, the particles of the others,
  *      in key order) after the n1 round-1 slots, at the exclusive prefix of
  *      the answer sizes in request-queue order;
@@ -571,7 +571,8 @@ int rafi_nb_seed(rafi_ctx *particles, const rafi_nb_job *job, const void *in, ui
  * [4][D], optional): per-domain counts of the particle, virtual 1, request
  * and virtual 2 rounds; sizes (host [3], optional): the lengths of the
  * virtual 1, request and virtual 2 queues. RAFI_ERR_OVERFLOW if the
- * answers do not fit the virtual context (nothing of round 2 is emitted);
+ * answers do not fit the virtual context (nothing of the second virtual
+ * round is emitted);
  * RAFI_ERR_ARG for mismatched contexts, streams or sizes. */
 int rafi_nb_step(rafi_ctx *particles, rafi_ctx *virtuals, rafi_ctx *requests, const rafi_nb_job *job,
                  uint64_t *round_counts, uint64_t *sizes);

@@ -11,12 +11,12 @@
 //   3. the domain hierarchy: Morton cells of level L (runs of one key prefix
 //      within a domain) and the domain root, with mass and centre of mass;
 //      the domain's bounding box;
-//   4. virtual-particle context, round 1: every root to every other
+//   4. virtual-particle context, first round: every root to every other
 //      non-empty domain;
 //   5. request context: a receiver keeps a root it accepts (Barnes-Hut
 //      acceptance against its own box) and sends a refinement request to
 //      the owner of one it does not;
-//   6. virtual-particle context, round 2: the accepted roots, and each
+//   6. virtual-particle context, second round: the accepted roots, and each
 //      owner's answer to each request: its cells that the requester
 //      accepts, and the particles of those it does not. Answers take fixed
 //      slots after a prefix sum of their sizes, so the queues are the same
@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(kNBThreads) nb_cell_start_kernel(const uint32_
     if (i < n && flags[i]) cell_start[cell_of[i]] = (uint32_t)i;
 }
 
-// Virtual-particle round 1: slot s (D - 1) + k carries root s to domain
+// First virtual-particle round: slot s (D - 1) + k carries root s to domain
 // r = k (+1 from s on), if both domains hold particles.
 __global__ void __launch_bounds__(kNBThreads) nb_roots_kernel(rafi_device_view V, const NBNode *__restrict__ roots,
                                                              const NBBox *__restrict__ boxes, int32_t D)
@@ -335,7 +335,7 @@ __global__ void __launch_bounds__(kNBThreads) nb_accept_kernel(rafi_device_view 
     }
 }
 
-// Virtual-particle round 2, first n1 slots: the accepted roots stay with their receiver.
+// Second virtual-particle round, first n1 slots: the accepted roots stay with their receiver.
 __global__ void __launch_bounds__(kNBThreads) nb_keep_kernel(rafi_device_view V, const int32_t *__restrict__ acc)
 {
     const uint64_t i = (uint64_t)blockIdx.x * kNBThreads + threadIdx.x;
@@ -772,7 +772,7 @@ int rafi_nb_step(rafi_ctx *P, rafi_ctx *V, rafi_ctx *Rq, const rafi_nb_job *job,
                        cell_of, counters, roots, boxes, dcell);
     RAFI_LAUNCH_CHECK();
 
-    // 4. virtual particles, round 1: the roots
+    // 4. virtual particles, first round: the roots
     rc = rafi_open(V, n1_slots, RAFI_SLOTS_ORDERED);
     if (rc != RAFI_OK) return rc;
     rafi_device_view vv;
@@ -802,7 +802,7 @@ int rafi_nb_step(rafi_ctx *P, rafi_ctx *V, rafi_ctx *Rq, const rafi_nb_job *job,
     if (rc != RAFI_OK) return rc;
     rafi_view(Rq, &rv);
 
-    // 6. answer sizes, their prefix, then round 2
+    // 6. answer sizes, their prefix, then the second virtual round
     uint32_t *cnt = at<uint32_t>(ws, L.off_cnt), *aoff = at<uint32_t>(ws, L.off_aoff);
     uint32_t answers = 0;
     if (nr) {
