@@ -557,7 +557,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: every domain of the forwarding path is resident on a "
-              "single MI355X and there is no multi-GPU exchange in this build; run with --gpus 1.",
+              "single MI355X and the exchange is a device-local split (no multi-GPU exchange); run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 
