@@ -844,8 +844,9 @@ int rafi_nb_step(rafi_ctx *P, rafi_ctx *V, rafi_ctx *Rq, const rafi_nb_job *job,
                                pv, vv, eps2, n, part);
         hipLaunchKernelGGL(nb_fold_kernel, dim3(blocks_for(n)), dim3(kNBThreads), 0, s, q, pv.in_offsets, D, n, vv,
                            part, hdt);
-        RAFI_LAUNCH_CHECK();
-        RAFI_HIP_CHECK(hipFreeAsync(part, s));
+        const hipError_t launched = hipGetLastError();
+        const hipError_t freed = hipFreeAsync(part, s);  // freed whatever the launches reported
+        if (launched != hipSuccess || freed != hipSuccess) return RAFI_ERR_HIP;
     }
     if (sizes) {
         sizes[0] = n1;
