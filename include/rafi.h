@@ -408,6 +408,14 @@ typedef struct rafi_sl_job {
                                 rafi_sl_pack (16-byte loads), 3 = the unpadded field (12-byte
                                 loads, 3/4 of the bytes). Same results either way; other
                                 values: RAFI_ERR_ARG. */
+    uint32_t quad_items;     /* launches whose input queue holds at most this many particles
+                                (with refill_lanes 0) run four lanes per particle, one per
+                                coordinate, exchanging cell index, weights and tests within
+                                the lane quad (about a third of the dependent instructions
+                                per step), and gather each particle's cell two steps ahead
+                                while it integrates: for launches too small to fill the GPU,
+                                which are bound by each particle's step latency. 0: never.
+                                Same results either way. */
 } rafi_sl_job;
 
 /* Item: position (3 x float32) and particle id; the step count lives in

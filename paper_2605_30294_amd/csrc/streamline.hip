@@ -236,6 +236,233 @@ advance_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids)
     }
 }
 
+// ------------------------------------------------ four lanes per particle ---
+// Launches over few particles are bound by the latency of each particle's
+// chain of RK4 steps, not by throughput. There a quad of lanes carries one
+// particle: lane a (a < 3) holds coordinate a of the position, computes that
+// axis's cell index and weight, gathers component a of the 8 corners and
+// interpolates it; lane 3 repeats lane 2. The cell index, the weights and
+// the step tests are exchanged within the quad by DPP moves. Every
+// component's arithmetic is the one-lane kernel's, in the same order, so the
+// results are bit-identical; each lane runs about a third of the chain.
+constexpr int kQuadThreads = 256;
+
+// DPP quad permutations (lane j of a quad reads lane p[j]): 0xb1 = [1,0,3,2],
+// 0x4e = [2,3,0,1], 0x55 * k = [k,k,k,k]. All four lanes of a quad must be
+// active (the quad kernel branches only on quad-uniform values).
+template <int CTRL>
+__device__ inline int32_t quad_read(int32_t v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, true);
+}
+
+__device__ inline int32_t quad_sum(int32_t v)
+{
+    v += quad_read<0xb1>(v);
+    return v + quad_read<0x4e>(v);
+}
+
+__device__ inline int32_t quad_all(bool b)
+{
+    int32_t v = b ? 1 : 0;
+    v &= quad_read<0xb1>(v);
+    return v & quad_read<0x4e>(v);
+}
+
+template <int K>
+__device__ inline float quad_lane(float v)
+{
+    return __int_as_float(quad_read<0x55 * K>(__float_as_int(v)));
+}
+
+// s_waitcnt immediate for vmcnt(0) alone (expcnt and lgkmcnt at their
+// maxima, i.e. not waited on).
+constexpr int kWaitLoads = 0x0f70;
+
+// This lane's component of the 8 corners of one cell.
+struct QuadCell {
+    int32_t base = -1;  // linear index of corner (i0, j0, k0), the same on the 4 lanes; -1: empty
+    float c[8];
+};
+
+// Lane geometry of the quad kernel: f points at component a of voxel 0, o[]
+// holds the 8 corner offsets in floats, stride is the voxel stride of axis a
+// (0 on lane 3, whose axis repeats lane 2's).
+struct QuadAxis {
+    const float *f;
+    int32_t o[8];
+    float hi;     // n - 1
+    int32_t top;  // n - 2
+    int32_t stride;
+};
+
+// Cell (quad-uniform linear index) and this lane's weight of coordinate q,
+// as the one-lane sampler computes them.
+__device__ inline int32_t quad_cell(const QuadAxis &ax, float q, float &w)
+{
+    const float uc = fminf(fmaxf(q - 0.5f, 0.0f), ax.hi);
+    const int32_t i = min((int32_t)floorf(uc), ax.top);
+    w = uc - (float)i;
+    return quad_sum(i * ax.stride);
+}
+
+template <int FW>
+__device__ inline void quad_gather(const QuadAxis &ax, int32_t base, QuadCell &dst)
+{
+    const float *b = ax.f + (size_t)base * FW;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) dst.c[k] = b[ax.o[k]];
+    dst.base = base;
+}
+
+// The one-lane sampler restricted to this lane's component. On a cell
+// change the corners come from a look-ahead slot if one holds that cell
+// (pnow: gathered for this step, arrived; pnext: gathered for the next step),
+// else from the field.
+template <int FW>
+__device__ inline float field_quad(const QuadAxis &ax, QuadCell &cc, const QuadCell &pnow, const QuadCell &pnext,
+                                   float q)
+{
+    float w;
+    const int32_t base = quad_cell(ax, q, w);
+    const float w0 = quad_lane<0>(w), w1 = quad_lane<1>(w), w2 = quad_lane<2>(w);
+    if (base != cc.base) {
+        if (base == pnow.base)
+            cc = pnow;
+        else if (base == pnext.base)
+            cc = pnext;
+        else {
+            quad_gather<FW>(ax, base, cc);
+            // wait here, on this path only: the other paths then carry no
+            // pending load into the interpolation below
+            __builtin_amdgcn_s_waitcnt(kWaitLoads);
+        }
+    }
+    const float *c = cc.c;
+    return lerpf(lerpf(lerpf(c[0], c[1], w0), lerpf(c[2], c[3], w0), w1),
+                 lerpf(lerpf(c[4], c[5], w0), lerpf(c[6], c[7], w0), w1), w2);
+}
+
+// Particle state of the quad kernel (lane a holds coordinate a).
+struct QuadWalk {
+    float x;    // position
+    float sum;  // k1 + 2 k2 + 2 k3 + k4 of the last step
+    int32_t steps, taken, why, dest;
+    bool done;  // stopped or forwarded (the same on the 4 lanes)
+};
+
+// One RK4 step and its tests, unless the particle is done.
+template <int FW>
+__device__ inline void quad_step(const QuadAxis &ax, QuadCell &cc, const QuadCell &pnow, const QuadCell &pnext,
+                                 QuadWalk &s, float h, float hh, float h6, float lo, float hi, float fn, int32_t bsz,
+                                 int32_t dmul, int32_t d, int32_t max_steps, int32_t cap)
+{
+    if (s.done) return;
+    const float x = s.x;
+    const float k1 = field_quad<FW>(ax, cc, pnow, pnext, x);
+    const float k2 = field_quad<FW>(ax, cc, pnow, pnext, __fmaf_rn(hh, k1, x));
+    const float k3 = field_quad<FW>(ax, cc, pnow, pnext, __fmaf_rn(hh, k2, x));
+    const float k4 = field_quad<FW>(ax, cc, pnow, pnext, __fmaf_rn(h, k3, x));
+    const float sum = __fmaf_rn(2.0f, k3, __fmaf_rn(2.0f, k2, k1)) + k4;
+    const float nx = __fmaf_rn(h6, sum, x);
+    ++s.steps;
+    ++s.taken;
+    s.sum = sum;
+    s.x = nx;
+    if (quad_all(__float_as_uint(nx) == __float_as_uint(x))) {
+        s.why = RAFI_SL_STAGNANT;
+        s.done = true;
+        return;
+    }
+    int32_t e = d;
+    if (!quad_all(nx >= lo && nx < hi)) {
+        const bool ok = nx >= 0.0f && nx < fn;
+        const int32_t all_ok = quad_all(ok);
+        const int32_t idx = quad_sum(ok ? ((int32_t)floorf(nx) / bsz) * dmul : 0);
+        e = all_ok ? idx : -1;
+    }
+    // (selects, not branches: both fields stay in registers)
+    const int32_t why = e < 0 ? RAFI_SL_EXITED : s.steps >= max_steps ? RAFI_SL_MAXSTEPS : 0;
+    const bool forward = why == 0 && (e != d || s.taken >= cap);
+    s.why = why;
+    s.dest = forward ? e : s.dest;
+    s.done = why != 0 || forward;
+}
+
+// Settle the slot gathered a step ago (normally arrived), then gather into
+// `slot` the cell two steps ahead along the last step's mean velocity. Runs
+// on every path of the loop (also for done particles, whose gathers are
+// clamped into the field and never read), so that the compiler's count of
+// pending loads is the same on every path.
+template <int FW>
+__device__ inline void quad_look_ahead(const QuadAxis &ax, const QuadWalk &s, float h6, QuadCell &slot)
+{
+    __builtin_amdgcn_s_waitcnt(kWaitLoads);
+    float w;
+    quad_gather<FW>(ax, quad_cell(ax, __fmaf_rn(2.0f * h6, s.sum, s.x), w), slot);
+}
+
+template <int FW>
+__global__ void __launch_bounds__(kQuadThreads)
+advance_quad_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids)
+{
+    constexpr uint32_t kPer = kQuadThreads / 4;  // particles per workgroup
+    const uint64_t n_in = rafi_queue_length(view);
+    const uint32_t nb = (uint32_t)((n_in + kPer - 1) / kPer);
+    if (blockIdx.x >= nb) return;
+    const uint64_t i = rafi_xcd_block(blockIdx.x, nb) * (uint64_t)kPer + (threadIdx.x >> 2);
+    if (i >= n_in) return;  // the same on the 4 lanes of a quad
+    const int32_t lane = threadIdx.x & 3, a = min(lane, 2);
+    const Geo g = make_geo(job);
+    const int32_t d = find_domain(view.in_offsets, view.n_domains, i);
+    const int32_t bsz = a == 0 ? g.b0 : a == 1 ? g.b1 : g.b2;
+    const int32_t bc = a == 0 ? d % g.g0 : a == 1 ? (d / g.g0) % g.g1 : d / (g.g0 * g.g1);
+    const float lo = (float)(bc * bsz), hi = (float)((bc + 1) * bsz);
+    // weight of this axis's brick coordinate in the domain index
+    const int32_t dmul = lane == 3 ? 0 : a == 0 ? 1 : a == 1 ? g.g0 : g.g0 * g.g1;
+    const int32_t sy = g.n, sz = g.n * g.n;
+    const QuadAxis ax{static_cast<const float *>(job.field4) + a,
+                      {0, FW, sy * FW, (sy + 1) * FW, sz * FW, (sz + 1) * FW, (sz + sy) * FW, (sz + sy + 1) * FW},
+                      (float)(g.n - 1), g.n - 2, lane == 3 ? 0 : a == 0 ? 1 : a == 1 ? sy : sz};
+    const float fn = (float)g.n;
+
+    SLItem it = static_cast<const SLItem *>(view.in_items)[i];
+    if ((uint64_t)(uint32_t)it.id >= n_ids) {  // never true for items this library emitted
+        if (lane == 0) rafi_forward_t(view, i, it, RAFI_POISON);
+        return;
+    }
+    const float h = job.h, hh = job.h * 0.5f, h6 = (float)((double)job.h / 6.0);
+    const bool capped = job.steps_per_visit > 0 && n_in > job.tail_items;
+    const int32_t cap = capped ? job.steps_per_visit : 0x7fffffff;
+    QuadWalk s{a == 0 ? it.x : a == 1 ? it.y : it.z, 0.0f, job.steps[it.id], 0, 0, d, false};
+    QuadCell cc, pa, pb;
+    // two steps per trip, so that the two look-ahead slots swap roles
+    // without copies; a particle done after the first skips the second
+    for (;;) {
+        quad_step<FW>(ax, cc, pa, pb, s, h, hh, h6, lo, hi, fn, bsz, dmul, d, job.max_steps, cap);
+        quad_look_ahead<FW>(ax, s, h6, pa);
+        quad_step<FW>(ax, cc, pb, pa, s, h, hh, h6, lo, hi, fn, bsz, dmul, d, job.max_steps, cap);
+        quad_look_ahead<FW>(ax, s, h6, pb);
+        if (s.done) break;
+    }
+    const float x = s.x;
+    const int32_t steps = s.steps, why = s.why, dest = s.dest;
+    const float px = quad_lane<0>(x), py = quad_lane<1>(x), pz = quad_lane<2>(x);
+    if (why && lane < 3) job.endpoint[3 * (size_t)it.id + lane] = x;
+    if (lane != 0) return;
+    job.steps[it.id] = steps;
+    if (job.counters) count_forwards(job.counters, why == 0 && dest != d, why == 0 && dest == d);
+    if (why) {
+        if (job.reason) job.reason[it.id] = why;
+        rafi_done(view, i);
+    } else {
+        it.x = px;
+        it.y = py;
+        it.z = pz;
+        rafi_forward_t(view, i, it, dest);
+    }
+}
+
 constexpr int kSLThreads = 256;
 
 // Persistent form of advance_kernel. Each wave keeps 64 particles in flight:
@@ -409,6 +636,14 @@ int launch_advance(rafi_ctx *c, const rafi_sl_job *job, const rafi_device_view &
         else
             hipLaunchKernelGGL(advance_persistent_kernel<4>, dim3(blocks), dim3(kSLThreads), 0, c->stream, v, *job,
                                c->wave_slots, c->work, blocks * (kSLThreads / 64));
+    } else if (v.n_in && v.n_in <= job->quad_items) {
+        const uint32_t blocks = (uint32_t)((v.n_in + kQuadThreads / 4 - 1) / (kQuadThreads / 4));
+        if (job->field_stride == 3)
+            hipLaunchKernelGGL(advance_quad_kernel<3>, dim3(blocks), dim3(kQuadThreads), 0, c->stream, v, *job,
+                               c->wave_slots);
+        else
+            hipLaunchKernelGGL(advance_quad_kernel<4>, dim3(blocks), dim3(kQuadThreads), 0, c->stream, v, *job,
+                               c->wave_slots);
     } else if (v.n_in) {
         if (job->field_stride == 3)
             hipLaunchKernelGGL(advance_kernel<3>, dim3((uint32_t)one_per_item), dim3(kSLThreads), 0, c->stream, v,

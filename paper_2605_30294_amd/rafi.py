@@ -69,7 +69,7 @@ class SLJob(C.Structure):
     _fields_ = [("field4", C.c_void_p), ("endpoint", C.c_void_p), ("steps", C.c_void_p), ("reason", C.c_void_p),
                 ("counters", C.c_void_p), ("n", C.c_int32), ("grid", C.c_int32 * 3), ("h", C.c_float),
                 ("max_steps", C.c_int32), ("steps_per_visit", C.c_int32), ("tail_items", C.c_uint32),
-                ("refill_lanes", C.c_int32), ("field_stride", C.c_int32)]
+                ("refill_lanes", C.c_int32), ("field_stride", C.c_int32), ("quad_items", C.c_uint32)]
 
 
 class NBJob(C.Structure):
@@ -376,8 +376,12 @@ def sl_pack(field: torch.Tensor) -> torch.Tensor:
     return f4
 
 
+SL_QUAD_ITEMS = 98304  # launch size at and below which four lanes carry each particle
+
+
 def sl_job(field4: torch.Tensor, grid, endpoint, steps, reason=None, h=0.25, max_steps=2000,
-           steps_per_visit=0, counters=None, tail_items=0, refill_lanes=0) -> SLJob:
+           steps_per_visit=0, counters=None, tail_items=0, refill_lanes=0,
+           quad_items=SL_QUAD_ITEMS) -> SLJob:
     """field4: the packed [n, n, n, 4] field of sl_pack, or the [n, n, n, 3] field
     itself (read unpadded). counters: optional int64 device tensor [2]
     (cross-brick forwards, same-brick forwards)."""
@@ -386,7 +390,7 @@ def sl_job(field4: torch.Tensor, grid, endpoint, steps, reason=None, h=0.25, max
         raise ValueError("field must be a contiguous [n, n, n, 3] or [n, n, n, 4] tensor")
     return SLJob(_dptr(field4), _dptr(endpoint), _dptr(steps), _dptr(reason), _dptr(counters), field4.shape[0],
                  (C.c_int32 * 3)(*[int(g) for g in grid]), float(h), int(max_steps), int(steps_per_visit),
-                 int(tail_items), int(refill_lanes), stride)
+                 int(tail_items), int(refill_lanes), stride, int(quad_items))
 
 
 def sl_seed(ctx: Context, job: SLJob, seeds: torch.Tensor):
@@ -406,7 +410,8 @@ def sl_trace_job(ctx: Context, job: SLJob, seeds: torch.Tensor, max_rounds: int 
 
 
 def sl_trace(field4: torch.Tensor, grid, seeds: torch.Tensor, h=0.25, max_steps=2000, ctx: Context | None = None,
-             max_rounds: int = 100000, steps_per_visit=0, tail_items=0, refill_lanes=0):
+             max_rounds: int = 100000, steps_per_visit=0, tail_items=0, refill_lanes=0,
+             quad_items=SL_QUAD_ITEMS):
     dev = field4.device
     N = seeds.shape[0]
     if ctx is None:
@@ -416,7 +421,7 @@ def sl_trace(field4: torch.Tensor, grid, seeds: torch.Tensor, h=0.25, max_steps=
     reason = torch.empty(N, dtype=torch.int32, device=dev)
     counters = torch.zeros(2, dtype=torch.int64, device=dev)
     job = sl_job(field4, grid, endpoint, steps, reason, h, max_steps, steps_per_visit, counters, tail_items,
-                 refill_lanes)
+                 refill_lanes, quad_items)
     rounds, fwd = sl_trace_job(ctx, job, seeds, max_rounds)
     return dict(endpoint=endpoint, steps=steps, reason=reason, rounds=rounds, forwarded=fwd, ctx=ctx,
                 counters=counters)

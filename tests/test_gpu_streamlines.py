@@ -14,7 +14,8 @@ from paper_2605_30294_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def _stepwise(field, grid, seeds, h=0.25, max_steps=2000, steps_per_visit=0, refill_lanes=0, packed=True):
+def _stepwise(field, grid, seeds, h=0.25, max_steps=2000, steps_per_visit=0, refill_lanes=0, packed=True,
+              quad_items=rafi.SL_QUAD_ITEMS):
     dev = device()
     N = len(seeds)
     f4 = torch.from_numpy(np.ascontiguousarray(field)).to(dev)
@@ -24,7 +25,8 @@ def _stepwise(field, grid, seeds, h=0.25, max_steps=2000, steps_per_visit=0, ref
     ep = torch.zeros((N, 3), dtype=torch.float32, device=dev)
     st = torch.zeros(N, dtype=torch.int32, device=dev)
     why = torch.zeros(N, dtype=torch.int32, device=dev)
-    job = rafi.sl_job(f4, grid, ep, st, why, h, max_steps, steps_per_visit, refill_lanes=refill_lanes)
+    job = rafi.sl_job(f4, grid, ep, st, why, h, max_steps, steps_per_visit, refill_lanes=refill_lanes,
+                      quad_items=quad_items)
     rafi.sl_seed(ctx, job, torch.from_numpy(seeds).to(dev))
     counts, queues = [], []
     while True:
@@ -51,16 +53,18 @@ def _compare(g, o):
     assert g["stats"]["bad_dest"] == 0 and g["stats"]["dropped"] == 0
 
 
-# refill_lanes 0: one thread per particle; 1..64: persistent waves that take new
+# refill_lanes 0: one thread per particle (quad 0), or four lanes per particle in
+# launches over at most `quad` particles; 1..64: persistent waves that take new
 # particles whenever that many lanes are idle (1 and 64 are the extremes)
-@pytest.mark.parametrize("refill", [0, 1, 16, 64])
+@pytest.mark.parametrize("refill,quad", [(0, 0), (0, rafi.SL_QUAD_ITEMS), (0, 2048),
+                                               (1, 0), (16, 0), (64, 0)])
 @pytest.mark.parametrize("n,grid,N,max_steps", [(64, (4, 4, 4), 4096, 2000), (64, (2, 1, 4), 3001, 500),
                                                 (32, (1, 1, 1), 100, 300), (96, (3, 4, 2), 2000, 800)])
-def test_abc_matches_oracle(orc, n, grid, N, max_steps, refill):
+def test_abc_matches_oracle(orc, n, grid, N, max_steps, refill, quad):
     field = W.abc_field(n)
     seeds = W.streamline_seeds(N, n, seed=N + n)
-    announce(f"sl abc n={n} grid={grid} N={N} refill={refill}")
-    g = _stepwise(field, grid, seeds, max_steps=max_steps, refill_lanes=refill)
+    announce(f"sl abc n={n} grid={grid} N={N} refill={refill} quad={quad}")
+    g = _stepwise(field, grid, seeds, max_steps=max_steps, refill_lanes=refill, quad_items=quad)
     o = orc.streamlines(field, grid, seeds, max_steps=max_steps, queue_cap=1 << 24)
     _compare(g, o)
 
@@ -81,15 +85,16 @@ def test_steps_per_visit_cap(orc, cap, refill):
     assert np.array_equal(g["endpoint"], u["endpoint"]) and np.array_equal(g["steps"], u["steps"])
 
 
-@pytest.mark.parametrize("refill", [0, 16])
-def test_unpadded_field_layout(orc, refill):
+@pytest.mark.parametrize("refill,quad", [(0, 0), (0, rafi.SL_QUAD_ITEMS), (16, 0)])
+def test_unpadded_field_layout(orc, refill, quad):
     """The n^3 x 3 field read as is (12-byte voxels) gives the same routing and
     results as the padded layout."""
     n, grid, N = 64, (4, 2, 2), 3000
     field = W.abc_field(n)
     seeds = W.streamline_seeds(N, n, seed=77)
-    announce(f"sl unpadded field refill={refill}")
-    g = _stepwise(field, grid, seeds, max_steps=900, refill_lanes=refill, packed=False)
+    announce(f"sl unpadded field refill={refill} quad={quad}")
+    g = _stepwise(field, grid, seeds, max_steps=900, refill_lanes=refill, packed=False,
+                  quad_items=quad)
     o = orc.streamlines(field, grid, seeds, max_steps=900, queue_cap=1 << 24)
     _compare(g, o)
 
@@ -136,6 +141,10 @@ def test_full_cfg1_sampled(orc):
         assert torch.equal(r["reason"], r4["reason"])
         assert int(r4["counters"][0]) == int(r["counters"][0])
         assert r4["forwarded"] == N + int(r4["counters"].sum())
+    # one lane per particle in every launch: same particles
+    r6 = rafi.sl_trace(f4, (4, 4, 4), torch.from_numpy(seeds).to(dev), quad_items=0)
+    assert torch.equal(r["endpoint"], r6["endpoint"]) and torch.equal(r["steps"], r6["steps"])
+    assert torch.equal(r["reason"], r6["reason"]) and r6["forwarded"] == r["forwarded"]
     # the unpadded field layout: same particles
     r5 = rafi.sl_trace(torch.from_numpy(field).to(dev), (4, 4, 4), torch.from_numpy(seeds).to(dev),
                        steps_per_visit=128)
