@@ -14,7 +14,9 @@ same for any schedule) divided by the job's GPU wall time. A particle that
 has taken `--steps-per-visit` steps in one launch is also forwarded to its
 own brick so that a round never waits on one long-lived particle; those
 same-brick forwards are reported separately and not counted in `value`. Also reported: RK4 steps per second, the
-roofline of the dominant kernel (the RK4 brick kernel) from HIP events taken
+roofline of the dominant kernels (the RK4 brick march: every domain launch,
+one lane per particle in large launches, a lane quad per particle in small
+ones) from HIP events taken
 on the stream it runs on, the CPU oracle on a bounded sample, and extras: the
 64M-item x 32-byte multi-split microbenchmark (uniform and Zipf over 1024
 destinations) against the HBM roofline, and the 128^3 / 64-view
@@ -55,13 +57,14 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-# HBM-side bytes per launch of the RK4 kernel: FETCH_SIZE + WRITE_SIZE per
-# dispatch, scaled by a plain copy of known size (profiles/
-# rk4_advance_256cube_1Mseeds.md), for the source file and schedule below;
-# reported only while both still hold.
-RK4_TRAFFIC = {"kernel": "advance_kernel<3>", "bytes_per_launch": 386147774,
-               "source": "paper_2605_30294_amd/csrc/streamline.hip", "source_sha256_16": "3aa6d0f15bab2101",
-               "schedule": (64, 0, 0), "field_layout": "unpadded"}
+# HBM-side bytes per RK4 launch (mean over every domain launch of the job,
+# both kernels): FETCH_SIZE + WRITE_SIZE per dispatch, scaled by a plain copy
+# of known size (profiles/rk4_advance_256cube_1Mseeds.md), for the source
+# file and schedule (steps_per_visit, tail_items, refill_lanes, quad_items)
+# below; reported only while both still hold.
+RK4_TRAFFIC = {"kernel": "advance_kernel<3> + advance_quad_kernel<3>", "bytes_per_launch": 386617872,
+               "source": "paper_2605_30294_amd/csrc/streamline.hip", "source_sha256_16": "eac1b26ac7163518",
+               "schedule": (64, 0, 0, 98304), "field_layout": "unpadded"}
 
 
 def rk4_traffic(schedule, layout):
@@ -92,19 +95,20 @@ def streamline_job(args, dev):
     steps = torch.empty(N, dtype=torch.int32, device=dev)
     reason = torch.empty(N, dtype=torch.int32, device=dev)
     counters = torch.zeros(2, dtype=torch.int64, device=dev)
+    quad = rafi.SL_QUAD_ITEMS if args.quad_items is None else args.quad_items
     job = rafi.sl_job(f4, grid, endpoint, steps, reason, h, max_steps, args.steps_per_visit, counters,
-                      args.tail_items, args.refill_lanes)
+                      args.tail_items, args.refill_lanes, quad)
     tuned = None
     if args.autotune or args.steps_per_visit < 0:      # sweep the schedule (results do not depend on it)
         from paper_2605_30294_amd import autotune
         tuned, _, sweep = autotune.tune_streamlines(ctx, job, seeds)
-        log("streamline schedule sweep (ms, (steps_per_visit, tail_items, refill_lanes)): "
+        log("streamline schedule sweep (ms, (steps_per_visit, tail_items, refill_lanes, quad_items)): "
             + ", ".join(f"{m:.2f} {t}" for m, t in sweep))
     # field layout: the same values with 16 or 12 bytes per voxel; keep the faster
     layout_ms = {}
     for name, f in (layouts.items() if args.field_layout == "auto" or args.autotune else ()):
         lj = rafi.sl_job(f, grid, endpoint, steps, reason, h, max_steps, job.steps_per_visit, counters,
-                         job.tail_items, job.refill_lanes)
+                         job.tail_items, job.refill_lanes, job.quad_items)
         rafi.sl_trace_job(ctx, lj, seeds)
         torch.cuda.synchronize()
         a = torch.cuda.Event(enable_timing=True)
@@ -119,7 +123,7 @@ def streamline_job(args, dev):
     log("streamline field layout (ms): " + ", ".join(f"{k} {v:.2f}" for k, v in layout_ms.items())
         + f"; using {layout}")
     job = rafi.sl_job(layouts[layout], grid, endpoint, steps, reason, h, max_steps, job.steps_per_visit, counters,
-                      job.tail_items, job.refill_lanes)
+                      job.tail_items, job.refill_lanes, job.quad_items)
     for _ in range(args.warmup):
         rafi.sl_trace_job(ctx, job, seeds)
     torch.cuda.synchronize()
@@ -151,15 +155,22 @@ def streamline_job(args, dev):
     avg_launch_ms = dom_ms / max(launches, 1)
     flops_per_launch = rk4_steps * RK4_FLOPS_PER_STEP / max(launches, 1)
     achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
+    schedule = (job.steps_per_visit, job.tail_items, job.refill_lanes, job.quad_items)
+    fw = "<3>" if layout == "unpadded" else "<4>"
+    if job.refill_lanes:
+        kernels = "advance_persistent_kernel" + fw
+    elif job.quad_items:
+        kernels = f"advance_kernel{fw} + advance_quad_kernel{fw} (launches over <= {job.quad_items} particles)"
+    else:
+        kernels = "advance_kernel" + fw
     out = dict(ms=ms, rounds=rounds, forwarded=N + cross, step_items=fwd, self_fwd=self_fwd, rk4_steps=rk4_steps,
-               schedule=(job.steps_per_visit, job.tail_items, job.refill_lanes), field_layout=layout,
+               schedule=schedule, field_layout=layout,
                domain_ms=dom_ms, split_ms=split_ms,
                launches=launches, avg_launch_ms=avg_launch_ms,
-               roofline={"kernel": ("advance_persistent_kernel" if job.refill_lanes else "advance_kernel")
-                         + ("<3>" if layout == "unpadded" else "<4>") + " (RK4 brick march)", "bound": "alu",
+               roofline={"kernel": kernels + ", RK4 brick march: every domain launch", "bound": "alu",
                          "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
                          "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
-                         "traffic": rk4_traffic((job.steps_per_visit, job.tail_items, job.refill_lanes), layout),
+                         "traffic": rk4_traffic(schedule, layout),
                          "traffic_unit": "bytes per launch (HBM side: FETCH_SIZE + WRITE_SIZE, calibrated)",
                          "per_launch_flops": flops_per_launch, "avg_launch_ms": round(avg_launch_ms, 4)})
     ctx.close()
@@ -544,10 +555,14 @@ def main():
     ap.add_argument("--refill-lanes", type=int, default=0,
                     help="persistent RK4 waves refill when this many lanes are idle (0: one thread per "
                          "particle); ignored when the schedule is autotuned")
+    ap.add_argument("--quad-items", type=int, default=None,
+                    help="launches over at most this many particles run four lanes per particle (default: "
+                         "the library's SL_QUAD_ITEMS; 0: never); ignored when the schedule is autotuned")
     ap.add_argument("--field-layout", default="unpadded", choices=["auto", "padded", "unpadded"],
                     help="RK4 field with 16-byte (padded) or 12-byte voxels; auto keeps the faster")
     ap.add_argument("--autotune", action="store_true",
-                    help="sweep (steps_per_visit, tail_items, refill_lanes) and the field layout before timing "
+                    help="sweep (steps_per_visit, tail_items, refill_lanes, quad_items) and the field layout "
+                         "before timing "
                          "instead of using the defaults below (the measured best on MI355X)")
     ap.add_argument("--steps-per-visit", type=int, default=64,
                     help="RK4 steps a particle takes per domain visit before it is forwarded to its own "
@@ -615,7 +630,8 @@ def main():
         "rounds": sl["rounds"], "forwarded_per_step": sl["forwarded"],
         "forward_step_items_per_step": sl["step_items"], "same_brick_forwards_per_step": sl["self_fwd"],
         "schedule": {"steps_per_visit": sl["schedule"][0], "tail_items": sl["schedule"][1],
-                     "refill_lanes": sl["schedule"][2], "field_layout": sl["field_layout"]},
+                     "refill_lanes": sl["schedule"][2], "quad_items": sl["schedule"][3],
+                     "field_layout": sl["field_layout"]},
         "time_split": {"domain_kernels_ms": round(sl["domain_ms"], 4), "forward_steps_ms": round(sl["split_ms"], 4)},
         "roofline": sl["roofline"],
         "cpu_baseline": cpu,

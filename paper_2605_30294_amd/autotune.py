@@ -77,26 +77,29 @@ def tune_batch(batch, volumes, image, space=None, reps=2, use_cache=True):
     return best, best_ms, results
 
 
-# (steps_per_visit, tail_items, refill_lanes)
-STREAMLINE_SPACE = [(c, t, r) for c in (32, 64, 128, 256, 512) for t in (0, 65536) for r in (0, 8, 16, 32)]
+# (steps_per_visit, tail_items, refill_lanes, quad_items); the quad launches
+# apply only with refill_lanes 0
+STREAMLINE_SPACE = ([(c, t, r, 0) for c in (32, 64, 128, 256, 512) for t in (0, 65536) for r in (8, 16, 32)]
+                    + [(c, t, 0, q) for c in (32, 64, 128, 256, 512) for t in (0, 65536)
+                       for q in (0, 65536, 98304, 131072, 262144)])
 
 
 def _set_schedule(job, tuning):
-    job.steps_per_visit, job.tail_items, job.refill_lanes = (int(v) for v in tuning)
+    job.steps_per_visit, job.tail_items, job.refill_lanes, job.quad_items = (int(v) for v in tuning)
 
 
 def tune_streamlines(ctx, job, seeds, space=None, reps=1, use_cache=True):
-    """Picks (steps_per_visit, tail_items, refill_lanes) for a streamline job by
-    timing whole traces; results do not depend on the choice.
+    """Picks (steps_per_visit, tail_items, refill_lanes, quad_items) for a
+    streamline job by timing whole traces; results do not depend on the choice.
     Returns (best, ms, results)."""
     from . import rafi
 
     path = cache_path()
     dev = torch.cuda.get_device_name(torch.cuda.current_device())
     key = (f"{dev}|streamlines|n={job.n}|grid={list(job.grid)}|seeds={seeds.shape[0]}|max_steps={job.max_steps}"
-           f"|schedule=cap,tail,refill")
+           f"|schedule=cap,tail,refill,quad")
     cache = _load(path) if use_cache else {}
-    if use_cache and key in cache and len(cache[key]["tuning"]) == 3:
+    if use_cache and key in cache and len(cache[key]["tuning"]) == 4:
         _set_schedule(job, cache[key]["tuning"])
         return tuple(cache[key]["tuning"]), cache[key]["ms"], []
     results = []
