@@ -48,23 +48,38 @@ struct CellCache {
     V3 c[8];
 };
 
+// Cell index and weight along one axis of sample coordinate q: the sample
+// shifted by half a voxel, clamped to [0, n-1], its floor limited to n-2.
+// (med3 is the clamp for any non-NaN value; the floor is an integer below
+// 2^24, so taking the limit in float is exact.)
+__device__ inline float cell_axis(float q, float hi, float top, int32_t &i)
+{
+    const float uc = __builtin_amdgcn_fmed3f(q - 0.5f, 0.0f, hi);
+    const float fl = fminf(floorf(uc), top);
+    i = (int32_t)fl;
+    return uc - fl;
+}
+
+// Linear voxel index i0 + n i1 + n^2 i2. The entry points check n^3 < 2^31,
+// so n <= 1290 and every factor is below 2^24: the full-rate 24-bit
+// multiplies are exact.
+__device__ inline int32_t voxel_index(int32_t i0, int32_t i1, int32_t i2, int32_t sy, int32_t sz)
+{
+    return i0 + (int32_t)__umul24((uint32_t)i1, (uint32_t)sy) + (int32_t)__umul24((uint32_t)i2, (uint32_t)sz);
+}
+
 template <int FW>
 __device__ inline void field_at(const typename Voxel<FW>::type *__restrict__ f, int32_t n, CellCache &cc, float qx,
                                 float qy, float qz, float &vx, float &vy, float &vz)
 {
-    const float hi = (float)(n - 1);
-    float u[3] = {qx - 0.5f, qy - 0.5f, qz - 0.5f};
+    const float hi = (float)(n - 1), top = (float)(n - 2);
     int32_t i0[3];
     float w[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const float uc = fminf(fmaxf(u[a], 0.0f), hi);
-        const int32_t i = min((int32_t)floorf(uc), n - 2);
-        i0[a] = i;
-        w[a] = uc - (float)i;
-    }
+    w[0] = cell_axis(qx, hi, top, i0[0]);
+    w[1] = cell_axis(qy, hi, top, i0[1]);
+    w[2] = cell_axis(qz, hi, top, i0[2]);
     const int32_t sy = n, sz = n * n;  // n^3 < 2^31 (checked by the entry points)
-    const int32_t base = i0[0] + sy * i0[1] + sz * i0[2];
+    const int32_t base = voxel_index(i0[0], i0[1], i0[2], sy, sz);
     if (base != cc.base) {
         const typename Voxel<FW>::type *b = f + base;
         cc.c[0] = load_voxel<FW>(b, 0);
@@ -291,8 +306,8 @@ struct QuadCell {
 struct QuadAxis {
     const float *f;
     int32_t o[8];
-    float hi;     // n - 1
-    int32_t top;  // n - 2
+    float hi;   // n - 1
+    float top;  // n - 2
     int32_t stride;
 };
 
@@ -300,10 +315,9 @@ struct QuadAxis {
 // as the one-lane sampler computes them.
 __device__ inline int32_t quad_cell(const QuadAxis &ax, float q, float &w)
 {
-    const float uc = fminf(fmaxf(q - 0.5f, 0.0f), ax.hi);
-    const int32_t i = min((int32_t)floorf(uc), ax.top);
-    w = uc - (float)i;
-    return quad_sum(i * ax.stride);
+    int32_t i;
+    w = cell_axis(q, ax.hi, ax.top, i);
+    return quad_sum((int32_t)__umul24((uint32_t)i, (uint32_t)ax.stride));
 }
 
 template <int FW>
@@ -423,7 +437,7 @@ advance_quad_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids)
     const int32_t sy = g.n, sz = g.n * g.n;
     const QuadAxis ax{static_cast<const float *>(job.field4) + a,
                       {0, FW, sy * FW, (sy + 1) * FW, sz * FW, (sz + 1) * FW, (sz + sy) * FW, (sz + sy + 1) * FW},
-                      (float)(g.n - 1), g.n - 2, lane == 3 ? 0 : a == 0 ? 1 : a == 1 ? sy : sz};
+                      (float)(g.n - 1), (float)(g.n - 2), lane == 3 ? 0 : a == 0 ? 1 : a == 1 ? sy : sz};
     const float fn = (float)g.n;
 
     SLItem it = static_cast<const SLItem *>(view.in_items)[i];
