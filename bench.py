@@ -62,8 +62,8 @@ def log(msg):
 # of known size (profiles/rk4_advance_256cube_1Mseeds.md), for the source
 # file and schedule (steps_per_visit, tail_items, refill_lanes, quad_items)
 # below; reported only while both still hold.
-RK4_TRAFFIC = {"kernel": "advance_kernel<3> + advance_quad_kernel<3>", "bytes_per_launch": 386617872,
-               "source": "paper_2605_30294_amd/csrc/streamline.hip", "source_sha256_16": "eac1b26ac7163518",
+RK4_TRAFFIC = {"kernel": "advance_kernel<3> + advance_quad_kernel<3>", "bytes_per_launch": 385890932,
+               "source": "paper_2605_30294_amd/csrc/streamline.hip", "source_sha256_16": "59d733d2381cafeb",
                "schedule": (64, 0, 0, 98304), "field_layout": "unpadded"}
 
 

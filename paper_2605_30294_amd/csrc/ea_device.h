@@ -104,15 +104,13 @@ __device__ inline Tri tri_setup(int32_t n, const float p[3])
 {
     int32_t i0[3];
     float f[3];
-    const float hi = (float)(n - 1), top = (float)(n - 2);
+    const float hi = (float)(n - 1);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        // the clamp to [0, n-1] as one med3 (p is never NaN), and the floor
-        // limited to n-2 in float: exact, as the floor is an integer below 2^24
-        const float u = __builtin_amdgcn_fmed3f(p[a] - 0.5f, 0.0f, hi);
-        const float fl = fminf(floorf(u), top);
-        i0[a] = (int32_t)fl;
-        f[a] = u - fl;
+        const float u = fminf(fmaxf(p[a] - 0.5f, 0.0f), hi);
+        const int32_t i = min((int32_t)floorf(u), n - 2);
+        i0[a] = i;
+        f[a] = u - (float)i;
     }
     return Tri{i0[0] + (int64_t)n * (i0[1] + (int64_t)n * i0[2]), i0[0], i0[1], i0[2], f[0], f[1], f[2]};
 }
