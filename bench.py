@@ -62,9 +62,9 @@ def log(msg):
 # of known size (profiles/rk4_advance_256cube_1Mseeds.md), for the source
 # file and schedule (steps_per_visit, tail_items, refill_lanes, quad_items)
 # below; reported only while both still hold.
-RK4_TRAFFIC = {"kernel": "advance_kernel<3> + advance_quad_kernel<3>", "bytes_per_launch": 385890932,
+RK4_TRAFFIC = {"kernel": "advance_kernel<3> + advance_quad_kernel<3>", "bytes_per_launch": 371811470,
                "source": "paper_2605_30294_amd/csrc/streamline.hip", "source_sha256_16": "59d733d2381cafeb",
-               "schedule": (64, 0, 0, 98304), "field_layout": "unpadded"}
+               "schedule": (96, 0, 0, 98304), "field_layout": "unpadded"}
 
 
 def rk4_traffic(schedule, layout):
@@ -564,7 +564,7 @@ def main():
                     help="sweep (steps_per_visit, tail_items, refill_lanes, quad_items) and the field layout "
                          "before timing "
                          "instead of using the defaults below (the measured best on MI355X)")
-    ap.add_argument("--steps-per-visit", type=int, default=64,
+    ap.add_argument("--steps-per-visit", type=int, default=96,
                     help="RK4 steps a particle takes per domain visit before it is forwarded to its own "
                          "brick (0 = until it leaves, -1 = autotune with the tail threshold); results do "
                          "not depend on it")
