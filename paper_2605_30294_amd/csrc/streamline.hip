@@ -102,6 +102,76 @@ __device__ inline void field_at(const typename Voxel<FW>::type *__restrict__ f, 
 #undef TRI
 }
 
+// The same sampler reading the field through a buffer resource, for fields
+// of at most 2^31 - 1 bytes: a cell's 8 corners are loaded with one per-lane
+// byte offset (the corner voxel), a wave-uniform offset per row (0, n, n^2,
+// n^2 + n voxels) and an immediate of 0 or 1 voxel, so the loads need one
+// address register instead of four 64-bit pointers. Same values.
+struct FieldBuf {
+    __amdgpu_buffer_rsrc_t r;
+    int32_t row[4];  // byte offsets of the rows (0, n, n^2, n^2 + n voxels)
+};
+
+template <int FW>
+__device__ inline V3 load_voxel_buf(const FieldBuf &fb, int32_t voff, int32_t soff)
+{
+    if constexpr (FW == 4) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(fb.r, voff, soff, 0);
+        return V3{__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2])};
+    } else {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b96(fb.r, voff, soff, 0);
+        return V3{__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2])};
+    }
+}
+
+template <int FW>
+__device__ inline void field_at_buf(const FieldBuf &fb, int32_t n, CellCache &cc, float qx, float qy, float qz,
+                                    float &vx, float &vy, float &vz)
+{
+    const float hi = (float)(n - 1), top = (float)(n - 2);
+    int32_t i0[3];
+    float w[3];
+    w[0] = cell_axis(qx, hi, top, i0[0]);
+    w[1] = cell_axis(qy, hi, top, i0[1]);
+    w[2] = cell_axis(qz, hi, top, i0[2]);
+    const int32_t base = voxel_index(i0[0], i0[1], i0[2], n, n * n);
+    if (base != cc.base) {
+        const int32_t vo = base * (FW * 4);  // below 2^31: the launch checks the field size
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            cc.c[2 * r] = load_voxel_buf<FW>(fb, vo, fb.row[r]);
+            cc.c[2 * r + 1] = load_voxel_buf<FW>(fb, vo + FW * 4, fb.row[r]);
+        }
+        cc.base = base;
+    }
+    const V3 *c = cc.c;
+#define TRI(comp)                                                                                   \
+    lerpf(lerpf(lerpf(c[0].comp, c[1].comp, w[0]), lerpf(c[2].comp, c[3].comp, w[0]), w[1]),        \
+          lerpf(lerpf(c[4].comp, c[5].comp, w[0]), lerpf(c[6].comp, c[7].comp, w[0]), w[1]), w[2])
+    vx = TRI(x);
+    vy = TRI(y);
+    vz = TRI(z);
+#undef TRI
+}
+
+// rk4_step over any sampler S(qx, qy, qz, vx, vy, vz).
+template <typename S>
+__device__ inline void rk4_step_with(S &&sample, float h, float hh, float h6, float x, float y, float z, float &nx,
+                                     float &ny, float &nz)
+{
+    float k1x, k1y, k1z, k2x, k2y, k2z, k3x, k3y, k3z, k4x, k4y, k4z;
+    sample(x, y, z, k1x, k1y, k1z);
+    sample(__fmaf_rn(hh, k1x, x), __fmaf_rn(hh, k1y, y), __fmaf_rn(hh, k1z, z), k2x, k2y, k2z);
+    sample(__fmaf_rn(hh, k2x, x), __fmaf_rn(hh, k2y, y), __fmaf_rn(hh, k2z, z), k3x, k3y, k3z);
+    sample(__fmaf_rn(h, k3x, x), __fmaf_rn(h, k3y, y), __fmaf_rn(h, k3z, z), k4x, k4y, k4z);
+    const float sx = __fmaf_rn(2.0f, k3x, __fmaf_rn(2.0f, k2x, k1x)) + k4x;
+    const float sy = __fmaf_rn(2.0f, k3y, __fmaf_rn(2.0f, k2y, k1y)) + k4y;
+    const float sz = __fmaf_rn(2.0f, k3z, __fmaf_rn(2.0f, k2z, k1z)) + k4z;
+    nx = __fmaf_rn(h6, sx, x);
+    ny = __fmaf_rn(h6, sy, y);
+    nz = __fmaf_rn(h6, sz, z);
+}
+
 // One classical RK4 step from (x, y, z), with the operation order fixed above.
 template <int FW>
 __device__ inline void rk4_step(const typename Voxel<FW>::type *__restrict__ F, int32_t n, CellCache &cc, float h,
@@ -188,7 +258,7 @@ __device__ inline void count_forwards(unsigned long long *counters, bool cross, 
     }
 }
 
-template <int FW>
+template <int FW, bool BUF>
 __global__ void __launch_bounds__(256)
 advance_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids)
 {
@@ -206,7 +276,7 @@ advance_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids)
     const float lo2 = (float)(bz * g.b2), hi2 = (float)((bz + 1) * g.b2);
     const typename Voxel<FW>::type *__restrict__ F = reinterpret_cast<const typename Voxel<FW>::type *>(job.field4);
 
-    SLItem it = static_cast<const SLItem *>(view.in_items)[i];
+    const SLItem it = static_cast<const SLItem *>(view.in_items)[i];
     if ((uint64_t)(uint32_t)it.id >= n_ids) {  // never true for items this library emitted
         rafi_forward_t(view, i, it, RAFI_POISON);
         return;
@@ -218,9 +288,25 @@ advance_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids)
     float x = it.x, y = it.y, z = it.z;
     int32_t dest = d, why = 0;
     CellCache cc;
+    FieldBuf fb;
+    if constexpr (BUF) {
+        const int32_t row = g.n * FW * 4, plane = g.n * row;
+        fb.r = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(job.field4), (short)0, plane * g.n, 0x00020000);
+        fb.row[0] = 0;
+        fb.row[1] = row;
+        fb.row[2] = plane;
+        fb.row[3] = plane + row;
+    }
     for (int32_t taken = 0;;) {
         float nx, ny, nz;
-        rk4_step<FW>(F, g.n, cc, h, hh, h6, x, y, z, nx, ny, nz);
+        if constexpr (BUF)
+            rk4_step_with(
+                [&](float qx, float qy, float qz, float &vx, float &vy, float &vz) {
+                    field_at_buf<FW>(fb, g.n, cc, qx, qy, qz, vx, vy, vz);
+                },
+                h, hh, h6, x, y, z, nx, ny, nz);
+        else
+            rk4_step<FW>(F, g.n, cc, h, hh, h6, x, y, z, nx, ny, nz);
         ++steps;
         ++taken;
         const bool same = __float_as_uint(nx) == __float_as_uint(x) && __float_as_uint(ny) == __float_as_uint(y) &&
@@ -235,19 +321,20 @@ advance_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids)
         if (steps >= job.max_steps) { why = RAFI_SL_MAXSTEPS; break; }
         if (e != d || taken >= cap) { dest = e; break; }
     }
-    job.steps[it.id] = steps;
+    // the slot and the particle id again, rather than keeping them live
+    // through the loop
+    const uint64_t slot = rafi_xcd_block(blockIdx.x, nb) * (uint64_t)blockDim.x + threadIdx.x;
+    const int32_t id = static_cast<const SLItem *>(view.in_items)[slot].id;
+    job.steps[id] = steps;
     if (job.counters) count_forwards(job.counters, why == 0 && dest != d, why == 0 && dest == d);
     if (why) {
-        job.endpoint[3 * (size_t)it.id] = x;
-        job.endpoint[3 * (size_t)it.id + 1] = y;
-        job.endpoint[3 * (size_t)it.id + 2] = z;
-        if (job.reason) job.reason[it.id] = why;
-        rafi_done(view, i);
+        job.endpoint[3 * (size_t)id] = x;
+        job.endpoint[3 * (size_t)id + 1] = y;
+        job.endpoint[3 * (size_t)id + 2] = z;
+        if (job.reason) job.reason[id] = why;
+        rafi_done(view, slot);
     } else {
-        it.x = x;
-        it.y = y;
-        it.z = z;
-        rafi_forward_t(view, i, it, dest);
+        rafi_forward_t(view, slot, SLItem{x, y, z, id}, dest);
     }
 }
 
@@ -659,12 +746,21 @@ int launch_advance(rafi_ctx *c, const rafi_sl_job *job, const rafi_device_view &
             hipLaunchKernelGGL(advance_quad_kernel<4>, dim3(blocks), dim3(kQuadThreads), 0, c->stream, v, *job,
                                c->wave_slots);
     } else if (v.n_in) {
-        if (job->field_stride == 3)
-            hipLaunchKernelGGL(advance_kernel<3>, dim3((uint32_t)one_per_item), dim3(kSLThreads), 0, c->stream, v,
-                               *job, c->wave_slots);
-        else
-            hipLaunchKernelGGL(advance_kernel<4>, dim3((uint32_t)one_per_item), dim3(kSLThreads), 0, c->stream, v,
-                               *job, c->wave_slots);
+        // buffer loads while the field's byte offsets fit a signed 32-bit register
+        const uint64_t n = (uint64_t)job->n;
+        const bool buf = n * n * n * (uint64_t)(job->field_stride == 3 ? 12 : 16) <= 0x7fffffffull;
+        const dim3 grid((uint32_t)one_per_item), block(kSLThreads);
+        if (job->field_stride == 3) {
+            if (buf)
+                hipLaunchKernelGGL((advance_kernel<3, true>), grid, block, 0, c->stream, v, *job, c->wave_slots);
+            else
+                hipLaunchKernelGGL((advance_kernel<3, false>), grid, block, 0, c->stream, v, *job, c->wave_slots);
+        } else {
+            if (buf)
+                hipLaunchKernelGGL((advance_kernel<4, true>), grid, block, 0, c->stream, v, *job, c->wave_slots);
+            else
+                hipLaunchKernelGGL((advance_kernel<4, false>), grid, block, 0, c->stream, v, *job, c->wave_slots);
+        }
     }
     prof_domain_end(c, ph);
     RAFI_LAUNCH_CHECK();

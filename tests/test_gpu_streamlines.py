@@ -160,3 +160,27 @@ def test_full_cfg1_sampled(orc):
     assert np.all(st[why == 3] == 2000)
     out = np.any((ep < 0) | (ep >= n), axis=1)
     assert np.array_equal(out, why == 2)
+
+
+@pytest.mark.parametrize("n,packed", [(564, False), (512, True)])
+def test_large_field_global_loads(orc, n, packed):
+    """Fields of more than 2^31 - 1 bytes (564^3 x 12 B, 512^3 x 16 B) are
+    read with 64-bit addresses, smaller ones through a buffer resource: the
+    one-lane kernel (quad_items 0) must match the oracle on both sides."""
+    dev = device()
+    field_d = W.abc_field(n, device=dev)
+    f = rafi.sl_pack(field_d) if packed else field_d
+    assert f.numel() * 4 > 2**31 - 1
+    seeds = W.streamline_seeds(256, n, seed=11)
+    announce(f"sl large field n={n} packed={packed}")
+    r = rafi.sl_trace(f, (4, 4, 4), torch.from_numpy(seeds).to(dev), steps_per_visit=96, quad_items=0)
+    torch.cuda.synchronize()
+    ep, st, why = r["endpoint"].cpu().numpy(), r["steps"].cpu().numpy(), r["reason"].cpu().numpy()
+    r["ctx"].close()
+    field = field_d.cpu().numpy()
+    del f, field_d, r
+    torch.cuda.empty_cache()
+    o = orc.streamlines_brute(field, (4, 4, 4), seeds)
+    assert np.array_equal(ep.view(np.uint32), o["endpoint"].view(np.uint32))
+    assert np.array_equal(st, o["steps"])
+    assert np.array_equal(why, o["reason"])
