@@ -62,8 +62,8 @@ def log(msg):
 # of known size (profiles/rk4_advance_256cube_1Mseeds.md), for the source
 # file and schedule (steps_per_visit, tail_items, refill_lanes, quad_items)
 # below; reported only while both still hold.
-RK4_TRAFFIC = {"kernel": "advance_kernel<3> + advance_quad_kernel<3>", "bytes_per_launch": 371811470,
-               "source": "paper_2605_30294_amd/csrc/streamline.hip", "source_sha256_16": "59d733d2381cafeb",
+RK4_TRAFFIC = {"kernel": "advance_kernel<3, true> + advance_quad_kernel<3>", "bytes_per_launch": 360585892,
+               "source": "paper_2605_30294_amd/csrc/streamline.hip", "source_sha256_16": "0a3ee6d2bf4318c5",
                "schedule": (96, 0, 0, 98304), "field_layout": "unpadded"}
 
 
@@ -156,13 +156,15 @@ def streamline_job(args, dev):
     flops_per_launch = rk4_steps * RK4_FLOPS_PER_STEP / max(launches, 1)
     achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
     schedule = (job.steps_per_visit, job.tail_items, job.refill_lanes, job.quad_items)
-    fw = "<3>" if layout == "unpadded" else "<4>"
+    fw = 3 if layout == "unpadded" else 4
+    # the one-lane kernel reads fields of at most 2^31 - 1 bytes through a buffer resource
+    one_lane = f"advance_kernel<{fw}, {'true' if n ** 3 * fw * 4 <= 2 ** 31 - 1 else 'false'}>"
     if job.refill_lanes:
-        kernels = "advance_persistent_kernel" + fw
+        kernels = f"advance_persistent_kernel<{fw}>"
     elif job.quad_items:
-        kernels = f"advance_kernel{fw} + advance_quad_kernel{fw} (launches over <= {job.quad_items} particles)"
+        kernels = f"{one_lane} + advance_quad_kernel<{fw}> (launches over <= {job.quad_items} particles)"
     else:
-        kernels = "advance_kernel" + fw
+        kernels = one_lane
     out = dict(ms=ms, rounds=rounds, forwarded=N + cross, step_items=fwd, self_fwd=self_fwd, rk4_steps=rk4_steps,
                schedule=schedule, field_layout=layout,
                domain_ms=dom_ms, split_ms=split_ms,
