@@ -184,3 +184,25 @@ def test_large_field_global_loads(orc, n, packed):
     assert np.array_equal(ep.view(np.uint32), o["endpoint"].view(np.uint32))
     assert np.array_equal(st, o["steps"])
     assert np.array_equal(why, o["reason"])
+
+
+@pytest.mark.parametrize("quad", [0, rafi.SL_QUAD_ITEMS])
+@pytest.mark.parametrize("n", [8, 2])
+def test_edge_seeds_tiny_fields(orc, n, quad):
+    """Seeds on brick faces, just below them and below n, at -0.0 and
+    outside the volume, in 8^3 and 2^3 fields of 2x2x2 bricks (1-voxel bricks
+    at n = 2): routing, counts and results equal the oracle's with one lane
+    or a lane quad per particle."""
+    b = n // 2
+    below = lambda v: float(np.nextafter(np.float32(v), np.float32(0)))
+    vals = [0.0, -0.0, float(b), below(b), below(n), 0.3 * n]
+    grid_pts = np.array([(x, y, z) for x in vals for y in vals for z in vals], dtype=np.float32)
+    outside = np.array([[-0.5, 1.0, 1.0], [n, 0.5, 0.5], [0.5, n + 0.25, 0.5], [0.5, 0.5, -1e-7],
+                        [below(n), below(n), n], [-0.0, -0.0, -1.0], [1e9, 0, 0], [0, -1e9, 0], [0, 0, n]],
+                       dtype=np.float32)
+    seeds = np.concatenate([grid_pts, outside])
+    field = W.abc_field(n)
+    announce(f"sl edge seeds n={n} quad={quad}")
+    g = _stepwise(field, (2, 2, 2), seeds, max_steps=300, quad_items=quad)
+    o = orc.streamlines(field, (2, 2, 2), seeds, max_steps=300, queue_cap=1 << 22)
+    _compare(g, o)
