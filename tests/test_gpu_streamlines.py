@@ -206,3 +206,36 @@ def test_edge_seeds_tiny_fields(orc, n, quad):
     g = _stepwise(field, (2, 2, 2), seeds, max_steps=300, quad_items=quad)
     o = orc.streamlines(field, (2, 2, 2), seeds, max_steps=300, queue_cap=1 << 22)
     _compare(g, o)
+
+
+def test_streamline_autotune(orc, tmp_path, monkeypatch):
+    """The schedule autotuner times whole traces over (steps_per_visit,
+    tail_items, refill_lanes, quad_items), sets the job to the fastest, caches
+    it; results under the chosen schedule equal the oracle's."""
+    from paper_2605_30294_amd import autotune
+    monkeypatch.setenv("RAFI_TUNE_CACHE", str(tmp_path / "tune.json"))
+    dev = device()
+    n, grid, N = 64, (4, 4, 4), 4096
+    field = W.abc_field(n)
+    seeds = W.streamline_seeds(N, n, seed=21)
+    announce("sl autotune")
+    f4 = rafi.sl_pack(torch.from_numpy(field).to(dev))
+    ctx = rafi.Context(64, rafi.SL_ITEM_BYTES, N)
+    ep = torch.zeros((N, 3), dtype=torch.float32, device=dev)
+    st = torch.zeros(N, dtype=torch.int32, device=dev)
+    why = torch.zeros(N, dtype=torch.int32, device=dev)
+    job = rafi.sl_job(f4, grid, ep, st, why, 0.25, 600)
+    space = [(32, 0, 0, 0), (32, 0, 0, 4096), (16, 0, 8, 0), (64, 1024, 0, 2048)]
+    d_seeds = torch.from_numpy(seeds).to(dev)
+    best, ms, results = autotune.tune_streamlines(ctx, job, d_seeds, space=space)
+    assert tuple(best) in space and len(results) == len(space) and ms > 0
+    assert (job.steps_per_visit, job.tail_items, job.refill_lanes, job.quad_items) == tuple(best)
+    again, _, cached = autotune.tune_streamlines(ctx, job, d_seeds, space=space)
+    assert tuple(again) == tuple(best) and cached == []
+    rafi.sl_trace_job(ctx, job, d_seeds)
+    torch.cuda.synchronize()
+    o = orc.streamlines_brute(field, grid, seeds, max_steps=600)
+    assert np.array_equal(ep.cpu().numpy().view(np.uint32), o["endpoint"].view(np.uint32))
+    assert np.array_equal(st.cpu().numpy(), o["steps"])
+    assert np.array_equal(why.cpu().numpy(), o["reason"])
+    ctx.close()
