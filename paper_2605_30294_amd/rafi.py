@@ -384,7 +384,11 @@ def sl_job(field4: torch.Tensor, grid, endpoint, steps, reason=None, h=0.25, max
            quad_items=SL_QUAD_ITEMS) -> SLJob:
     """field4: the packed [n, n, n, 4] field of sl_pack, or the [n, n, n, 3] field
     itself (read unpadded). counters: optional int64 device tensor [2]
-    (cross-brick forwards, same-brick forwards)."""
+    (cross-brick forwards, same-brick forwards). Schedule (results do not
+    depend on it): steps_per_visit caps the RK4 steps per brick visit (0: none),
+    uncapped in launches over at most tail_items particles; refill_lanes > 0
+    runs persistent waves; launches over at most quad_items particles (with
+    refill_lanes 0) run four lanes per particle (0: never)."""
     stride = int(field4.shape[-1])
     if field4.dim() != 4 or stride not in (3, 4) or not field4.is_contiguous():
         raise ValueError("field must be a contiguous [n, n, n, 3] or [n, n, n, 4] tensor")
