@@ -181,7 +181,11 @@ def _dptr(t: torch.Tensor | None):
     if t is None:
         return None
     assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA/HIP tensors"
-    return C.c_void_p(t.data_ptr())
+    p = t.data_ptr()
+    if p == 0 and t.numel() == 0:
+        # torch gives empty tensors no address; a view of a non-empty storage still has one
+        p = t.untyped_storage().data_ptr() + t.storage_offset() * t.element_size()
+    return C.c_void_p(p)
 
 
 def _stream(stream=None):
@@ -420,9 +424,10 @@ def sl_trace(field4: torch.Tensor, grid, seeds: torch.Tensor, h=0.25, max_steps=
     N = seeds.shape[0]
     if ctx is None:
         ctx = Context(int(np.prod(grid)), SL_ITEM_BYTES, max(N, 1))
-    endpoint = torch.empty((N, 3), dtype=torch.float32, device=dev)
-    steps = torch.empty(N, dtype=torch.int32, device=dev)
-    reason = torch.empty(N, dtype=torch.int32, device=dev)
+    # at least one row, so that the output pointers are valid also for no seeds
+    endpoint = torch.empty((max(N, 1), 3), dtype=torch.float32, device=dev)[:N]
+    steps = torch.empty(max(N, 1), dtype=torch.int32, device=dev)[:N]
+    reason = torch.empty(max(N, 1), dtype=torch.int32, device=dev)[:N]
     counters = torch.zeros(2, dtype=torch.int64, device=dev)
     job = sl_job(field4, grid, endpoint, steps, reason, h, max_steps, steps_per_visit, counters, tail_items,
                  refill_lanes, quad_items)

@@ -239,3 +239,27 @@ def test_streamline_autotune(orc, tmp_path, monkeypatch):
     assert np.array_equal(st.cpu().numpy(), o["steps"])
     assert np.array_equal(why.cpu().numpy(), o["reason"])
     ctx.close()
+
+
+@pytest.mark.parametrize("quad", [0, rafi.SL_QUAD_ITEMS])
+@pytest.mark.parametrize("N", [0, 1, 65])
+def test_empty_and_few_seeds(orc, N, quad):
+    """No seeds: one forward step with nothing in it, no launch. One seed and
+    a ragged 65 (a partial quad workgroup and wave): the oracle's results."""
+    dev = device()
+    n = 32
+    field = W.abc_field(n)
+    seeds = W.streamline_seeds(max(N, 1), n, seed=9)[:N]
+    announce(f"sl few seeds N={N} quad={quad}")
+    f4 = rafi.sl_pack(torch.from_numpy(field).to(dev))
+    r = rafi.sl_trace(f4, (2, 2, 2), torch.from_numpy(seeds).to(dev).reshape(N, 3), max_steps=400,
+                      steps_per_visit=16, quad_items=quad)
+    torch.cuda.synchronize()
+    assert r["endpoint"].shape == (N, 3) and r["steps"].shape == (N,)
+    if N == 0:
+        assert r["forwarded"] == 0 and r["rounds"] == 1
+        return
+    o = orc.streamlines_brute(field, (2, 2, 2), seeds, max_steps=400)
+    assert np.array_equal(r["endpoint"].cpu().numpy().view(np.uint32), o["endpoint"].view(np.uint32))
+    assert np.array_equal(r["steps"].cpu().numpy(), o["steps"])
+    assert np.array_equal(r["reason"].cpu().numpy(), o["reason"])
