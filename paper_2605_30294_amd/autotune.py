@@ -79,8 +79,8 @@ def tune_batch(batch, volumes, image, space=None, reps=2, use_cache=True):
 
 # (steps_per_visit, tail_items, refill_lanes, quad_items); the quad launches
 # apply only with refill_lanes 0
-STREAMLINE_SPACE = ([(c, t, r, 0) for c in (32, 64, 128, 256, 512) for t in (0, 65536) for r in (8, 16, 32)]
-                    + [(c, t, 0, q) for c in (32, 64, 128, 256, 512) for t in (0, 65536)
+STREAMLINE_SPACE = ([(c, t, r, 0) for c in (32, 64, 96, 128, 256, 512) for t in (0, 65536) for r in (8, 16, 32)]
+                    + [(c, t, 0, q) for c in (32, 64, 96, 128, 256, 512) for t in (0, 65536)
                        for q in (0, 65536, 98304, 131072, 262144)])
 
 
