@@ -96,7 +96,9 @@ def streamline_job(args, dev):
     reason = torch.empty(N, dtype=torch.int32, device=dev)
     counters = torch.zeros(2, dtype=torch.int64, device=dev)
     quad = rafi.SL_QUAD_ITEMS if args.quad_items is None else args.quad_items
-    job = rafi.sl_job(f4, grid, endpoint, steps, reason, h, max_steps, args.steps_per_visit, counters,
+    # the schedule sweep runs on the chosen layout (under "auto", the unpadded one)
+    first = layouts["unpadded" if args.field_layout == "auto" else args.field_layout]
+    job = rafi.sl_job(first, grid, endpoint, steps, reason, h, max_steps, args.steps_per_visit, counters,
                       args.tail_items, args.refill_lanes, quad)
     tuned = None
     if args.autotune or args.steps_per_visit < 0:      # sweep the schedule (results do not depend on it)
