@@ -41,7 +41,8 @@ enum {
     RAFI_ERR_OVERFLOW = -4,   /* emits beyond the slot range were dropped (Sec. 3.3) */
     RAFI_ERR_BAD_DEST = -5,   /* slots carried a destination outside {-1} U [0, n_domains) */
     RAFI_ERR_MAX_ROUNDS = -6, /* a driver loop hit its round limit with items still alive */
-    RAFI_ERR_STATE = -7       /* call not valid in the context's current state */
+    RAFI_ERR_STATE = -7,      /* call not valid in the context's current state */
+    RAFI_ERR_TOO_LARGE = -8   /* problem larger than a fixed buffer; nothing was done */
 };
 
 /* Destination of an item that leaves the system (the -1 of Sec. 3.2). */
@@ -233,6 +234,27 @@ int rafi_split_set_variant(int32_t variant);
 int rafi_multisplit(const void *items, const int32_t *dest, uint64_t n, uint32_t item_bytes,
                     int32_t n_domains, void *out, uint64_t *offsets, uint64_t *summary,
                     void *workspace, uint64_t workspace_bytes, void *hip_stream);
+
+/*
+ * The stateless split for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): rafi_multisplit with the workspace taken from a fixed 32 MiB
+ * buffer of the library's own (static device memory, one copy per device,
+ * held until the process ends). Arguments, layout, results and errors as
+ * rafi_multisplit; it calls no allocating routine. Problems whose workspace
+ * (rafi_multisplit_workspace) exceeds 32 MiB return RAFI_ERR_TOO_LARGE
+ * before anything is enqueued. Every n fits for n_domains <= 2045, and
+ * n <= 2^24 fits for every n_domains; D = 2046 and more fail above about
+ * 2^25 slots (the table holds up to 4096 tiles of D + 2 counts). hip_stream (or the
+ * null stream) must belong to the current device, else RAFI_ERR_ARG. The
+ * buffer needs no clearing: every split writes each workspace entry it reads.
+ * All calls on one device share the buffer: calls that overlap on that
+ * device (different streams, or host threads) race and must be ordered by
+ * the caller; calls in one stream are ordered already.
+ */
+int rafi_multisplit_noalloc(const void *items, const int32_t *dest, uint64_t n, uint32_t item_bytes,
+                            int32_t n_domains, void *out, uint64_t *offsets, uint64_t *summary,
+                            void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Emission-absorption volume ray march over bricked domains (the

@@ -3,6 +3,7 @@
 // device interface, call forwardRays() between kernel launches).
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "internal.h"
@@ -225,6 +226,41 @@ int round_finish(rafi_ctx *c, uint64_t *total)
 
 using namespace rafi;
 
+namespace {
+// Workspace of rafi_multisplit_noalloc: file-scope device memory, one copy
+// per device, held until the process ends. In host code the array's name is
+// not a device address; only the address hipGetSymbolAddress returns (kept
+// per device in g_scratch) may reach a kernel or a copy.
+constexpr uint64_t kNoAllocScratchBytes = 32ull << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+// The scratch address on the device of stream s, which must be the current
+// device. Looked up once per device, on the first call there.
+int noalloc_scratch(hipStream_t s, void **out)
+{
+    int dev = 0;
+    RAFI_HIP_CHECK(hipGetDevice(&dev));
+    if (s) {
+        hipDevice_t sd = 0;
+        RAFI_HIP_CHECK(hipStreamGetDevice(s, &sd));
+        if (sd != dev) return RAFI_ERR_ARG;
+    }
+    if (dev < 0 || dev >= kMaxDevices) return RAFI_ERR_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        RAFI_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return RAFI_ERR_HIP;
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return RAFI_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char *rafi_strerror(int code)
@@ -238,6 +274,7 @@ const char *rafi_strerror(int code)
     case RAFI_ERR_BAD_DEST: return "slots with an invalid destination were dropped";
     case RAFI_ERR_MAX_ROUNDS: return "round limit reached with items still alive";
     case RAFI_ERR_STATE: return "call not valid in the current state";
+    case RAFI_ERR_TOO_LARGE: return "problem larger than the fixed scratch buffer";
     default: return "unknown error";
     }
 }
@@ -458,6 +495,23 @@ int rafi_multisplit(const void *items, const int32_t *dest, uint64_t n, uint32_t
     if (workspace_bytes < p.bytes) return RAFI_ERR_ARG;
     return split_run(p, items, dest, out, offsets, summary, nullptr, 1, workspace,
                      static_cast<hipStream_t>(hip_stream));
+}
+
+int rafi_multisplit_noalloc(const void *items, const int32_t *dest, uint64_t n, uint32_t item_bytes,
+                            int32_t n_domains, void *out, uint64_t *offsets, uint64_t *summary, void *hip_stream)
+{
+    if (!valid_shape(n_domains, item_bytes) || n >= (1ull << 32) || !offsets || !summary) return RAFI_ERR_ARG;
+    if (n && (!items || !dest || !out)) return RAFI_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(items) | reinterpret_cast<uintptr_t>(out) |
+         reinterpret_cast<uintptr_t>(dest)) & 15)
+        return RAFI_ERR_ARG;
+    const SplitPlan p = split_plan(n, n_domains, item_bytes);
+    if (p.bytes > kNoAllocScratchBytes) return RAFI_ERR_TOO_LARGE;
+    const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    void *ws = nullptr;
+    const int rc = noalloc_scratch(s, &ws);
+    if (rc != RAFI_OK) return rc;
+    return split_run(p, items, dest, out, offsets, summary, nullptr, 1, ws, s);
 }
 
 }  // extern "C"

@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "librafi.so")
 RAFI_OK = 0
 RAFI_DONE = -1
 RAFI_POISON = -2
-ERR_ARG, ERR_OOM, ERR_HIP, ERR_OVERFLOW, ERR_BAD_DEST, ERR_MAX_ROUNDS, ERR_STATE = range(-1, -8, -1)
+ERR_ARG, ERR_OOM, ERR_HIP, ERR_OVERFLOW, ERR_BAD_DEST, ERR_MAX_ROUNDS, ERR_STATE, ERR_TOO_LARGE = range(-1, -9, -1)
 SLOTS_ORDERED, SLOTS_APPEND = 0, 1
 EA_ITEM_BYTES = 16
 DT_ITEM_BYTES = 48
@@ -125,6 +125,7 @@ _SIGS = {
     "rafi_multisplit_workspace": ([C.c_uint64, C.c_int32, C.c_uint32, _U64P], C.c_int),
     "rafi_split_set_variant": ([C.c_int32], C.c_int),
     "rafi_multisplit": ([_P, _P, C.c_uint64, C.c_uint32, C.c_int32, _P, _P, _P, _P, C.c_uint64, _P], C.c_int),
+    "rafi_multisplit_noalloc": ([_P, _P, C.c_uint64, C.c_uint32, C.c_int32, _P, _P, _P, _P], C.c_int),
     "rafi_ea_raygen": ([_P, C.POINTER(EAJob)], C.c_int),
     "rafi_ea_march": ([_P, C.POINTER(EAJob)], C.c_int),
     "rafi_ea_render": ([_P, C.POINTER(EAJob), C.c_int32, C.POINTER(C.c_int32)], C.c_int),
@@ -312,6 +313,19 @@ def multisplit(items: torch.Tensor, dest: torch.Tensor, n_domains: int, out=None
     _check(lib().rafi_multisplit(_dptr(items), _dptr(dest), n, S, n_domains, _dptr(out), _dptr(offsets),
                                  _dptr(summary), _dptr(workspace), workspace.numel(), _stream(stream)),
            "rafi_multisplit")
+    return out, offsets, summary
+
+
+def multisplit_noalloc(items: torch.Tensor, dest: torch.Tensor, n_domains: int, out: torch.Tensor,
+                       offsets: torch.Tensor, summary: torch.Tensor, stream=None):
+    """The stateless forward step with the library's fixed device scratch
+    buffer as its workspace (rafi_multisplit_noalloc): the caller passes
+    every output (out like items, offsets int64 [D+1], summary int64 [4])
+    and nothing is allocated. Results as multisplit()."""
+    n = dest.numel()
+    S = items.element_size() * (items.shape[1] if items.dim() > 1 else 1)
+    _check(lib().rafi_multisplit_noalloc(_dptr(items), _dptr(dest), n, S, n_domains, _dptr(out), _dptr(offsets),
+                                         _dptr(summary), _stream(stream)), "rafi_multisplit_noalloc")
     return out, offsets, summary
 
 

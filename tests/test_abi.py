@@ -49,7 +49,7 @@ def test_argument_validation_without_device():
     # misaligned pointers are rejected before any launch
     assert L.rafi_multisplit(C.c_void_p(8), C.c_void_p(16), 10, 16, 4, C.c_void_p(32), C.c_void_p(64),
                              C.c_void_p(128), C.c_void_p(256), 1 << 20, None) == rafi.ERR_ARG
-    for code in range(0, -8, -1):
+    for code in range(0, -9, -1):
         assert rafi.strerror(code) != "unknown error"
     assert L.rafi_round(None, None, None) == rafi.ERR_ARG
     assert L.rafi_ea_render(None, None, 1, None) == rafi.ERR_ARG
@@ -64,6 +64,12 @@ def test_argument_validation_without_device():
     assert L.rafi_nb_splitters(None, 10, 4, None, None, None) == rafi.ERR_ARG
     assert L.rafi_nb_seed(None, None, None, 0) == rafi.ERR_ARG
     assert L.rafi_nb_step(None, None, None, None, None, None) == rafi.ERR_ARG
+    # the no-allocation split refuses problems beyond its fixed scratch buffer
+    # (checked before any device call) and misaligned pointers
+    assert L.rafi_multisplit_noalloc(C.c_void_p(256), C.c_void_p(512), 1 << 26, 32, 4096, C.c_void_p(1024),
+                                     C.c_void_p(2048), C.c_void_p(4096), None) == rafi.ERR_TOO_LARGE
+    assert L.rafi_multisplit_noalloc(C.c_void_p(8), C.c_void_p(16), 10, 16, 4, C.c_void_p(32), C.c_void_p(64),
+                                     C.c_void_p(128), None) == rafi.ERR_ARG
     assert L.rafi_split_set_variant(16) == rafi.ERR_ARG
     assert L.rafi_split_set_variant(-1) == rafi.ERR_ARG
 
