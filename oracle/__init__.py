@@ -82,7 +82,7 @@ def _declare(L):
     L.oracle_nb_seed.argtypes = [C.POINTER(NBParams), _p, _p, C.c_int64, _p, _p]
     L.oracle_nb_seed.restype = C.c_int
     L.oracle_nb_step.argtypes = [C.POINTER(NBParams), _p, _p, C.c_int64, _p, _p, C.c_uint64, _p, C.c_uint64, _p,
-                                 C.c_uint64, _p]
+                                 C.c_uint64, _p, _p]
     L.oracle_nb_step.restype = C.c_int
     L.oracle_philox4x32_10.argtypes = [_p, _p, _p]
     L.oracle_philox4x32_10.restype = None
@@ -376,8 +376,9 @@ def nb_seed(particles, K, cell_level=4, theta=0.5, eps=1e-3):
 
 def nb_step(queue, K, dt, cell_level=4, theta=0.5, eps=1e-3, log_cap=1 << 22):
     """One step of O8 on a particle queue. Returns the new queue, the four
-    rounds' per-domain counts (particle, virtual 1, request, virtual 2) and
-    the three exchange queues."""
+    rounds' per-domain counts (particle, virtual 1, request, virtual 2), the
+    three exchange queues and, per particle of the new queue, the sum of its
+    force terms' magnitudes per component (acc_mag, float64)."""
     q = np.array(queue, dtype=NB_PARTICLE, copy=True)
     D = len(K) - 1
     P = _nb_params(D, cell_level, dt, theta, eps)
@@ -388,11 +389,12 @@ def nb_step(queue, K, dt, cell_level=4, theta=0.5, eps=1e-3, log_cap=1 << 22):
     rr = np.zeros(cap1, dtype=np.int32)
     vp2 = np.zeros(log_cap, dtype=NB_VP)
     lens = np.zeros(3, dtype=np.uint64)
+    acc_mag = np.zeros((q.shape[0], 3), dtype=np.float64)
     rc = lib().oracle_nb_step(C.byref(P), _ptr(K), _ptr(q), q.shape[0], _ptr(rc_counts), _ptr(vp1), cap1,
-                              _ptr(rr), cap1, _ptr(vp2), log_cap, _ptr(lens))
+                              _ptr(rr), cap1, _ptr(vp2), log_cap, _ptr(lens), _ptr(acc_mag))
     if rc != 0:
         raise RuntimeError(f"oracle_nb_step failed: {rc}")
     n1, nr, n2 = (int(x) for x in lens)
     if n2 > log_cap:
         raise RuntimeError("second virtual-particle queue longer than log_cap")
-    return dict(queue=q, round_counts=rc_counts, vp1=vp1[:n1], rr=rr[:nr], vp2=vp2[:n2])
+    return dict(queue=q, round_counts=rc_counts, vp1=vp1[:n1], rr=rr[:nr], vp2=vp2[:n2], acc_mag=acc_mag)

@@ -1069,10 +1069,10 @@ int oracle_dt_render(const float *vol, const orc_dt_params *P, const orc_view *v
  *     accepts, and with the particles (size 0) of those it does not. The
  *     received nodes, in queue order, are the requester's remote list.
  *   - Force on a particle: the softened point-mass terms of its domain's
- *     other particles in key order, then of its remote list in order. This
- *     source sequence is cut into chunks of NB_CHUNK sources (the particle
- *     itself keeps its position in the sequence); each chunk's terms are
- *     added in order from zero, and the chunk sums are added in chunk order.
+ *     other particles in key order, then of its remote list in order, each
+ *     term evaluated and added in float64 (the section fixes no order and
+ *     no precision; this is the plain sum over that source sequence). The
+ *     float64 total, rounded to float32, is the stored acceleration.
  *   - Slots: the forward step keeps slot order within a destination (O1),
  *     and fan-out uses fixed slots: root s -> r at s (D-1) + k; a request at
  *     the slot of the root it answers; answers after the n1 slots of the
@@ -1083,8 +1083,6 @@ typedef struct {
     int32_t n_domains, cell_level;
     float dt, theta, eps;
 } orc_nb_params;
-
-#define NB_CHUNK 1024   /* sources per chunk of a particle's force sum */
 
 typedef struct {
     float pos[3], vel[3], acc[3], mass;
@@ -1143,16 +1141,19 @@ static float nb_wrap(float x)
 
 static uint32_t nb_key(const orc_nb_particle *p) { return oracle_morton30(p->pos[0], p->pos[1], p->pos[2]); }
 
-/* a += m (q - p) / (|q - p|^2 + eps^2)^(3/2), in this operation order */
-static void nb_term(const float p[3], const float q[3], float m, float eps2, float a[3])
+/* a += m (q - p) / (|q - p|^2 + eps^2)^(3/2), in float64; mag += |term|
+ * per component (the scale of the sum's rounding error, for tolerances) */
+static void nb_term(const float p[3], const float q[3], float m, double eps2, double a[3], double mag[3])
 {
-    const float dx = q[0] - p[0], dy = q[1] - p[1], dz = q[2] - p[2];
-    const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
-    const float inv = 1.0f / sqrtf(r2);
-    const float s = m * (inv * inv * inv);
-    a[0] = fmaf(s, dx, a[0]);
-    a[1] = fmaf(s, dy, a[1]);
-    a[2] = fmaf(s, dz, a[2]);
+    const double dx = (double)q[0] - p[0], dy = (double)q[1] - p[1], dz = (double)q[2] - p[2];
+    const double r2 = dx * dx + dy * dy + dz * dz + eps2;
+    const double s = m / (r2 * sqrt(r2));
+    a[0] += s * dx;
+    a[1] += s * dy;
+    a[2] += s * dz;
+    mag[0] += fabs(s * dx);
+    mag[1] += fabs(s * dy);
+    mag[2] += fabs(s * dz);
 }
 
 /* size^2 < theta^2 d^2, d = distance from c to the box [lo, hi] */
@@ -1217,14 +1218,17 @@ static int cmp_key_index(const void *a, const void *b)
  * accelerations updated. Logs (any may be NULL): counts per domain of the
  * four forward rounds in the order particle, virtual 1, request, virtual 2
  * (round_counts[4][D]); the three exchange queues (vp1 [cap_vp1], rr
- * [cap_rr], vp2 [cap_vp2]) and their lengths (lens[3]).
+ * [cap_rr], vp2 [cap_vp2]) and their lengths (lens[3]); per particle of the
+ * new queue, the sum of the force terms' magnitudes per component
+ * (acc_mag[n][3], float64).
  */
 int oracle_nb_step(const orc_nb_params *P, const uint32_t *K, orc_nb_particle *queue, int64_t n,
                    uint64_t *round_counts, orc_nb_vp *vp1_log, uint64_t cap_vp1, int32_t *rr_log,
-                   uint64_t cap_rr, orc_nb_vp *vp2_log, uint64_t cap_vp2, uint64_t *lens)
+                   uint64_t cap_rr, orc_nb_vp *vp2_log, uint64_t cap_vp2, uint64_t *lens, double *acc_mag)
 {
     const int32_t D = P->n_domains, L = P->cell_level;
-    const float dt = P->dt, hdt = 0.5f * P->dt, eps2 = P->eps * P->eps;
+    const float dt = P->dt, hdt = 0.5f * P->dt;
+    const double eps2 = (double)P->eps * P->eps;
     const size_t nn = (size_t)(n ? n : 1);
     orc_nb_particle *tmp = (orc_nb_particle *)malloc(sizeof(orc_nb_particle) * nn);
     int32_t *dest = (int32_t *)calloc(nn, sizeof(int32_t));
@@ -1381,30 +1385,20 @@ int oracle_nb_step(const orc_nb_params *P, const uint32_t *K, orc_nb_particle *q
     if (vp2_log) for (int64_t i = 0; i < (int64_t)o2[D] && (uint64_t)i < cap_vp2; ++i) vp2_log[i] = v2[i];
     if (lens) { lens[0] = (uint64_t)n1; lens[1] = (uint64_t)nr; lens[2] = o2[D]; }
 
-    /* 7. forces (own domain, then the remote list, in chunks) and the second half-kick */
-    for (int32_t r = 0; r < D; ++r) {
-        const int64_t nloc = (int64_t)(offs[r + 1] - offs[r]), len = nloc + (int64_t)(o2[r + 1] - o2[r]);
+    /* 7. forces (own domain's other particles, then the remote list) and the second half-kick */
+    for (int32_t r = 0; r < D; ++r)
         for (int64_t i = (int64_t)offs[r]; i < (int64_t)offs[r + 1]; ++i) {
-            float a[3] = {0.0f, 0.0f, 0.0f};
-            for (int64_t c0 = 0; c0 < len; c0 += NB_CHUNK) {
-                float A[3] = {0.0f, 0.0f, 0.0f};
-                for (int64_t k = c0; k < c0 + NB_CHUNK && k < len; ++k) {
-                    if (k < nloc) {
-                        const int64_t j = (int64_t)offs[r] + k;
-                        if (j != i) nb_term(queue[i].pos, queue[j].pos, queue[j].mass, eps2, A);
-                    } else {
-                        const int64_t v = (int64_t)o2[r] + (k - nloc);
-                        nb_term(queue[i].pos, v2[v].pos, v2[v].mass, eps2, A);
-                    }
-                }
-                for (int c = 0; c < 3; ++c) a[c] = a[c] + A[c];
-            }
+            double a[3] = {0.0, 0.0, 0.0}, mag[3] = {0.0, 0.0, 0.0};
+            for (int64_t j = (int64_t)offs[r]; j < (int64_t)offs[r + 1]; ++j)
+                if (j != i) nb_term(queue[i].pos, queue[j].pos, queue[j].mass, eps2, a, mag);
+            for (int64_t v = (int64_t)o2[r]; v < (int64_t)o2[r + 1]; ++v)
+                nb_term(queue[i].pos, v2[v].pos, v2[v].mass, eps2, a, mag);
+            if (acc_mag) for (int c = 0; c < 3; ++c) acc_mag[3 * i + c] = mag[c];
             for (int c = 0; c < 3; ++c) {
-                queue[i].acc[c] = a[c];
-                queue[i].vel[c] = fmaf(hdt, a[c], queue[i].vel[c]);
+                queue[i].acc[c] = (float)a[c];
+                queue[i].vel[c] = fmaf(hdt, queue[i].acc[c], queue[i].vel[c]);
             }
         }
-    }
     free(tmp); free(dest); free(counts); free(offs); free(keys); free(idx); free(cells); free(cell_first); free(root);
     free(lo); free(hi); free(rsize); free(vo); free(v1); free(vdest); free(o1); free(acc); free(ro); free(rq);
     free(rdest); free(orr); free(aoff); free(wo); free(v2); free(wdest); free(o2);

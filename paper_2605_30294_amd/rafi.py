@@ -658,6 +658,15 @@ class NBody:
                          self.vp1.data_ptr() if log_vp1 else None, self.vp1.shape[0] if log_vp1 else 0)
         _check(lib().rafi_nb_seed(self.P.handle, C.byref(self.job), _dptr(particles), n), "rafi_nb_seed")
 
+    def reseed(self, particles: torch.Tensor):
+        """Round 0 again (rafi_nb_seed): the particle queue becomes these
+        particles, in any order, grouped by their owning domains."""
+        assert particles.dtype == torch.float32 and particles.dim() == 2 and particles.shape[1] == 10
+        assert particles.shape[0] <= self.n
+        self._seed_src = particles   # read by the seed kernel on the library's stream
+        _check(lib().rafi_nb_seed(self.P.handle, C.byref(self.job), _dptr(particles), particles.shape[0]),
+               "rafi_nb_seed")
+
     def step(self, dt: float | None = None):
         """One step; returns (round counts [4, D], queue sizes [3])."""
         if dt is not None:
