@@ -26,12 +26,21 @@ DONE = -1
 SL_LIVE, SL_STAGNANT, SL_EXITED, SL_MAXSTEPS = 0, 1, 2, 3
 
 
+# RAFI_ORACLE_SANITIZE=1 builds a separate copy with AddressSanitizer and
+# UndefinedBehaviorSanitizer (host code only; load it with libasan preloaded).
+_SANITIZE = os.environ.get("RAFI_ORACLE_SANITIZE") == "1"
+if _SANITIZE:
+    _LIB = os.path.join(_HERE, "librafi_oracle_asan.so")
+
+
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (no fast-math, no contraction)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-               "-fno-fast-math", "-Wall", "-Wextra", "-Wno-unused-parameter",
-               "-o", _LIB + ".tmp", _SRC, "-lm"]
+               "-fno-fast-math", "-Wall", "-Wextra", "-Wno-unused-parameter"]
+        if _SANITIZE:
+            cmd += ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer"]
+        cmd += ["-o", _LIB + ".tmp", _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -95,6 +104,10 @@ def _declare(L):
     L.oracle_multisplit.restype = C.c_int
     L.oracle_trilinear.argtypes = [_p, C.c_int32, C.c_float, C.c_float, C.c_float]
     L.oracle_trilinear.restype = C.c_double
+    L.oracle_tri_vec3.argtypes = [_p, C.c_int32, C.c_float, C.c_float, C.c_float, _p]
+    L.oracle_tri_vec3.restype = None
+    L.oracle_dt_density.argtypes = [_p, C.c_int32, C.c_float, C.c_float, C.c_float]
+    L.oracle_dt_density.restype = C.c_float
     L.oracle_ea_render.argtypes = [_p, C.POINTER(EAParams), _p, C.c_int32, _p, _p, _p, C.c_int32,
                                    _p, _p, C.c_uint64, _p, _p, C.c_int32]
     L.oracle_ea_render.restype = C.c_int
@@ -145,6 +158,22 @@ def multisplit(items: np.ndarray, dest: np.ndarray, n_domains: int):
 def trilinear(volume: np.ndarray, q) -> float:
     vol = np.ascontiguousarray(volume, dtype=np.float64)
     return lib().oracle_trilinear(_ptr(vol), vol.shape[0], float(q[0]), float(q[1]), float(q[2]))
+
+
+def tri_vec3(field: np.ndarray, q) -> np.ndarray:
+    """The RK4 sampler (O4): float32 trilinear of an [n, n, n, 3] field
+    (x fastest, 3 components per voxel) at q, clamp-to-edge."""
+    f = np.ascontiguousarray(field, dtype=np.float32)
+    out = np.zeros(3, dtype=np.float32)
+    lib().oracle_tri_vec3(_ptr(f), f.shape[0], *(float(np.float32(c)) for c in q), _ptr(out))
+    return out
+
+
+def dt_density(volume: np.ndarray, q) -> np.ndarray:
+    """The delta-tracking density sampler (O7): float32 trilinear of an
+    [n, n, n] float32 volume (x fastest) at q, clamp-to-edge."""
+    v = np.ascontiguousarray(volume, dtype=np.float32)
+    return np.float32(lib().oracle_dt_density(_ptr(v), v.shape[0], *(float(np.float32(c)) for c in q)))
 
 
 def _ea_params(n, grid, dt, c):

@@ -552,6 +552,13 @@ static void tri_vec3(const float *field, int32_t n, const float q[3], float out[
 #undef FV
 }
 
+/* Exposed for the sampler pins (linear fields, clamp band, component order). */
+void oracle_tri_vec3(const float *field, int32_t n, float qx, float qy, float qz, float *out)
+{
+    const float q[3] = {qx, qy, qz};
+    tri_vec3(field, n, q, out);
+}
+
 /* One RK4 step from p into pn. */
 static void rk4_step(const float *field, int32_t n, float h, const float p[3], float pn[3])
 {
@@ -864,6 +871,13 @@ static float dt_density(const float *vol, int32_t n, const float q[3])
     const float x00 = lerpf(b[0], b[1], f[0]), x01 = lerpf(b[sy], b[sy + 1], f[0]);
     const float x10 = lerpf(b[sz], b[sz + 1], f[0]), x11 = lerpf(b[sz + sy], b[sz + sy + 1], f[0]);
     return lerpf(lerpf(x00, x01, f[1]), lerpf(x10, x11, f[1]), f[2]);
+}
+
+/* Exposed for the sampler pins (linear data, clamp band, strides). */
+float oracle_dt_density(const float *vol, int32_t n, float qx, float qy, float qz)
+{
+    const float q[3] = {qx, qy, qz};
+    return dt_density(vol, n, q);
 }
 
 static void dt_isotropic(const orc_dt_params *P, orc_dt_item *it)

@@ -120,3 +120,79 @@ def test_round_invariants(orc):
     assert np.array_equal(b[:, 0] + 2 * (b[:, 1] + 2 * b[:, 2]), doms)
     # at most one shadow ray per scattering event: nothing written past max_bounce events
     assert np.all(np.isfinite(r["contrib"])) and np.all(r["contrib"] >= 0)
+
+
+def _linear_volume_f32(n, a, b, c, d):
+    # dyadic slopes and voxel centres: every voxel value is exact in float32
+    x = np.arange(n, dtype=np.float64) + 0.5
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    v = a * X + b * Y + c * Z + d
+    assert np.array_equal(v.astype(np.float32).astype(np.float64), v)
+    return v.astype(np.float32)
+
+
+def test_density_sampler_linear_data_strides_and_clamp(orc):
+    """The delta-tracking medium's float32 trilinear sampler reproduces a
+    linear density with distinct per-axis slopes (so a swapped stride or
+    axis fails), within float32 rounding, inside the centre lattice and in
+    the half-voxel clamp band at every face, where it takes the value at the
+    clamped coordinate."""
+    n = 12
+    a, b, c, d = 0.75, -1.25, 2.5, 40.0
+    vol = _linear_volume_f32(n, a, b, c, d)
+    scale = abs(d) + (abs(a) + abs(b) + abs(c)) * n
+    tol = 8 * np.finfo(np.float32).eps * scale
+    rng = np.random.default_rng(5)
+    pts = list(rng.uniform(0.5, n - 0.5, (300, 3)).astype(np.float32))
+    band = []
+    for ax in range(3):
+        for lo in (True, False):
+            for _ in range(20):
+                q = rng.uniform(0.5, n - 0.5, 3).astype(np.float32)
+                q[ax] = np.float32(rng.uniform(0.0, 0.5) if lo else rng.uniform(n - 0.5, n))
+                band.append(q)
+    band += [np.float32([0.0, 0.0, 0.0]), np.float32([n - 1e-3] * 3), np.float32([0.25, n - 0.25, 6.0]),
+             np.float32([-2.0, 5.5, n + 3.0])]
+    for q in pts + band:
+        qc = np.clip(q.astype(np.float64), 0.5, n - 0.5)
+        exact = a * qc[0] + b * qc[1] + c * qc[2] + d
+        assert abs(float(orc.dt_density(vol, q)) - exact) <= tol, (q, exact)
+    # voxel centres give the voxel values exactly
+    for (i, j, k) in [(0, 0, 0), (3, 7, 11), (11, 11, 11), (5, 0, 9), (11, 0, 4)]:
+        assert orc.dt_density(vol, (i + 0.5, j + 0.5, k + 0.5)) == vol[k, j, i]
+    # a stride error would move the value by far more than the tolerance
+    assert abs(b - c) * 1.0 > 100 * tol
+
+
+def test_collision_probability_in_a_linear_medium(orc):
+    """Non-uniform medium: density a + b x + c z (a ramp in x and z), +z rays.
+    A path leaves the cube without a real collision with probability
+    exp(-kappa * integral of the clamped density along its ray). Checked per
+    band of pixel columns (x), so that swapping the sampler's axes or
+    strides, which flattens or reverses the x dependence, fails."""
+    n, w, kappa = 16, 64, 0.02
+    a, b, c = 0.5, 0.25, 0.125
+    x = np.arange(n, dtype=np.float64) + 0.5
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    vol = (a + b * X + c * Z).astype(np.float32)
+    smax = kappa * float(vol.max()) * 1.5
+    views = W.plusz_view(n, w, w)
+    seeds = 8
+    miss = np.zeros((w, w))                   # [py, px]
+    for seed in range(seeds):
+        r = orc.dt_render(vol, (2, 2, 2), views, kappa, smax, 1.0, (0.0, 0.0, -1.0), 1.0, 1, 200 + seed)
+        miss += (r["contrib"][:, 0] == 0).reshape(w, w)
+    px = (np.arange(w) + 0.5) * (n / w)
+    xc = np.clip(px, 0.5, n - 0.5)
+    zint = 0.5 * 0.5 + ((n - 0.5) ** 2 - 0.25) / 2 + 0.5 * (n - 0.5)   # integral of clamp(z) over [0, n]
+    p_col = np.exp(-kappa * ((a + b * xc) * n + c * zint))
+    bands = 4
+    for k in range(bands):
+        cols = slice(k * w // bands, (k + 1) * w // bands)
+        trials = seeds * w * (w // bands)
+        m = miss[:, cols].sum() / trials
+        p = p_col[cols].mean()
+        se = math.sqrt(p * (1 - p) / trials)
+        assert abs(m - p) < 5 * se, (k, m, p, se)
+    # the bands differ by far more than their standard errors
+    assert p_col[: w // bands].mean() - p_col[-w // bands:].mean() > 40 * se

@@ -112,3 +112,39 @@ def test_one_step_per_round_equals_until_exit(orc):
     assert np.array_equal(a["steps"], b["steps"])
     assert np.array_equal(a["reason"], b["reason"])
     assert b["rounds"] == int(a["steps"].max()) + 1
+
+
+def test_vector_sampler_linear_field_components_and_clamp(orc):
+    """The RK4 sampler's float32 trilinear of a 3-component field reproduces a
+    linear field whose components have distinct gradients, within float32
+    rounding: inside the centre lattice and in the half-voxel clamp band at
+    every face, where each component takes its value at the clamped
+    coordinate (per axis: clamp q to [1/2, n - 1/2])."""
+    n = 10
+    G = np.array([[0.5, -0.25, 1.0], [-1.5, 0.75, 0.125], [2.0, 1.25, -0.5]])
+    b = np.array([30.0, -20.0, 10.0])
+    x = np.arange(n, dtype=np.float64) + 0.5
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    f = np.empty((n, n, n, 3), dtype=np.float64)
+    for c in range(3):
+        f[..., c] = b[c] + G[c, 0] * X + G[c, 1] * Y + G[c, 2] * Z
+    assert np.array_equal(f.astype(np.float32).astype(np.float64), f)   # dyadic: exact in float32
+    f = f.astype(np.float32)
+    tol = 8 * np.finfo(np.float32).eps * (np.abs(b) + np.abs(G).sum(1) * n)
+    rng = np.random.default_rng(6)
+    pts = list(rng.uniform(0.5, n - 0.5, (300, 3)).astype(np.float32))
+    for ax in range(3):
+        for lo in (True, False):
+            for _ in range(20):
+                q = rng.uniform(0.5, n - 0.5, 3).astype(np.float32)
+                q[ax] = np.float32(rng.uniform(0.0, 0.5) if lo else rng.uniform(n - 0.5, n))
+                pts.append(q)
+    pts += [np.float32([0.0, 0.0, 0.0]), np.float32([n - 1e-3] * 3), np.float32([0.49, 9.51, 0.01])]
+    for q in pts:
+        qc = np.clip(q.astype(np.float64), 0.5, n - 0.5)
+        exact = b + G @ qc
+        got = orc.tri_vec3(f, q).astype(np.float64)
+        assert np.all(np.abs(got - exact) <= tol), (q, got, exact)
+    # voxel centres give the voxel's three components exactly
+    for (i, j, k) in [(0, 0, 0), (9, 9, 9), (2, 7, 4)]:
+        assert np.array_equal(orc.tri_vec3(f, (i + 0.5, j + 0.5, k + 0.5)), f[k, j, i])
