@@ -88,14 +88,14 @@ typedef struct rafi_device_view {
     unsigned long long *append;       /* device counter of slots taken by rafi_emit (append mode) */
 } rafi_device_view;
 
-typedef struct rafi_stats {
+typedef struct rafi_stats_t {
     uint64_t rounds;     /* rafi_round calls since creation */
     uint64_t forwarded;  /* items delivered to a domain queue, summed over rounds */
     uint64_t done;       /* slots that carried RAFI_DONE */
     uint64_t bad_dest;   /* slots with an invalid destination (poison included) */
     uint64_t dropped;    /* emits to a slot outside [0, n_slots) */
     uint64_t last_total; /* total returned by the last rafi_round */
-} rafi_stats;
+} rafi_stats_t;
 
 /*
  * Create a context for n_domains domains of items of item_bytes bytes, with
@@ -115,7 +115,10 @@ void rafi_destroy(rafi_ctx *ctx);
 int rafi_resize(rafi_ctx *ctx, uint64_t capacity);
 
 /* Stream for all later work on this context (a hipStream_t, passed as void*).
- * The stream must outlive its use by the context. */
+ * The stream must outlive its use by the context. The paper's library runs on
+ * one stream and leaves several asynchronous streams to future work (Sec. 7);
+ * here each context has one stream of the caller's choice, so contexts on
+ * different streams (and the batched form) can overlap. */
 int rafi_set_stream(rafi_ctx *ctx, void *hip_stream);
 
 /* Debug mode: when on, every rafi_begin/rafi_round pre-fills the output
@@ -177,8 +180,10 @@ int rafi_round(rafi_ctx *ctx, uint64_t *counts, uint64_t *total);
  * offsets into offsets_dst (device, n_domains + 1 uint64); either may be NULL. */
 int rafi_copy_queue(const rafi_ctx *ctx, void *items_dst, uint64_t *offsets_dst);
 
-/* Cumulative statistics (host copy, updated by rafi_round). */
-int rafi_get_stats(const rafi_ctx *ctx, rafi_stats *out);
+/* Cumulative statistics (host copy, updated by rafi_round): the counts that
+ * Sec. 3.3 and 4.2 leave to the application (dropped emits, invalid
+ * destinations) besides the per-round totals of Sec. 4.2.3. */
+int rafi_stats(const rafi_ctx *ctx, rafi_stats_t *out);
 
 /*
  * Per-phase GPU time, measured with HIP events recorded on the context stream

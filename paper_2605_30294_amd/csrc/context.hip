@@ -465,7 +465,7 @@ int rafi_get_profile(rafi_ctx *c, rafi_profile *out)
     return RAFI_OK;
 }
 
-int rafi_get_stats(const rafi_ctx *c, rafi_stats *out)
+int rafi_stats(const rafi_ctx *c, rafi_stats_t *out)
 {
     if (!c || !out) return RAFI_ERR_ARG;
     *out = c->stats;

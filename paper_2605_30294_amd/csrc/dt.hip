@@ -351,10 +351,14 @@ int rafi_dt_render(rafi_ctx *c, const rafi_dt_job *job, int32_t max_rounds, int3
     int rc = rafi_dt_raygen(c, job);
     if (rc != RAFI_OK) return rc;
     const uint64_t paths = n_paths_of(job);
-    // each trace launch is enqueued one step ahead of the host (run_rounds)
+    // Each trace launch is enqueued one step ahead of the host (run_rounds).
+    // bound (the slots just split) only bounds the queue length, so the
+    // output is clamped to the capacity: a queue that really needs more than
+    // capacity slots has its excess emits dropped and counted
+    // (RAFI_ERR_OVERFLOW), while the grid still covers every queued item.
+    const uint64_t cap = c->cap;
     auto launch = [&](uint64_t bound) -> int {
-        if (2 * bound > c->cap) return RAFI_ERR_ARG;
-        const int orc = rafi_open(c, 2 * bound, RAFI_SLOTS_ORDERED);
+        const int orc = rafi_open(c, std::min<uint64_t>(2 * bound, cap), RAFI_SLOTS_ORDERED);
         if (orc != RAFI_OK) return orc;
         rafi_device_view v;
         rafi_view(c, &v);
@@ -367,7 +371,8 @@ int rafi_dt_render(rafi_ctx *c, const rafi_dt_job *job, int32_t max_rounds, int3
         RAFI_LAUNCH_CHECK();
         return RAFI_OK;
     };
-    rc = run_rounds(c, max_rounds, rounds, nullptr, launch, [](uint64_t n) { return 2 * n; });
+    rc = run_rounds(c, max_rounds, rounds, nullptr, launch,
+                    [cap](uint64_t n) { return std::min<uint64_t>(2 * n, cap); });
     if (rc == RAFI_OK && job->image) {
         if (paths)
             hipLaunchKernelGGL(dt_resolve_kernel, dim3((uint32_t)((paths + 255) / 256)), dim3(256), 0, c->stream,

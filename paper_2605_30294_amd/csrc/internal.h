@@ -97,7 +97,7 @@ struct rafi_ctx {
     uint64_t wave_slots = 0;            // n_slots of the last rafi_begin (item ids stay below it)
     uint32_t tile_items = 256, n_tiles = 0;
     int debug = 0;
-    rafi_stats stats{};
+    rafi_stats_t stats{};
     // profiling: event pairs waiting to be resolved
     int prof_on = 0;
     rafi_profile prof{};

@@ -118,7 +118,7 @@ _SIGS = {
     "rafi_round": ([_P, _P, _U64P], C.c_int),
     "rafi_emit_bulk": ([_P, _P, _P, C.c_uint64], C.c_int),
     "rafi_copy_queue": ([_P, _P, _P], C.c_int),
-    "rafi_get_stats": ([_P, C.POINTER(Stats)], C.c_int),
+    "rafi_stats": ([_P, C.POINTER(Stats)], C.c_int),
     "rafi_set_profiling": ([_P, C.c_int32], C.c_int),
     "rafi_get_profile": ([_P, C.POINTER(Profile)], C.c_int),
     "rafi_strerror": ([C.c_int], C.c_char_p),
@@ -278,7 +278,7 @@ class Context:
 
     def stats(self) -> dict:
         s = Stats()
-        _check(lib().rafi_get_stats(self._h, C.byref(s)), "rafi_get_stats")
+        _check(lib().rafi_stats(self._h, C.byref(s)), "rafi_stats")
         return {k: getattr(s, k) for k, _ in Stats._fields_}
 
 
@@ -334,7 +334,9 @@ def multisplit_noalloc(items: torch.Tensor, dest: torch.Tensor, n_domains: int, 
 def ea_job(volume: torch.Tensor, grid, views_dev: torch.Tensor, n_views: int, width: int, height: int,
            image: torch.Tensor, tau=None, klast=None, dt=0.5, c=0.025, kfirst=None, visit_log=None,
            visit_count=None, emit_mode=SLOTS_ORDERED) -> EAJob:
-    n = volume.shape[0]
+    n = volume.shape[0] if volume.dim() == 3 else -1
+    if volume.dim() != 3 or tuple(volume.shape) != (n, n, n) or volume.dtype != torch.float32:
+        raise ValueError(f"volume must be a float32 [n, n, n] tensor, got {volume.dtype} {tuple(volume.shape)}")
     stride = 0 if visit_log is None else visit_log.shape[1]
     return EAJob(_dptr(volume), _dptr(views_dev), _dptr(image), _dptr(tau), _dptr(klast), _dptr(kfirst),
                  _dptr(visit_log), _dptr(visit_count), n, (C.c_int32 * 3)(*[int(g) for g in grid]), n_views,
@@ -389,6 +391,8 @@ def ea_render(volume: torch.Tensor, grid, views: np.ndarray, dt=0.5, c=0.025, ct
 
 def sl_pack(field: torch.Tensor) -> torch.Tensor:
     n = field.shape[0]
+    if field.dim() != 4 or tuple(field.shape) != (n, n, n, 3) or field.dtype != torch.float32:
+        raise ValueError(f"field must be a float32 [n, n, n, 3] tensor, got {field.dtype} {tuple(field.shape)}")
     f4 = torch.empty((n, n, n, 4), dtype=torch.float32, device=field.device)
     _check(lib().rafi_sl_pack(_dptr(field), n, _dptr(f4), _stream()), "rafi_sl_pack")
     return f4
@@ -408,8 +412,11 @@ def sl_job(field4: torch.Tensor, grid, endpoint, steps, reason=None, h=0.25, max
     runs persistent waves; launches over at most quad_items particles (with
     refill_lanes 0) run four lanes per particle (0: never)."""
     stride = int(field4.shape[-1])
-    if field4.dim() != 4 or stride not in (3, 4) or not field4.is_contiguous():
-        raise ValueError("field must be a contiguous [n, n, n, 3] or [n, n, n, 4] tensor")
+    n = field4.shape[0]
+    if field4.dim() != 4 or stride not in (3, 4) or tuple(field4.shape[:3]) != (n, n, n) \
+            or field4.dtype != torch.float32 or not field4.is_contiguous():
+        raise ValueError("field must be a contiguous float32 [n, n, n, 3] or [n, n, n, 4] tensor, got "
+                         f"{field4.dtype} {tuple(field4.shape)}")
     return SLJob(_dptr(field4), _dptr(endpoint), _dptr(steps), _dptr(reason), _dptr(counters), field4.shape[0],
                  (C.c_int32 * 3)(*[int(g) for g in grid]), float(h), int(max_steps), int(steps_per_visit),
                  int(tail_items), int(refill_lanes), stride, int(quad_items))
@@ -459,18 +466,22 @@ class EARender(torch.autograd.Function):
 
     @staticmethod
     def forward(fctx, volume, grid, views, dt, c, rafi_ctx, bwd_tile_items=0):
-        out = ea_render(volume.contiguous(), grid, views, dt=dt, c=c, ctx=rafi_ctx, want_tau=True)
+        # the job holds the raw address of the contiguous volume: keep that
+        # tensor (a copy when the input is a permuted or sliced view) alive
+        # until the backward has read it
+        vol = volume.detach().contiguous()
+        out = ea_render(vol, grid, views, dt=dt, c=c, ctx=rafi_ctx, want_tau=True)
         out["job"].bwd_tile_items = int(bwd_tile_items)
         fctx.keep = (out["ctx"], out["job"], out["views_dev"], out["tau"], out["klast"], out["kfirst"],
-                     out["image"])
-        fctx.save_for_backward(volume)
+                     out["image"], vol)
+        fctx.save_for_backward(volume)   # autograd's check against in-place changes
         return out["image"]
 
     @staticmethod
     def backward(fctx, grad_image):
-        (volume,) = fctx.saved_tensors
-        rctx, job, _views, _tau, _klast, _kfirst, _image = fctx.keep
-        grad = torch.zeros_like(volume)
+        fctx.saved_tensors
+        rctx, job, _views, _tau, _klast, _kfirst, _image, vol = fctx.keep
+        grad = torch.zeros_like(vol, memory_format=torch.contiguous_format)
         ea_backward_job(rctx, job, grad_image.contiguous().to(torch.float32), grad)
         return grad, None, None, None, None, None, None
 

@@ -90,7 +90,7 @@ def test_struct_layouts_match_header(tmp_path):
     import subprocess
     structs = {"rafi_device_view": rafi.DeviceView, "rafi_ea_job": rafi.EAJob, "rafi_sl_job": rafi.SLJob,
                "rafi_dt_job": rafi.DTJob, "rafi_nb_job": rafi.NBJob, "rafi_ortho_view": rafi.ViewRec, "rafi_ea_scene": rafi.SceneRec,
-               "rafi_batch_tuning": rafi.BatchTuning, "rafi_stats": rafi.Stats, "rafi_profile": rafi.Profile}
+               "rafi_batch_tuning": rafi.BatchTuning, "rafi_stats_t": rafi.Stats, "rafi_profile": rafi.Profile}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "rafi.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -119,3 +119,24 @@ def test_python_layer_names():
     assert rafi.trace_streamlines is rafi.sl_trace
     assert callable(rafi.multisplit)
     assert issubclass(rafi.EARender, __import__("torch").autograd.Function)
+
+
+def test_binding_rejects_bad_volume_and_field_shapes():
+    """The job builders check shape and dtype before any pointer reaches the
+    library: a non-cubic or non-float32 volume or field would make the
+    kernels read n^3 voxels past the allocation."""
+    import torch
+    views = None
+    img = torch.empty(4)
+    for vol in (torch.zeros(4, 4, 2), torch.zeros(4, 4, 4, dtype=torch.float16), torch.zeros(4, 4),
+                torch.zeros(4, 4, 4, dtype=torch.float64)):
+        with pytest.raises(ValueError):
+            rafi.ea_job(vol, (1, 1, 1), views, 1, 2, 2, img)
+    ep, st = torch.empty(1, 3), torch.empty(1, dtype=torch.int32)
+    for f in (torch.zeros(8, 8, 4, 3), torch.zeros(8, 8, 8, 2), torch.zeros(8, 8, 8, 3, dtype=torch.float16),
+              torch.zeros(8, 8, 8)):
+        with pytest.raises(ValueError):
+            rafi.sl_job(f, (1, 1, 1), ep, st)
+    for f in (torch.zeros(8, 8, 4, 3), torch.zeros(8, 8, 8, 3, dtype=torch.float64)):
+        with pytest.raises(ValueError):
+            rafi.sl_pack(f)

@@ -165,3 +165,31 @@ def test_adjoint_scale_sampled(orc):
         fd = (Lp - Lm) / (2 * eps)
         gv = g.reshape(-1)[v]
         assert abs(gv - fd) <= 1e-3 * abs(fd) + 1e-6 * np.abs(g).max(), (v, gv, fd)
+
+
+def test_gradient_of_a_permuted_volume(orc):
+    """A non-contiguous volume (a permuted view of the leaf tensor): the render
+    works on a contiguous copy that must outlive the forward; the gradient
+    reaches the leaf through the permutation and matches the float64 oracle.
+    Allocations between forward and backward would reuse a freed copy."""
+    dev = device()
+    n, grid = 32, (2, 2, 2)
+    vol_np = W.blob_volume(n, 65)
+    tgt_np = W.blob_volume(n, 66)
+    views = W.random_views(2, n, 32, 32, seed=67)
+    announce("adjoint of a permuted volume")
+    leaf = torch.from_numpy(np.ascontiguousarray(vol_np.transpose(2, 1, 0))).to(dev).requires_grad_(True)
+    vol = leaf.permute(2, 1, 0)                      # equals vol_np, not contiguous
+    assert not vol.is_contiguous()
+    with torch.no_grad():
+        target = rafi.ea_render(torch.from_numpy(tgt_np).to(dev), grid, views, c=C32)["image"]
+    img = rafi.ea_render_differentiable(vol, grid, views, c=C32)
+    junk = [torch.full((n, n, n), 7.0, device=dev) for _ in range(4)]   # takes freed blocks, if any
+    loss = ((img - target) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    del junk
+    g = leaf.grad.permute(2, 1, 0).cpu().numpy().astype(np.float64)
+    L64, g64, _ = orc.ea_loss_grad(vol_np, grid, views, target.cpu().numpy().astype(np.float64), c=C32)
+    assert abs(float(loss) - L64) <= 1e-4 * abs(L64)
+    assert _rel_l2(g, g64) <= REL_L2, _rel_l2(g, g64)

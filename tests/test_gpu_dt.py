@@ -129,3 +129,47 @@ def test_capacity_is_checked():
         rafi.dt_trace(ctx, job)
     assert e.value.code == rafi.ERR_ARG
     ctx.close()
+
+
+@pytest.mark.parametrize("B", [1, 2])
+def test_render_dense_medium_few_bounces(orc, B):
+    """The pipelined render at rafi_dt_capacity's own sizing, 2 paths (B + 1)
+    slots, in a dense medium where most paths collide at once: the
+    look-ahead launch only bounds the queue length, so it must not refuse a
+    queue that fits. Contributions match the oracle."""
+    dev = device()
+    n, grid = 32, (2, 2, 2)
+    vol_np = W.blob_volume(n, 93)
+    views = W.plusz_view(n, 48, 48)
+    kappa = 0.6
+    smax = float(np.float32(kappa * float(vol_np.max()) * 1.05))
+    announce(f"dt render dense B={B}")
+    r = rafi.dt_render(torch.from_numpy(vol_np).to(dev), grid, views, kappa, smax, 0.95, (0.0, 0.6, 0.8), 1.0, B,
+                       11)
+    torch.cuda.synchronize()
+    st = r["ctx"].stats()
+    assert st["dropped"] == 0 and st["bad_dest"] == 0
+    o = orc.dt_render(vol_np, grid, views, kappa, smax, 0.95, (0.0, 0.6, 0.8), 1.0, B, 11)
+    assert r["rounds"] == o["rounds"]
+    # with two bounces the queue exceeds a quarter of the capacity in some
+    # round, where a launch sized for twice the split slots would not fit
+    if B == 2:
+        assert int(o["round_counts"].sum(axis=1).max()) > rafi.dt_capacity(48 * 48, B) // 4
+    ok, i, rr = rel_close(r["contrib"].cpu().numpy().ravel(), o["contrib"].ravel(), RTOL, ATOL)
+    assert ok, (i, rr)
+    r["ctx"].close()
+
+
+def test_render_overflow_is_reported():
+    """A context too small for the render's fan-out: the excess emits are
+    dropped and counted, and the render reports RAFI_ERR_OVERFLOW."""
+    dev = device()
+    n, grid = 32, (2, 2, 2)
+    vol = torch.from_numpy(W.blob_volume(n, 5)).to(dev)
+    views = W.plusz_view(n, 32, 32)
+    ctx = rafi.Context(8, rafi.DT_ITEM_BYTES, 32 * 32)          # room for the raygen only
+    with pytest.raises(rafi.RafiError) as e:
+        rafi.dt_render(vol, grid, views, 0.05, 1.0, 0.8, (0.0, 0.0, -1.0), 1.0, 2, 1, ctx=ctx)
+    assert e.value.code == rafi.ERR_OVERFLOW
+    assert ctx.stats()["dropped"] > 0
+    ctx.close()
