@@ -37,7 +37,7 @@ def build(force: bool = False) -> str:
     """Compile the oracle with gcc (no fast-math, no contraction)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-               "-fno-fast-math", "-Wall", "-Wextra", "-Wno-unused-parameter"]
+               "-fno-fast-math", "-fopenmp", "-Wall", "-Wextra", "-Wno-unused-parameter"]
         if _SANITIZE:
             cmd += ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer"]
         cmd += ["-o", _LIB + ".tmp", _SRC, "-lm"]
@@ -55,6 +55,21 @@ def lib():
         _lib = C.CDLL(build())
         _declare(_lib)
     return _lib
+
+
+def default_threads() -> int:
+    """Threads for a timed oracle run: the CPUs this process may use, at most 16."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def set_threads(n: int) -> None:
+    """Run the per-item loops on n OpenMP threads (1: sequential, the
+    default). Results are the same bits for every n."""
+    lib().oracle_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().oracle_get_threads())
 
 
 class EAParams(C.Structure):
@@ -102,6 +117,10 @@ def _declare(L):
     L.oracle_dt_render.restype = C.c_int
     L.oracle_multisplit.argtypes = [C.c_uint64, C.c_uint32, _p, _p, C.c_int32, _p, _p, _p, _p, _p]
     L.oracle_multisplit.restype = C.c_int
+    L.oracle_set_threads.argtypes = [C.c_int32]
+    L.oracle_set_threads.restype = None
+    L.oracle_get_threads.argtypes = []
+    L.oracle_get_threads.restype = C.c_int32
     L.oracle_trilinear.argtypes = [_p, C.c_int32, C.c_float, C.c_float, C.c_float]
     L.oracle_trilinear.restype = C.c_double
     L.oracle_tri_vec3.argtypes = [_p, C.c_int32, C.c_float, C.c_float, C.c_float, _p]

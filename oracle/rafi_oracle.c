@@ -5,7 +5,11 @@
  * statement of what the forwarding path computes. Only the test suite, the
  * smoke check and the benchmark's CPU-baseline leg load it; the product
  * library never calls it, and it shares no source, header, table or constant
- * with the HIP path. Single-threaded.
+ * with the HIP path. Single-threaded by default; oracle_set_threads(n)
+ * runs the items of one (domain, round) on n OpenMP threads for timing.
+ * Every item's work reads only shared inputs and writes only its own output
+ * slot and its own per-item results, so the results are the same bits for
+ * any thread count.
  *
  * Precision: floating point that decides an integer (sample positions, which
  * brick owns a point, RK4 trajectories that decide routing and step counts) is
@@ -27,6 +31,12 @@
 #include <string.h>
 
 #define ORC_DONE (-1)
+
+/* Threads for the per-item loops (1: plain sequential loops). */
+static int g_threads = 1;
+
+void oracle_set_threads(int32_t n) { g_threads = n < 1 ? 1 : n; }
+int32_t oracle_get_threads(void) { return g_threads; }
 
 /* ======================================================================
  * O1. The forward step = a stable counting sort by destination.
@@ -321,10 +331,12 @@ int oracle_ea_render(const double *vol, const orc_ea_params *P, const orc_view *
         rounds++;
         if (total == 0) break;
 
-        /* Domain kernels: walk domains in order, items in queue order. */
-        n_out = 0;
+        /* Domain kernels: walk domains in order, items in queue order; the
+         * item at queue position i emits into output slot i. */
         for (int32_t d = 0; d < D; ++d) {
-            for (uint64_t i = offs[d]; i < offs[d + 1]; ++i) {
+            const int64_t b = (int64_t)offs[d], end = (int64_t)offs[d + 1];
+#pragma omp parallel for schedule(dynamic, 64) num_threads(g_threads) if (g_threads > 1)
+            for (int64_t i = b; i < end; ++i) {
                 orc_ray it = Q[i];
                 const orc_view *v;
                 int32_t px, py;
@@ -332,9 +344,8 @@ int oracle_ea_render(const double *vol, const orc_ea_params *P, const orc_view *
                 float org[3];
                 ray_origin(v, px, py, org);
                 int32_t e = ea_advance(vol, P, v, org, &it, d);
-                O[n_out] = it;
-                odest[n_out] = e;
-                n_out++;
+                O[i] = it;
+                odest[i] = e;
                 if (e == ORC_DONE) {
                     if (image) image[it.ray] = it.I;
                     if (tau_out) tau_out[it.ray] = it.tau;
@@ -342,6 +353,7 @@ int oracle_ea_render(const double *vol, const orc_ea_params *P, const orc_view *
                 }
             }
         }
+        n_out = total;
     }
     if (queue_len) *queue_len = qlen;
     free(O); free(Q); free(odest); free(counts); free(offs); free(nvis);
@@ -365,6 +377,7 @@ int oracle_ea_brute(const double *vol, const orc_ea_params *P, const orc_view *v
     int64_t n_rays = 0;
     for (int32_t i = 0; i < n_views; ++i) n_rays += (int64_t)views[i].width * views[i].height;
     if (!ray_ids) n_ids = n_rays;
+#pragma omp parallel for schedule(dynamic, 256) num_threads(g_threads) if (g_threads > 1)
     for (int64_t q = 0; q < n_ids; ++q) {
         int64_t r = ray_ids ? ray_ids[q] : q;
         const orc_view *v;
@@ -668,15 +681,16 @@ int oracle_streamlines(const float *field, const orc_sl_params *P, const float *
             }
         rounds++;
         if (total == 0) break;
-        n_out = 0;
+        /* the particle at queue position i emits into output slot i */
         for (int32_t d = 0; d < D; ++d) {
-            for (uint64_t i = offs[d]; i < offs[d + 1]; ++i) {
+            const int64_t b = (int64_t)offs[d], end = (int64_t)offs[d + 1];
+#pragma omp parallel for schedule(dynamic, 64) num_threads(g_threads) if (g_threads > 1)
+            for (int64_t i = b; i < end; ++i) {
                 orc_particle it = Q[i];
                 int32_t why = ORC_SL_LIVE;
                 int32_t e = sl_advance(field, P, &it, d, steps_per_visit, &why);
-                O[n_out] = it;
-                odest[n_out] = e;
-                n_out++;
+                O[i] = it;
+                odest[i] = e;
                 if (e == ORC_DONE) {
                     memcpy(endpoint + 3 * (size_t)it.id, it.p, sizeof(it.p));
                     steps[it.id] = it.steps;
@@ -684,6 +698,7 @@ int oracle_streamlines(const float *field, const orc_sl_params *P, const float *
                 }
             }
         }
+        n_out = total;
     }
     if (queue_len) *queue_len = qlen;
     free(O); free(Q); free(odest); free(counts); free(offs); free(nvis);
@@ -697,6 +712,7 @@ int oracle_streamlines_brute(const float *field, const orc_sl_params *P, const f
                              int64_t n_seeds, float *endpoint, int32_t *steps, int32_t *reason,
                              int32_t *visit_log, int32_t visit_stride)
 {
+#pragma omp parallel for schedule(dynamic, 64) num_threads(g_threads) if (g_threads > 1)
     for (int64_t i = 0; i < n_seeds; ++i) {
         float p[3];
         memcpy(p, seeds + 3 * i, sizeof(p));
@@ -1040,10 +1056,14 @@ int oracle_dt_render(const float *vol, const orc_dt_params *P, const orc_view *v
         rounds++;
         if (total == 0) break;
         if (rounds >= max_rounds) { rounds = -1; break; }
-        /* domain kernels, fan-out 2 */
-        for (int32_t e = 0; e < D; ++e)
-            for (uint64_t i = offs[e]; i < offs[e + 1]; ++i)
+        /* domain kernels, fan-out 2 (each (path, event) contribution is
+         * written by the one item that finishes it) */
+        for (int32_t e = 0; e < D; ++e) {
+            const int64_t b = (int64_t)offs[e], end = (int64_t)offs[e + 1];
+#pragma omp parallel for schedule(dynamic, 64) num_threads(g_threads) if (g_threads > 1)
+            for (int64_t i = b; i < end; ++i)
                 dt_visit(vol, P, e, queue[i], contrib, &slots[2 * i], &sdest[2 * i]);
+        }
         n_slots = 2 * total;
     }
     if (queue_len) *queue_len = qlen;

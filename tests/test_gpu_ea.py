@@ -179,3 +179,26 @@ def test_adjoint_scale_forward_sampled(orc):
     ok, i, rr = rel_close(img[ids], o["image"], RTOL, ATOL)
     assert ok, (ids[i], img[ids[i]], o["image"][i], rr)
     assert 3 <= r["rounds"] <= 12
+
+
+def test_adjoint_scale_forward_exact(orc):
+    """128^3, 4x4x4 bricks, 64 views of 256x256 (4.2M rays): every round's
+    per-domain counts and queue (ray ids in order), and every ray's last
+    sample index, equal the oracle's bit for bit; every integral and optical
+    depth within 1e-5 relative (oracle threaded for speed: its results do
+    not depend on the thread count)."""
+    dev = device()
+    vol = W.blob_volume(128, W.SEED_ADJ_VOLUME)
+    views = W.random_views(64, 128, 256, 256)
+    announce("ea 128^3 x 64 views forward, exact")
+    g = _stepwise(torch.from_numpy(vol).to(dev), (4, 4, 4), views)
+    r = rafi.ea_render(torch.from_numpy(vol).to(dev), (4, 4, 4), views, c=C32, want_tau=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(r["image"].cpu().numpy(), g["image"]) and r["rounds"] == len(g["counts"])
+    assert np.array_equal(r["klast"].cpu().numpy(), g["klast"])
+    orc.set_threads(orc.default_threads())
+    try:
+        o = orc.ea_render(vol, (4, 4, 4), views, c=C32, queue_cap=1 << 24)
+    finally:
+        orc.set_threads(1)
+    _compare(g, o)

@@ -162,6 +162,35 @@ def test_full_cfg1_sampled(orc):
     assert np.array_equal(out, why == 2)
 
 
+def test_full_cfg1_exact(orc):
+    """256^3 ABC, 4x4x4 bricks, all 1M seeds, RK4 h = 0.25, <= 2000 steps, under
+    the benchmark's schedule (96 steps per visit, lane quads for launches over
+    at most 98304 particles, unpadded field). The pipelined job's endpoints,
+    step counts and reasons, and the stepwise run's per-round counts and
+    queues, equal the oracle's bit for bit (oracle threaded for speed: its
+    results do not depend on the thread count)."""
+    dev = device()
+    n, N, grid = 256, 1 << 20, (4, 4, 4)
+    field = W.abc_field(n)
+    seeds = W.streamline_seeds(N, n)
+    announce("sl cfg1 full, exact")
+    r = rafi.sl_trace(torch.from_numpy(field).to(dev), grid, torch.from_numpy(seeds).to(dev), steps_per_visit=96)
+    torch.cuda.synchronize()
+    ep, st, why = r["endpoint"].cpu().numpy(), r["steps"].cpu().numpy(), r["reason"].cpu().numpy()
+    r["ctx"].close()
+    g = _stepwise(field, grid, seeds, steps_per_visit=96, packed=False)
+    assert np.array_equal(g["endpoint"].view(np.uint32), ep.view(np.uint32))
+    orc.set_threads(orc.default_threads())
+    try:
+        o = orc.streamlines(field, grid, seeds, steps_per_visit=96, queue_cap=1 << 23)
+    finally:
+        orc.set_threads(1)
+    assert g["counts"].shape[0] == r["rounds"] == o["rounds"]
+    _compare(g, o)
+    assert np.array_equal(ep.view(np.uint32), o["endpoint"].view(np.uint32))
+    assert np.array_equal(st, o["steps"]) and np.array_equal(why, o["reason"])
+
+
 @pytest.mark.parametrize("n,packed", [(564, False), (512, True)])
 def test_large_field_global_loads(orc, n, packed):
     """Fields of more than 2^31 - 1 bytes (564^3 x 12 B, 512^3 x 16 B) are
