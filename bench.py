@@ -39,9 +39,12 @@ if ROOT not in sys.path:
 
 METRIC = "forwarded items/s + ray samples/s on 1 MI355X, % HBM peak; batched/adjoint vs plain"
 HBM_PEAK_GBS = 8000.0
-# float32 VALU peak without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-# = 39.3e12 lane-ops/s, i.e. 78.6 TFLOP/s counting an FMA as two flops.
-ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+# float32 vector peak, published: 157.3 TFLOP/s = 256 CUs x 128 float32
+# lanes per clock (packed pairs on 64 lanes) x 2 (FMA) x 2.4 GHz.
+ALU_PEAK_TFLOPS = 256 * 128 * 2 * 2.4e9 / 1e12
+# The ceiling without packed math (this build emits no packed float32
+# instructions): 256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz = 78.6 TFLOP/s.
+ALU_UNPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # Algorithmic float32 flops of one RK4 step (FMA = 2): per trilinear vec3
 # sample 2 subs for the weights x 3 axes + 7 lerps (sub + fma) x 3 components
 # = 69; four samples = 276; three stage offsets (3 fma) = 18; the weighted
@@ -174,6 +177,8 @@ def streamline_job(args, dev):
                roofline={"kernel": kernels + ", RK4 brick march: every domain launch", "bound": "alu",
                          "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
                          "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
+                         "peak_unpacked": round(ALU_UNPACKED_TFLOPS, 1),
+                         "frac_unpacked": round(achieved / ALU_UNPACKED_TFLOPS, 4),
                          "traffic": rk4_traffic(schedule, layout),
                          "traffic_unit": "bytes per launch (HBM side: FETCH_SIZE + WRITE_SIZE, calibrated)",
                          "per_launch_flops": flops_per_launch, "avg_launch_ms": round(avg_launch_ms, 4)})
@@ -181,34 +186,57 @@ def streamline_job(args, dev):
     return out, seeds_np
 
 
-def cpu_baseline(seeds_np, n_sample):
+def cpu_baseline(seeds_np, n_sample, n_single):
+    """The C oracle (untuned) on the host: the first n_sample seeds of the job
+    on all host cores (OpenMP over the items of each domain and round), and
+    the first n_single seeds on one core. Forwarded items as in `value`: the
+    oracle integrates until exit, so every forward after the seeding round
+    crosses a brick boundary."""
     import numpy as np
 
     import oracle
     from paper_2605_30294_amd import workloads as W
 
     field = W.abc_field(256)
-    sample = np.ascontiguousarray(seeds_np[:n_sample])
-    t = time.perf_counter()
-    r = oracle.streamlines(field, (4, 4, 4), sample, h=0.25, max_steps=2000)
-    dt = time.perf_counter() - t
-    fwd = int(r["round_counts"].sum())
-    log(f"cpu oracle: {n_sample} seeds in {dt:.2f} s, forwarded {fwd}")
-    return {"value": fwd / dt, "unit": "forwarded items/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_sample} of the 1M seeds, same field/grid/RK4 settings, "
-                      f"single-threaded C oracle ({dt:.1f} s, {int(r['steps'].sum())} RK4 steps)",
-            "rk4_steps_per_s": float(r["steps"].sum()) / dt}
+    host_cpus = len(os.sched_getaffinity(0))
+
+    def run(n, threads):
+        oracle.set_threads(threads)
+        try:
+            sample = np.ascontiguousarray(seeds_np[:n])
+            t = time.perf_counter()
+            r = oracle.streamlines(field, (4, 4, 4), sample, h=0.25, max_steps=2000)
+            return time.perf_counter() - t, int(r["round_counts"].sum()), int(r["steps"].sum())
+        finally:
+            oracle.set_threads(1)
+
+    threads = oracle.default_threads()
+    dt, fwd, rk4 = run(n_sample, threads)
+    log(f"cpu oracle: {n_sample} seeds on {threads} threads ({host_cpus} host CPUs) in {dt:.2f} s, "
+        f"forwarded {fwd}")
+    dt1, fwd1, rk41 = run(n_single, 1)
+    log(f"cpu oracle: {n_single} seeds on 1 thread in {dt1:.2f} s, forwarded {fwd1}")
+    sample = "all 1M seeds" if n_sample == len(seeds_np) else f"first {n_sample} of the 1M seeds"
+    return {"value": fwd / dt, "unit": "forwarded items/s", "cores": threads, "kind": "oracle",
+            "sample": f"{sample}, same field/grid/RK4 settings, C oracle with OpenMP over the items of each "
+                      f"domain and round on {threads} threads ({dt:.1f} s, {rk4} RK4 steps)",
+            "host_cpus": host_cpus, "rk4_steps_per_s": rk4 / dt,
+            "single_thread": {"value": fwd1 / dt1, "unit": "forwarded items/s", "cores": 1,
+                              "sample": f"first {n_single} of the 1M seeds ({dt1:.1f} s)"}}
 
 
-def split_microbench(dev, reps):
+def split_microbench(dev, reps, S=32):
+    """64M items of S bytes (32: an id and 7 float32 words; 44: the paper's
+    ray size, the same with 10 words) over 1024 destinations, uniform and
+    Zipf; every scatter shape, then the best one timed."""
     import numpy as np
     import torch
 
     from paper_2605_30294_amd import rafi
     from paper_2605_30294_amd import workloads as W
 
-    N, D, S = 1 << 26, 1024, 32
-    items = torch.from_numpy(W.split_items(N).view(np.int32)).to(dev)
+    N, D = 1 << 26, 1024
+    items = torch.from_numpy(W.split_items(N, S // 4).view(np.int32)).to(dev)
     res = {}
     ctx = rafi.Context(D, S, N)
 
@@ -240,7 +268,7 @@ def split_microbench(dev, reps):
                      "frac_hbm": alg / (split_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "scatter_GBps": alg / (scat_ms * 1e-3) / 1e9, "shape": best,
                      "shape_ms": {k: round(v, 4) for k, v in shapes.items()}}
-        log(f"split {dist}: {split_ms:.3f} ms ({res[dist]['GBps']:.0f} GB/s algorithmic), scatter {scat_ms:.3f} ms, "
+        log(f"split {dist} S={S}: {split_ms:.3f} ms ({res[dist]['GBps']:.0f} GB/s algorithmic), scatter {scat_ms:.3f} ms, "
             f"shapes {res[dist]['shape_ms']}")
         del dest
     ctx.close()
@@ -549,7 +577,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-seeds", type=int, default=262144)
+    ap.add_argument("--cpu-seeds", type=int, default=1 << 20,
+                    help="seeds of the job the oracle runs on all host cores for cpu_baseline")
+    ap.add_argument("--cpu-seeds-single", type=int, default=65536,
+                    help="seeds the oracle runs on one core (cpu_baseline.single_thread)")
     ap.add_argument("--only", default=None,
                     choices=["streamlines", "split", "split-domains", "ea", "adjoint", "batched", "dt", "nbody",
                              "copy"],
@@ -613,12 +644,13 @@ def main():
     extras = {}
     if not args.no_extras:
         extras["multisplit_64M_x32B_1024dest"] = split_microbench(dev, reps=20)
+        extras["multisplit_64M_x44B_1024dest"] = split_microbench(dev, reps=20, S=44)
         extras["ea_forward"] = ea_forward(dev, reps=5)
         extras["adjoint_vs_forward"] = ea_adjoint(dev, reps=3)
         extras["batched_vs_plain"] = batched(dev, reps=2)
         extras["delta_tracking"] = delta_tracking(dev, reps=3)
         extras["nbody_exchange"] = nbody_exchange(dev, reps=3)
-    cpu = None if args.no_cpu else cpu_baseline(seeds_np, args.cpu_seeds)
+    cpu = None if args.no_cpu else cpu_baseline(seeds_np, args.cpu_seeds, args.cpu_seeds_single)
 
     value = sl["forwarded"] / (sl["ms"] * 1e-3)
     line = {
