@@ -499,7 +499,12 @@ __global__ void __launch_bounds__(kNBThreads) nb_domain_wave_kernel(const NBPart
 // order, then its remote list) are cut into chunks of kForceChunk; workgroup
 // (tile, chunk) adds one chunk's terms in order from zero for the tile's
 // particles (the self term masked, as above) and stores the chunk sum;
-// nb_fold_kernel then adds a particle's chunk sums in chunk order.
+// nb_fold_kernel then adds a particle's chunk sums in chunk order. The
+// inverse distance is the hardware reciprocal square root (about 1 ulp):
+// a float32 sum in any order differs from the exact force by rounding of the
+// order of the terms' magnitudes times a few 1e-7, and the pair loop is bound
+// by instruction issue, where a correctly rounded root and division cost
+// about 25 instructions per pair.
 constexpr uint32_t kForceChunk = 1024;
 
 __global__ void __launch_bounds__(kNBThreads) nb_force_chunk_kernel(const NBParticle *__restrict__ q,
@@ -542,7 +547,7 @@ __global__ void __launch_bounds__(kNBThreads) nb_force_chunk_kernel(const NBPart
             const float4 sv = src[k2];
             const float dx = sv.x - p[0], dy = sv.y - p[1], dz = sv.z - p[2];
             const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmaf_rn(dx, dx, eps2)));
-            const float inv = 1.0f / sqrtf(r2);
+            const float inv = __builtin_amdgcn_rsqf(r2);
             const float f = sv.w * (inv * inv * inv);
             const float sc = __int_as_float(__float_as_int(f) & -(int32_t)(k2 != self));
             A[0] = __fmaf_rn(sc, dx, A[0]);
