@@ -44,7 +44,7 @@ __device__ inline V3 load_voxel(const typename Voxel<FW>::type *__restrict__ f, 
 // RK4 stages and steps usually fall in the same cell (a step moves a particle
 // by a fraction of a voxel), and then no memory is touched. Reuse is exact.
 struct CellCache {
-    int32_t base = -1;  // linear index of corner (i0, j0, k0), -1 = empty
+    int32_t base = -1;  // corner (i0, j0, k0): linear index, or byte offset (buffer loads); -1 = empty
     V3 c[8];
 };
 
@@ -134,15 +134,20 @@ __device__ inline void field_at_buf(const FieldBuf &fb, int32_t n, CellCache &cc
     w[0] = cell_axis(qx, hi, top, i0[0]);
     w[1] = cell_axis(qy, hi, top, i0[1]);
     w[2] = cell_axis(qz, hi, top, i0[2]);
-    const int32_t base = voxel_index(i0[0], i0[1], i0[2], n, n * n);
-    if (base != cc.base) {
-        const int32_t vo = base * (FW * 4);  // below 2^31: the launch checks the field size
+    // Byte offset of the corner voxel, which also names the cell. This path
+    // runs for fields of at most 2^31 - 1 bytes (checked at launch), so
+    // n <= 894 and the plane stride is at most 16 * 812^2 < 2^24 bytes: every
+    // factor of the full-rate 24-bit multiplies is below 2^24 and the sum
+    // below 2^31.
+    const int32_t vo = (int32_t)(__umul24((uint32_t)i0[0], FW * 4u) + __umul24((uint32_t)i0[1], (uint32_t)fb.row[1]) +
+                                 __umul24((uint32_t)i0[2], (uint32_t)fb.row[2]));
+    if (vo != cc.base) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             cc.c[2 * r] = load_voxel_buf<FW>(fb, vo, fb.row[r]);
             cc.c[2 * r + 1] = load_voxel_buf<FW>(fb, vo + FW * 4, fb.row[r]);
         }
-        cc.base = base;
+        cc.base = vo;
     }
     const V3 *c = cc.c;
 #define TRI(comp)                                                                                   \
@@ -207,6 +212,27 @@ __device__ inline int32_t owner_of(float x, float y, float z, const Geo &g)
     const int32_t by = (int32_t)floorf(y) / g.b1;
     const int32_t bz = (int32_t)floorf(z) / g.b2;
     return bx + g.g0 * (by + g.g1 * bz);
+}
+
+// Owner of a position just left the brick [lo, hi) of domain d. Each axis's
+// brick index moves by at most one when the position lies within one brick
+// edge of the old brick (a step is a fraction of a voxel in any field a brick
+// can hold without forwarding every step); the bounds are integers below
+// 2^24, so the float compares are exact and give floor(x) / b. Positions
+// farther away take the divisions. -1 outside the field (or NaN).
+__device__ inline int32_t owner_after_step(float x, float y, float z, const Geo &g, int32_t d, float lo0,
+                                           float hi0, float lo1, float hi1, float lo2, float hi2)
+{
+    const float fn = (float)g.n;
+    if (!(x >= 0.0f) || !(x < fn) || !(y >= 0.0f) || !(y < fn) || !(z >= 0.0f) || !(z < fn)) return -1;
+    const float b0 = (float)g.b0, b1 = (float)g.b1, b2 = (float)g.b2;
+    if (x >= lo0 - b0 && x < hi0 + b0 && y >= lo1 - b1 && y < hi1 + b1 && z >= lo2 - b2 && z < hi2 + b2) {
+        const int32_t cx = (int32_t)(x >= hi0) - (int32_t)(x < lo0);
+        const int32_t cy = (int32_t)(y >= hi1) - (int32_t)(y < lo1);
+        const int32_t cz = (int32_t)(z >= hi2) - (int32_t)(z < lo2);
+        return d + cx + g.g0 * (cy + g.g1 * cz);
+    }
+    return owner_of(x, y, z, g);
 }
 
 __global__ void pack_kernel(const float *__restrict__ f3, uint64_t nvox, float4 *__restrict__ f4)
@@ -316,7 +342,7 @@ advance_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids)
         z = nz;
         if (same) { why = RAFI_SL_STAGNANT; break; }
         const bool inside = x >= lo0 && x < hi0 && y >= lo1 && y < hi1 && z >= lo2 && z < hi2;
-        const int32_t e = inside ? d : owner_of(x, y, z, g);
+        const int32_t e = inside ? d : owner_after_step(x, y, z, g, d, lo0, hi0, lo1, hi1, lo2, hi2);
         if (e < 0) { why = RAFI_SL_EXITED; break; }
         if (steps >= job.max_steps) { why = RAFI_SL_MAXSTEPS; break; }
         if (e != d || taken >= cap) { dest = e; break; }
@@ -648,7 +674,7 @@ advance_persistent_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids
                 why = RAFI_SL_STAGNANT;
             } else {
                 const bool inside = nx >= lo0 && nx < hi0 && ny >= lo1 && ny < hi1 && nz >= lo2 && nz < hi2;
-                const int32_t e = inside ? d : owner_of(nx, ny, nz, g);
+                const int32_t e = inside ? d : owner_after_step(nx, ny, nz, g, d, lo0, hi0, lo1, hi1, lo2, hi2);
                 if (e < 0) why = RAFI_SL_EXITED;
                 else if (steps >= job.max_steps) why = RAFI_SL_MAXSTEPS;
                 else if (e != d || taken >= cap) dest = e;
