@@ -255,7 +255,7 @@ def split_microbench(dev, reps, S=32):
         ctx.emit_bulk(items, dest)
         # workgroup shape of the scatter: every shape gives the same bytes
         shapes = {}
-        for v in range(1, 16):
+        for v in range(1, 17):
             rafi.split_set_variant(v)
             shapes[v] = timed(3)[0]
         best = min(shapes, key=shapes.get)
@@ -622,7 +622,7 @@ def main():
         if args.only == "streamlines":
             res = streamline_job(args, dev)[0]
         elif args.only == "split":
-            res = split_microbench(dev, reps=args.steps)
+            res = {"32": split_microbench(dev, reps=args.steps), "44": split_microbench(dev, reps=args.steps, S=44)}
         elif args.only == "split-domains":
             res = split_domain_sweep(dev, reps=args.steps)
         elif args.only == "ea":

@@ -232,9 +232,12 @@ int rafi_multisplit_workspace(uint64_t n, int32_t n_domains, uint32_t item_bytes
  * as 0) use one workgroup per
  * CU over a group of tiles and write each destination's output in whole
  * 128-byte lines, keeping a run's unfinished line for the next chunk; 15
- * issues the next chunk's loads early. For tuning. Every shape gives the
- * same bytes. Not synchronised: set it while no split is being launched.
- * Outside 0..15: RAFI_ERR_ARG. */
+ * issues the next chunk's loads early; 16 (item sizes of 12 to 60 bytes
+ * that are not a multiple of 16, else as 0) uses one workgroup per CU with
+ * 2048-slot chunks whose bytes are staged in LDS in load order and written
+ * as consecutive 4-byte words (automatic for those sizes when a tile holds a
+ * chunk). For tuning. Every shape gives the same bytes. Not synchronised:
+ * set it while no split is being launched. Outside 0..16: RAFI_ERR_ARG. */
 int rafi_split_set_variant(int32_t variant);
 int rafi_multisplit(const void *items, const int32_t *dest, uint64_t n, uint32_t item_bytes,
                     int32_t n_domains, void *out, uint64_t *offsets, uint64_t *summary,

@@ -60,7 +60,9 @@ void free_queues(rafi_ctx *c)
 int alloc_queues(rafi_ctx *c, uint64_t cap)
 {
     const SplitPlan p = split_plan_bound(cap, c->D, c->S);
-    if (hipMalloc(&c->buf[0], cap * c->S) != hipSuccess || hipMalloc(&c->buf[1], cap * c->S) != hipSuccess ||
+    // item buffers padded by 16 bytes: the split may read whole 16-byte
+    // pieces past the last item
+    if (hipMalloc(&c->buf[0], cap * c->S + 16) != hipSuccess || hipMalloc(&c->buf[1], cap * c->S + 16) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&c->dest), cap * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(&c->ws, p.bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -170,7 +172,8 @@ void prof_domain_end(rafi_ctx *c, int h)
 
 int round_enqueue(rafi_ctx *c)
 {
-    const SplitPlan p = split_plan(c->n_slots, c->D, c->S);
+    SplitPlan p = split_plan(c->n_slots, c->D, c->S);
+    p.padded = true;  // the context's item buffers are padded (alloc_queues)
     if (p.bytes > c->ws_bytes) return RAFI_ERR_STATE;
     SplitEvents ev;
     const SplitEvents *evp = nullptr;

@@ -43,6 +43,9 @@ struct SplitPlan {
     uint64_t M = 0;          // rows * n_tiles table entries
     uint32_t scan_blocks = 0;
     uint64_t off_table = 0, off_part = 0, off_dummy = 0, off_done = 0, bytes = 0;  // workspace layout
+    // the item array may be read up to 16 bytes past its end (allocations the
+    // library pads for this: context queues)
+    bool padded = false;
     // off_dummy: 16 bytes any scatter lane may overwrite; off_done: the finished-tile
     // counter of the fused histogram + scan launch (zero between launches)
 };

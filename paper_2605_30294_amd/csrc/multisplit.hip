@@ -474,6 +474,41 @@ scatter_line_kernel(const uint32_t *__restrict__ items, const int32_t *__restric
         [&](int32_t e) { return table[(uint64_t)e * n_tiles + tile]; }, out, n, lds);
 }
 
+// The wide shape with raw staging (item sizes that are not a multiple of 16
+// bytes): one workgroup per CU, the chunk's bytes in LDS in load order.
+template <int NW, int R, int W>
+__global__ void __launch_bounds__(64 * W, (W + 3) / 4)
+scatter_wide_raw_kernel(const uint32_t *__restrict__ items, const int32_t *__restrict__ dest, uint64_t n,
+                        uint64_t words, int32_t D, int nbits, uint32_t T, uint32_t n_tiles,
+                        const uint32_t *__restrict__ table, uint32_t *__restrict__ out, uint32_t *__restrict__ dummy)
+{
+    extern __shared__ __align__(16) uint32_t lds[];
+    const uint64_t tstart = (uint64_t)blockIdx.x * T;
+    const uint64_t tend = min(tstart + T, n);
+    const uint32_t tile = blockIdx.x;
+    dev::wide_raw_scatter_tile<NW, R, W>(
+        items, dest, tstart, tend, words, D, 0, nbits,
+        [&](int32_t e) { return table[(uint64_t)e * n_tiles + tile]; }, out, n, dummy, lds);
+}
+
+template <int NW, int R, int W>
+bool try_wide_raw(const SplitPlan &p, const uint32_t *items, const int32_t *dest, const uint32_t *table,
+                  uint32_t *out, uint32_t *dummy, hipStream_t s)
+{
+    const size_t lds = dev::wide_raw_lds_bytes_c<NW, R, W>(p.D) + 64;
+    if (p.D > dev::kStagedMaxD || lds > dev::kStagedLdsPerCu) return false;
+    // readable words: the array, rounded up to whole 16-byte pieces where
+    // the allocation is padded for that
+    uint64_t words = p.n * (uint64_t)NW;
+    if (p.padded) words = (words + 3) & ~3ull;
+    if (words % 4 != 0 || words < 4) return false;
+    int nbits = 1;
+    while ((1 << nbits) < p.D) ++nbits;
+    hipLaunchKernelGGL((scatter_wide_raw_kernel<NW, R, W>), dim3(p.n_tiles), dim3(64 * W), lds, s, items, dest, p.n,
+                       words, p.D, nbits, p.tile, p.n_tiles, table, out, dummy);
+    return true;
+}
+
 int g_cus = 0;
 
 int cu_count()
@@ -524,6 +559,14 @@ bool launch_staged(const SplitPlan &p, const uint32_t *items, const int32_t *des
                    uint32_t *out, uint32_t *dummy, hipStream_t s)
 {
     int v = g_split_variant;
+    if constexpr (NW % 4 != 0 && NW >= 3 && NW <= 15) {
+        // item sizes that are not a multiple of 16 bytes: raw staging, one
+        // workgroup per CU (automatic when a tile fills a 2048-slot chunk)
+        if ((v == 16 || (v == 0 && p.tile >= 8 * 64 * 4)) &&
+            try_wide_raw<NW, 4, 8>(p, items, dest, table, out, dummy, s))
+            return true;
+    }
+    if (v == 16) v = 0;  // shape 16 does not take this item size: automatic
     if (v >= 14) {  // line-aligned writes, one workgroup per CU over a group of tiles
         if constexpr (NW == 8) {
             if (v == 14 && try_line<8, 4, 8, 1792, false>(p, items, dest, table, out, s)) return true;
@@ -643,7 +686,7 @@ void finish_plan(SplitPlan &p)
 
 int split_set_variant(int v)
 {
-    if (v < 0 || v > 15) return RAFI_ERR_ARG;
+    if (v < 0 || v > 16) return RAFI_ERR_ARG;
     g_split_variant = v;
     return RAFI_OK;
 }

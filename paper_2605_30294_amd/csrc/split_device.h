@@ -928,5 +928,170 @@ __device__ inline void gather_scatter_tile(const uint32_t *__restrict__ items, c
     }
 }
 
+// ------------------------------------------ wide scatter, raw staging ---
+// The wide shape for items whose size is not a multiple of 16 bytes (the
+// 44-byte rays of the paper's forwarding benchmark, the 40- and 24-byte
+// N-body items). A chunk's bytes are read as consecutive 16-byte pieces and
+// kept in LDS in load order: the chunk starts on a 16-byte boundary because
+// CH and every tile start are multiples of 4 items. Ranking moves indices
+// only: for each chunk-sorted slot j, its output slot and the chunk-local
+// item it takes. The write phase gives consecutive 4-byte words of the
+// sorted chunk to consecutive lanes, so a destination's run goes out as
+// contiguous words. All stores are issued (surplus lanes write the dummy
+// word), so the compiler counts outstanding memory operations exactly and
+// the next chunk's loads, issued before the write phase, never wait for
+// this chunk's stores.
+template <int NW, int R, int W>
+constexpr size_t wide_raw_lds_bytes_c(int32_t D)
+{
+    constexpr int CH = W * 64 * R;
+    return sizeof(uint32_t) * ((size_t)CH * NW + D + CH) + sizeof(uint16_t) * ((size_t)W * D + 2 + CH);
+}
+
+// words: 32-bit words of `items` that may be read, a multiple of 4 (at
+// least 4); the host rounds the array's length up to it only where the
+// allocation is padded for that.
+template <int NW, int R, int W, typename RunBase>
+__device__ inline void wide_raw_scatter_tile(const uint32_t *__restrict__ items, const int32_t *__restrict__ dest,
+                                             uint64_t tstart, uint64_t tend, uint64_t words, int32_t D,
+                                             int32_t dbase, int nbits, RunBase run_base, uint32_t *__restrict__ out,
+                                             uint64_t out_cap, uint32_t *__restrict__ dummy, uint32_t *lds)
+{
+    constexpr int NT = 64 * W, SEG = 64 * R, CH = W * SEG;
+    static_assert((R * NW) % 4 == 0, "a chunk is a whole number of 16-byte pieces per thread");
+    static_assert(CH <= 65536, "chunk-local indices are 16-bit");
+    constexpr int PPT = R * NW / 4;                      // 16-byte load pieces per thread per chunk
+    constexpr int WPT = R * NW;                          // 4-byte store words per thread per chunk
+    constexpr int EPT = (kStagedMaxD + NT - 1) / NT;     // max destinations per thread
+    uint32_t *stage = lds;                               // [CH * NW] the chunk's words in load order
+    uint32_t *rb = stage + CH * NW;                      // [D]
+    uint32_t *gpos = rb + D;                             // [CH] output slot of sorted slot j
+    uint16_t *cnt = reinterpret_cast<uint16_t *>(gpos + CH);  // [W * D (+2)]
+    uint16_t *ssrc = cnt + W * D + 2;                    // [CH] chunk-local item of sorted slot j
+    __shared__ uint32_t scan_lds[NT / 64 + 1];
+
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const int per = (D + NT - 1) / NT;
+    const int e0 = tid * per;
+
+    uint32_t cursor[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) cursor[k] = (k < per && e0 + k < D) ? run_base(e0 + k) : 0u;
+
+    typedef uint4 Pieces[PPT];
+    typedef int32_t Dests[R];
+    auto load_chunk = [&](Pieces &pc, Dests &dd, uint64_t cbase) {
+        const uint64_t qbase = cbase + (uint64_t)w * SEG;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t i = qbase + 64 * r + lane;
+            const uint64_t ic = i < tend ? i : tend - 1;
+            const int32_t x = __builtin_nontemporal_load(dest + ic);
+            dd[r] = i < tend ? x - dbase : -1;
+        }
+        const uint64_t wb = cbase * NW;  // a multiple of 4
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            // pieces past the readable words belong to no item of the tile
+            // (never stored): read the last piece instead
+            const uint64_t w0 = wb + 4ull * (uint64_t)(k * NT + tid);
+            pc[k] = load_nt4(items + (w0 + 4 <= words ? w0 : words - 4));
+        }
+        __asm__ __volatile__("" ::: "memory");
+    };
+
+    auto process = [&](Pieces &pc, Dests &dd, auto after_place) {
+        // the chunk's bytes into LDS, in load order
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) reinterpret_cast<uint4 *>(stage)[k * NT + tid] = pc[k];
+        uint16_t rank[R];
+        for (int k = tid; k < (W * D + 2) / 2; k += NT) reinterpret_cast<uint32_t *>(cnt)[k] = 0;
+        __syncthreads();
+
+        uint16_t *mycnt = cnt + w * D;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int32_t d = dd[r];
+            const bool ok = d >= 0 && d < D;
+            const uint64_t peers = match_peers((uint32_t)d, ok, nbits);
+            uint16_t before = 0;
+            if (ok) before = mycnt[d];
+            __builtin_amdgcn_wave_barrier();
+            rank[r] = (uint16_t)(before + __popcll(peers & lt));
+            if (ok && (peers & lt) == 0ull) mycnt[d] = (uint16_t)(before + __popcll(peers));
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+
+        uint32_t tot_e[EPT];
+        uint32_t local = 0;
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int32_t e = e0 + k;
+            uint32_t t = 0;
+            if (k < per && e < D)
+#pragma unroll
+                for (int ww = 0; ww < W; ++ww) t += cnt[ww * D + e];
+            tot_e[k] = t;
+            local += t;
+        }
+        uint32_t chunk_total;
+        uint32_t base = block_excl_scan<NT>(local, scan_lds, &chunk_total);
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int32_t e = e0 + k;
+            if (k < per && e < D) {
+                rb[e] = cursor[k] - base;  // output slot = rb[e] + chunk-sorted index
+                cursor[k] += tot_e[k];
+                uint32_t b = base;
+#pragma unroll
+                for (int ww = 0; ww < W; ++ww) {
+                    const uint32_t c = cnt[ww * D + e];
+                    cnt[ww * D + e] = (uint16_t)b;
+                    b += c;
+                }
+            }
+            base += tot_e[k];
+        }
+        __syncthreads();
+
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int32_t d = dd[r];
+            if (d >= 0 && d < D) {
+                const uint32_t pos = (uint32_t)cnt[w * D + d] + rank[r];
+                gpos[pos] = rb[d] + pos;
+                ssrc[pos] = (uint16_t)(w * SEG + 64 * r + lane);
+            }
+        }
+        __syncthreads();
+
+        after_place();
+
+        // write: WPT words per thread, all issued
+        const uint32_t n_words = chunk_total * NW;
+#pragma unroll
+        for (int u = 0; u < WPT; ++u) {
+            const uint32_t q = (uint32_t)(u * NT + tid);
+            const uint32_t qq = q < n_words ? q : (n_words ? n_words - 1 : 0);
+            const uint32_t j = qq / NW, part = qq - j * NW;
+            const uint32_t g = gpos[j];
+            // (ssrc[0] may be stale when the chunk is empty: keep the index in range)
+            const uint32_t v = stage[min((uint32_t)ssrc[j], (uint32_t)(CH - 1)) * NW + part];
+            uint32_t *dst = (q < n_words && g < out_cap) ? out + (uint64_t)g * NW + part : dummy;
+            *dst = v;
+        }
+        __syncthreads();
+    };
+
+    if (tstart >= tend) return;
+    Pieces pc;
+    Dests dd;
+    load_chunk(pc, dd, tstart);
+    for (uint64_t cbase = tstart; cbase < tend; cbase += CH)
+        process(pc, dd, [&] { load_chunk(pc, dd, cbase + CH); });
+}
+
 }  // namespace dev
 }  // namespace rafi

@@ -116,3 +116,68 @@ def test_split_line_aligned_shapes(orc, variant, n, D, words, dist):
         _run_split(orc, n, D, words, seed=variant * 1000 + n + 1, dist=dist)
     finally:
         rafi.split_set_variant(0)
+
+
+def _run_ctx_split(orc, n, D, words, seed, dist="mixed"):
+    """The same split through a context's round (item buffers padded by the
+    library, so the raw-staged shape also takes lengths that are not whole
+    16-byte pieces)."""
+    dev = device()
+    rng = np.random.default_rng(seed)
+    if dist == "mixed":
+        dest = rng.integers(-1, D, n).astype(np.int32)
+    elif dist == "cyclic":
+        dest = (np.arange(n) % D).astype(np.int32)
+    else:
+        dest = W.split_dest(n, D, dist, seed=seed)
+    items = rng.integers(0, 2**32, (n, words), dtype=np.uint64).astype(np.uint32)
+    announce(f"context split n={n} D={D} S={4 * words} dist={dist}")
+    ctx = rafi.Context(D, 4 * words, n)
+    try:
+        ctx.begin(n)
+        ctx.emit_bulk(torch.from_numpy(items.view(np.int32)).to(dev), torch.from_numpy(dest).to(dev))
+        counts, total, rc = ctx.round()
+        q, offs = ctx.copy_queue()
+        e_out, e_counts, e_off, e_done, e_bad = orc.multisplit(items, dest, D)
+        assert total == int(e_off[-1]) and np.array_equal(counts, e_counts)
+        assert np.array_equal(offs, e_off)
+        assert np.array_equal(q.cpu().numpy().view(np.uint32).reshape(-1), e_out.reshape(-1))
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("variant", [0, 16])
+@pytest.mark.parametrize("n,D,words,dist", [
+    (1_000_000, 1024, 11, "mixed"), (1_000_003, 1024, 11, "mixed"), (600_000, 64, 10, "zipf"),
+    (524_288, 1000, 6, "cyclic"), (300_000, 1024, 3, "mixed"), (2_000_000, 1024, 11, "cyclic"),
+    (70_000, 16, 11, "mixed")])
+def test_split_raw_staged_shape(orc, variant, n, D, words, dist):
+    """Item sizes that are not a multiple of 16 bytes (12, 24, 40, 44 bytes):
+    the raw-staged shape (chunk bytes in LDS in load order, 4-byte words
+    out), automatic or forced, through the stateless split (which keeps the
+    staged shapes when the array is not a whole number of 16-byte pieces)
+    and through a context."""
+    try:
+        rafi.split_set_variant(variant)
+        _run_split(orc, n, D, words, seed=variant * 1000 + n + 2, dist=dist)
+        _run_ctx_split(orc, n, D, words, seed=variant * 1000 + n + 3, dist=dist)
+    finally:
+        rafi.split_set_variant(0)
+
+
+@pytest.mark.parametrize("dist", ["uniform", "zipf"])
+def test_split_full_size_44_bytes(orc, dist):
+    """The microbenchmark at the paper's 44-byte ray size: 64M items, 1024
+    destinations."""
+    dev = device()
+    n, D = 1 << 26, 1024
+    dest = W.split_dest(n, D, dist)
+    items = W.split_items(n, 11)
+    announce(f"split full size 44 B {dist}")
+    out, offsets, summary = rafi.multisplit(torch.from_numpy(items.view(np.int32)).to(dev),
+                                            torch.from_numpy(dest).to(dev), D)
+    torch.cuda.synchronize()
+    e_out, e_counts, e_off, e_done, e_bad = orc.multisplit(items, dest, D)
+    assert np.array_equal(offsets.cpu().numpy().astype(np.uint64), e_off)
+    assert int(summary[0]) == n and int(summary[1]) == 0 and int(summary[2]) == 0
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), e_out)
