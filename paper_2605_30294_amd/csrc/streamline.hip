@@ -368,11 +368,19 @@ advance_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids)
 // Launches over few particles are bound by the latency of each particle's
 // chain of RK4 steps, not by throughput. There a quad of lanes carries one
 // particle: lane a (a < 3) holds coordinate a of the position, computes that
-// axis's cell index and weight, gathers component a of the 8 corners and
-// interpolates it; lane 3 repeats lane 2. The cell index, the weights and
-// the step tests are exchanged within the quad by DPP moves. Every
-// component's arithmetic is the one-lane kernel's, in the same order, so the
-// results are bit-identical; each lane runs about a third of the chain.
+// axis's cell and weight, gathers component a of the 8 corners and
+// interpolates it; lane 3 repeats lane 2. The weights and the step tests are
+// exchanged within the quad by DPP moves. Every component's arithmetic is the
+// one-lane kernel's, in the same order, so the results are bit-identical;
+// each lane runs about a third of the chain.
+//
+// A lone wave issues about one instruction per 4.5 cycles, a DPP move that
+// feeds the next instruction costs about 12 more, and any branch 30-60
+// cycles (compare, exec or condition, redirect). So the common path of a
+// sample and of a step is straight-line code: the rare events (a sample
+// leaving the cached cell, a step that may stop or forward the particle)
+// each sit behind one wave-uniform branch, laid out of line, that only
+// tests a per-lane candidate flag and is not taken.
 constexpr int kQuadThreads = 256;
 
 // DPP quad permutations (lane j of a quad reads lane p[j]): 0xb1 = [1,0,3,2],
@@ -442,91 +450,142 @@ __device__ inline void quad_gather(const QuadAxis &ax, int32_t base, QuadCell &d
     dst.base = base;
 }
 
-// The one-lane sampler restricted to this lane's component. On a cell
-// change the corners come from a look-ahead slot if one holds that cell
-// (pnow: gathered for this step, arrived; pnext: gathered for the next step),
-// else from the field.
-template <int FW>
-__device__ inline float field_quad(const QuadAxis &ax, QuadCell &cc, const QuadCell &pnow, const QuadCell &pnext,
-                                   float q)
-{
-    float w;
-    const int32_t base = quad_cell(ax, q, w);
-    const float w0 = quad_lane<0>(w), w1 = quad_lane<1>(w), w2 = quad_lane<2>(w);
-    if (base != cc.base) {
-        if (base == pnow.base)
-            cc = pnow;
-        else if (base == pnext.base)
-            cc = pnext;
-        else {
-            quad_gather<FW>(ax, base, cc);
-            // wait here, on this path only: the other paths then carry no
-            // pending load into the interpolation below
-            __builtin_amdgcn_s_waitcnt(kWaitLoads);
-        }
-    }
-    const float *c = cc.c;
-    return lerpf(lerpf(lerpf(c[0], c[1], w0), lerpf(c[2], c[3], w0), w1),
-                 lerpf(lerpf(c[4], c[5], w0), lerpf(c[6], c[7], w0), w1), w2);
-}
-
-// Particle state of the quad kernel (lane a holds coordinate a).
-struct QuadWalk {
-    float x;    // position
-    float sum;  // k1 + 2 k2 + 2 k3 + k4 of the last step
-    int32_t steps, taken, why, dest;
-    bool done;  // stopped or forwarded (the same on the 4 lanes)
+// The cell in use: this lane's component of the 8 corners, kept as
+// c[2k] = corner 2k and c[2k+1] = corner 2k+1 - corner 2k (the x-lerp's
+// difference, the same float the lerp forms, so reuse is exact), the floor of
+// this lane's axis (a float) and the quad's linear corner index.
+struct QuadCache {
+    float fl = -1.0f;
+    int32_t base = -1;
+    float c[8];
 };
 
-// One RK4 step and its tests, unless the particle is done.
-template <int FW>
-__device__ inline void quad_step(const QuadAxis &ax, QuadCell &cc, const QuadCell &pnow, const QuadCell &pnext,
-                                 QuadWalk &s, float h, float hh, float h6, float lo, float hi, float fn, int32_t bsz,
-                                 int32_t dmul, int32_t d, int32_t max_steps, int32_t cap)
+__device__ inline void cache_fill(QuadCache &cc, const QuadCell &s, float fl)
 {
-    if (s.done) return;
+#pragma unroll
+    for (int k = 0; k < 8; k += 2) {
+        cc.c[k] = s.c[k];
+        cc.c[k + 1] = s.c[k + 1] - s.c[k];
+    }
+    cc.base = s.base;
+    cc.fl = fl;
+}
+
+// The one-lane sampler's 7 lerps (x, then y, then z) on the cached cell.
+__device__ inline float interp_cached(const QuadCache &cc, float w0, float w1, float w2)
+{
+    const float *c = cc.c;
+    const float x0 = __fmaf_rn(w0, c[1], c[0]), x1 = __fmaf_rn(w0, c[3], c[2]);
+    const float x2 = __fmaf_rn(w0, c[5], c[4]), x3 = __fmaf_rn(w0, c[7], c[6]);
+    return lerpf(lerpf(x0, x1, w1), lerpf(x2, x3, w1), w2);
+}
+
+// One sample of this lane's component at coordinate q. The interpolation runs
+// on the cached cell at once. A lane whose axis floor differs from the cached
+// one flags its wave; only then do the quads that left their cell take the
+// corners from a look-ahead slot (pnow: gathered for this step, normally
+// arrived; pnext: gathered for the next step) or gather them, and
+// interpolate again.
+template <int FW>
+__device__ inline float sample_quad(const QuadAxis &ax, QuadCache &cc, const QuadCell &pnow, const QuadCell &pnext,
+                                    float q)
+{
+    const float uc = __builtin_amdgcn_fmed3f(q - 0.5f, 0.0f, ax.hi);
+    const float fl = fminf(floorf(uc), ax.top);
+    const float w = uc - fl;
+    const float w0 = quad_lane<0>(w), w1 = quad_lane<1>(w), w2 = quad_lane<2>(w);
+    float r = interp_cached(cc, w0, w1, w2);
+    if (__builtin_expect(__builtin_amdgcn_ballot_w64(fl != cc.fl) != 0, 0)) {
+        const int32_t moved = quad_sum(fl != cc.fl ? 1 : 0);
+        const int32_t base = quad_sum((int32_t)__umul24((uint32_t)(int32_t)fl, (uint32_t)ax.stride));
+        if (moved) {
+            if (base == pnow.base) {
+                cache_fill(cc, pnow, fl);
+            } else if (base == pnext.base) {
+                cache_fill(cc, pnext, fl);
+            } else {
+                QuadCell g;
+                quad_gather<FW>(ax, base, g);
+                __builtin_amdgcn_s_waitcnt(kWaitLoads);
+                cache_fill(cc, g, fl);
+            }
+            r = interp_cached(cc, w0, w1, w2);
+        }
+    }
+    return r;
+}
+
+// Particle state of the quad kernel (lane a holds coordinate a). A particle
+// that is done keeps running with step 0, so its position no longer moves,
+// and its results are kept aside; the wave loops until no particle is live.
+struct QuadRun {
+    float x, sum;
+    float h, hh, h6;  // job.h, h/2, h/6; all 0 once done
+    int32_t steps, taken;
+    bool live;
+    float out_x;
+    int32_t out_steps, out_why, out_dest;
+};
+
+// One RK4 step. The stop and forward tests run exactly (quad-wide, as the
+// one-lane kernel decides them) only when some live lane of the wave sees a
+// candidate: a coordinate that did not change, a coordinate outside the
+// brick's range, or a step count at its limit.
+template <int FW>
+__device__ inline void quad_step(const QuadAxis &ax, QuadCache &cc, const QuadCell &pnow, const QuadCell &pnext,
+                                 QuadRun &s, float lo, float hi, float fn, int32_t bsz, int32_t dmul, int32_t d,
+                                 int32_t max_steps, int32_t cap, bool &any_live)
+{
     const float x = s.x;
-    const float k1 = field_quad<FW>(ax, cc, pnow, pnext, x);
-    const float k2 = field_quad<FW>(ax, cc, pnow, pnext, __fmaf_rn(hh, k1, x));
-    const float k3 = field_quad<FW>(ax, cc, pnow, pnext, __fmaf_rn(hh, k2, x));
-    const float k4 = field_quad<FW>(ax, cc, pnow, pnext, __fmaf_rn(h, k3, x));
+    const float k1 = sample_quad<FW>(ax, cc, pnow, pnext, x);
+    const float k2 = sample_quad<FW>(ax, cc, pnow, pnext, __fmaf_rn(s.hh, k1, x));
+    const float k3 = sample_quad<FW>(ax, cc, pnow, pnext, __fmaf_rn(s.hh, k2, x));
+    const float k4 = sample_quad<FW>(ax, cc, pnow, pnext, __fmaf_rn(s.h, k3, x));
     const float sum = __fmaf_rn(2.0f, k3, __fmaf_rn(2.0f, k2, k1)) + k4;
-    const float nx = __fmaf_rn(h6, sum, x);
-    ++s.steps;
-    ++s.taken;
-    s.sum = sum;
+    const float nx = __fmaf_rn(s.h6, sum, x);
+    const int32_t steps = s.steps + 1, taken = s.taken + 1;
     s.x = nx;
-    if (quad_all(__float_as_uint(nx) == __float_as_uint(x))) {
-        s.why = RAFI_SL_STAGNANT;
-        s.done = true;
-        return;
+    s.sum = sum;
+    s.steps = steps;
+    s.taken = taken;
+    const bool cand = __float_as_uint(nx) == __float_as_uint(x) || !(nx >= lo && nx < hi) || steps >= max_steps ||
+                      taken >= cap;
+    if (__builtin_expect(__builtin_amdgcn_ballot_w64(s.live && cand) != 0, 0)) {
+        const bool stag = quad_all(__float_as_uint(nx) == __float_as_uint(x));
+        int32_t e = d;
+        if (!quad_all(nx >= lo && nx < hi)) {
+            const bool ok = nx >= 0.0f && nx < fn;
+            const int32_t all_ok = quad_all(ok);
+            const int32_t idx = quad_sum(ok ? ((int32_t)floorf(nx) / bsz) * dmul : 0);
+            e = all_ok ? idx : -1;
+        }
+        const int32_t why = stag ? RAFI_SL_STAGNANT : e < 0 ? RAFI_SL_EXITED : steps >= max_steps ? RAFI_SL_MAXSTEPS : 0;
+        const bool forward = why == 0 && (e != d || taken >= cap);
+        if (s.live && (why != 0 || forward)) {
+            s.live = false;
+            s.out_x = nx;
+            s.out_steps = steps;
+            s.out_why = why;
+            s.out_dest = forward ? e : d;
+            s.h = 0.0f;
+            s.hh = 0.0f;
+            s.h6 = 0.0f;
+        }
+        any_live = __builtin_amdgcn_ballot_w64(s.live) != 0;
     }
-    int32_t e = d;
-    if (!quad_all(nx >= lo && nx < hi)) {
-        const bool ok = nx >= 0.0f && nx < fn;
-        const int32_t all_ok = quad_all(ok);
-        const int32_t idx = quad_sum(ok ? ((int32_t)floorf(nx) / bsz) * dmul : 0);
-        e = all_ok ? idx : -1;
-    }
-    // (selects, not branches: both fields stay in registers)
-    const int32_t why = e < 0 ? RAFI_SL_EXITED : s.steps >= max_steps ? RAFI_SL_MAXSTEPS : 0;
-    const bool forward = why == 0 && (e != d || s.taken >= cap);
-    s.why = why;
-    s.dest = forward ? e : s.dest;
-    s.done = why != 0 || forward;
 }
 
 // Settle the slot gathered a step ago (normally arrived), then gather into
-// `slot` the cell two steps ahead along the last step's mean velocity. Runs
-// on every path of the loop (also for done particles, whose gathers are
-// clamped into the field and never read), so that the compiler's count of
-// pending loads is the same on every path.
+// `slot` the cell two steps ahead along the last step's mean velocity. Done
+// particles gather too (clamped into the field, never read), so that every
+// path of the loop issues the same loads and the compiler's count of pending
+// loads stays exact.
 template <int FW>
-__device__ inline void quad_look_ahead(const QuadAxis &ax, const QuadWalk &s, float h6, QuadCell &slot)
+__device__ inline void quad_look_ahead(const QuadAxis &ax, const QuadRun &s, float h6x2, QuadCell &slot)
 {
     __builtin_amdgcn_s_waitcnt(kWaitLoads);
     float w;
-    quad_gather<FW>(ax, quad_cell(ax, __fmaf_rn(2.0f * h6, s.sum, s.x), w), slot);
+    quad_gather<FW>(ax, quad_cell(ax, __fmaf_rn(h6x2, s.sum, s.x), w), slot);
 }
 
 template <int FW>
@@ -558,22 +617,27 @@ advance_quad_kernel(rafi_device_view view, rafi_sl_job job, uint64_t n_ids)
         if (lane == 0) rafi_forward_t(view, i, it, RAFI_POISON);
         return;
     }
-    const float h = job.h, hh = job.h * 0.5f, h6 = (float)((double)job.h / 6.0);
+    const float h6 = (float)((double)job.h / 6.0);
     const bool capped = job.steps_per_visit > 0 && n_in > job.tail_items;
     const int32_t cap = capped ? job.steps_per_visit : 0x7fffffff;
-    QuadWalk s{a == 0 ? it.x : a == 1 ? it.y : it.z, 0.0f, job.steps[it.id], 0, 0, d, false};
-    QuadCell cc, pa, pb;
-    // two steps per trip, so that the two look-ahead slots swap roles
-    // without copies; a particle done after the first skips the second
-    for (;;) {
-        quad_step<FW>(ax, cc, pa, pb, s, h, hh, h6, lo, hi, fn, bsz, dmul, d, job.max_steps, cap);
-        quad_look_ahead<FW>(ax, s, h6, pa);
-        quad_step<FW>(ax, cc, pb, pa, s, h, hh, h6, lo, hi, fn, bsz, dmul, d, job.max_steps, cap);
-        quad_look_ahead<FW>(ax, s, h6, pb);
-        if (s.done) break;
-    }
-    const float x = s.x;
-    const int32_t steps = s.steps, why = s.why, dest = s.dest;
+    QuadRun s{a == 0 ? it.x : a == 1 ? it.y : it.z, 0.0f, job.h, job.h * 0.5f, h6, job.steps[it.id], 0, true,
+              0.0f, 0, 0, d};
+    QuadCache cc;
+    QuadCell pa, pb;
+    bool any_live = true;
+    // Nothing loaded so far may still be pending in the loop: a load first read
+    // there would make every trip wait for all loads in flight.
+    __builtin_amdgcn_s_waitcnt(kWaitLoads);
+    // two steps per trip, so that the two look-ahead slots swap roles without
+    // copies (every live particle stops within max_steps, so the loop ends)
+    do {
+        quad_step<FW>(ax, cc, pa, pb, s, lo, hi, fn, bsz, dmul, d, job.max_steps, cap, any_live);
+        quad_look_ahead<FW>(ax, s, 2.0f * h6, pa);
+        quad_step<FW>(ax, cc, pb, pa, s, lo, hi, fn, bsz, dmul, d, job.max_steps, cap, any_live);
+        quad_look_ahead<FW>(ax, s, 2.0f * h6, pb);
+    } while (any_live);
+    const float x = s.out_x;
+    const int32_t steps = s.out_steps, why = s.out_why, dest = s.out_dest;
     const float px = quad_lane<0>(x), py = quad_lane<1>(x), pz = quad_lane<2>(x);
     if (why && lane < 3) job.endpoint[3 * (size_t)it.id + lane] = x;
     if (lane != 0) return;
