@@ -65,8 +65,8 @@ def log(msg):
 # of known size (profiles/rk4_advance_256cube_1Mseeds.md), for the source
 # file and schedule (steps_per_visit, tail_items, refill_lanes, quad_items)
 # below; reported only while both still hold.
-RK4_TRAFFIC = {"kernel": "advance_kernel<3, true> + advance_quad_kernel<3>", "bytes_per_launch": 361697277,
-               "source": "paper_2605_30294_amd/csrc/streamline.hip", "source_sha256_16": "34f4d8e1569101ea",
+RK4_TRAFFIC = {"kernel": "advance_kernel<3, true> + advance_quad_kernel<3>", "bytes_per_launch": 400344689,
+               "source": "paper_2605_30294_amd/csrc/streamline.hip", "source_sha256_16": "6a95fa3e013ff3be",
                "schedule": (96, 0, 0, 98304), "field_layout": "unpadded"}
 
 

@@ -112,6 +112,25 @@ def test_constant_field_exact(orc):
     assert np.array_equal(g["endpoint"][:, 0].astype(np.float64), x0 + 0.125 * steps)
 
 
+@pytest.mark.parametrize("quad", [0, rafi.SL_QUAD_ITEMS])
+def test_zero_field_stagnates(orc, quad):
+    """A zero field: every particle stops after one step, where it started
+    (the one-lane kernel's visit estimate then divides by zero speeds, and
+    seeds on brick faces give 0/0; neither may change a result)."""
+    n, grid = 32, (4, 2, 1)
+    field = W.constant_field(n, (0.0, 0.0, 0.0))
+    rng = np.random.default_rng(3)
+    seeds = rng.uniform(0, n, (700, 3)).astype(np.float32)
+    seeds[:100, 0] = 8.0 * rng.integers(0, 4, 100)      # on x brick faces
+    seeds[100:200, 1] = 16.0 * rng.integers(0, 2, 100)  # on y brick faces
+    announce(f"sl zero field quad={quad}")
+    g = _stepwise(field, grid, seeds, max_steps=50, quad_items=quad)
+    o = orc.streamlines(field, grid, seeds, max_steps=50, queue_cap=1 << 20)
+    _compare(g, o)
+    assert np.all(g["steps"] == 1) and np.all(g["reason"] == 1)
+    assert np.array_equal(g["endpoint"].view(np.uint32), seeds.view(np.uint32))
+
+
 def test_full_cfg1_sampled(orc):
     """256^3 ABC, 4x4x4 bricks, 1M seeds, RK4 h = 0.25, <= 2000 steps: the whole
     job on the GPU, a seeded sample of 4096 particles through the oracle."""
