@@ -45,6 +45,9 @@ ALU_PEAK_TFLOPS = 256 * 128 * 2 * 2.4e9 / 1e12
 # The ceiling without packed math (this build emits no packed float32
 # instructions): 256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz = 78.6 TFLOP/s.
 ALU_UNPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# RK4 steps per brick visit of the streamline job (the library's measured best;
+# the same value as rafi.SL_STEPS_PER_VISIT)
+STEPS_PER_VISIT = 112
 # Algorithmic float32 flops of one RK4 step (FMA = 2): per trilinear vec3
 # sample 2 subs for the weights x 3 axes + 7 lerps (sub + fma) x 3 components
 # = 69; four samples = 276; three stage offsets (3 fma) = 18; the weighted
@@ -65,9 +68,9 @@ def log(msg):
 # of known size (profiles/rk4_advance_256cube_1Mseeds.md), for the source
 # file and schedule (steps_per_visit, tail_items, refill_lanes, quad_items)
 # below; reported only while both still hold.
-RK4_TRAFFIC = {"kernel": "advance_kernel<3, true> + advance_quad_kernel<3>", "bytes_per_launch": 400344689,
+RK4_TRAFFIC = {"kernel": "advance_kernel<3, true> + advance_quad_kernel<3>", "bytes_per_launch": 408020608,
                "source": "paper_2605_30294_amd/csrc/streamline.hip", "source_sha256_16": "6a95fa3e013ff3be",
-               "schedule": (96, 0, 0, 98304), "field_layout": "unpadded"}
+               "schedule": (112, 0, 0, 98304), "field_layout": "unpadded"}
 
 
 def rk4_traffic(schedule, layout):
@@ -599,7 +602,7 @@ def main():
                     help="sweep (steps_per_visit, tail_items, refill_lanes, quad_items) and the field layout "
                          "before timing "
                          "instead of using the defaults below (the measured best on MI355X)")
-    ap.add_argument("--steps-per-visit", type=int, default=96,
+    ap.add_argument("--steps-per-visit", type=int, default=STEPS_PER_VISIT,
                     help="RK4 steps a particle takes per domain visit before it is forwarded to its own "
                          "brick (0 = until it leaves, -1 = autotune with the tail threshold); results do "
                          "not depend on it")

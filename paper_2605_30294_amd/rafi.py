@@ -399,6 +399,9 @@ def sl_pack(field: torch.Tensor) -> torch.Tensor:
 
 
 SL_QUAD_ITEMS = 98304  # launch size at and below which four lanes carry each particle
+# RK4 steps per brick visit of the benchmark's 256^3 / 1M-seed job (its measured
+# best; results do not depend on it)
+SL_STEPS_PER_VISIT = 112
 
 
 def sl_job(field4: torch.Tensor, grid, endpoint, steps, reason=None, h=0.25, max_steps=2000,

@@ -27,7 +27,8 @@ def test_bench_default_schedule_matches_measured_counters():
     """The default command line runs the schedule the counters describe."""
     b = _bench()
     from paper_2605_30294_amd import rafi
-    assert b.RK4_TRAFFIC["schedule"] == (96, 0, 0, rafi.SL_QUAD_ITEMS)
+    assert b.STEPS_PER_VISIT == rafi.SL_STEPS_PER_VISIT
+    assert b.RK4_TRAFFIC["schedule"] == (rafi.SL_STEPS_PER_VISIT, 0, 0, rafi.SL_QUAD_ITEMS)
 
 
 def test_streamline_tuning_space():

@@ -183,8 +183,8 @@ def test_full_cfg1_sampled(orc):
 
 def test_full_cfg1_exact(orc):
     """256^3 ABC, 4x4x4 bricks, all 1M seeds, RK4 h = 0.25, <= 2000 steps, under
-    the benchmark's schedule (96 steps per visit, lane quads for launches over
-    at most 98304 particles, unpadded field). The pipelined job's endpoints,
+    the benchmark's schedule (rafi.SL_STEPS_PER_VISIT steps per visit, lane
+    quads for launches over at most 98304 particles, unpadded field). The pipelined job's endpoints,
     step counts and reasons, and the stepwise run's per-round counts and
     queues, equal the oracle's bit for bit (oracle threaded for speed: its
     results do not depend on the thread count)."""
@@ -193,15 +193,16 @@ def test_full_cfg1_exact(orc):
     field = W.abc_field(n)
     seeds = W.streamline_seeds(N, n)
     announce("sl cfg1 full, exact")
-    r = rafi.sl_trace(torch.from_numpy(field).to(dev), grid, torch.from_numpy(seeds).to(dev), steps_per_visit=96)
+    r = rafi.sl_trace(torch.from_numpy(field).to(dev), grid, torch.from_numpy(seeds).to(dev),
+                      steps_per_visit=rafi.SL_STEPS_PER_VISIT)
     torch.cuda.synchronize()
     ep, st, why = r["endpoint"].cpu().numpy(), r["steps"].cpu().numpy(), r["reason"].cpu().numpy()
     r["ctx"].close()
-    g = _stepwise(field, grid, seeds, steps_per_visit=96, packed=False)
+    g = _stepwise(field, grid, seeds, steps_per_visit=rafi.SL_STEPS_PER_VISIT, packed=False)
     assert np.array_equal(g["endpoint"].view(np.uint32), ep.view(np.uint32))
     orc.set_threads(orc.default_threads())
     try:
-        o = orc.streamlines(field, grid, seeds, steps_per_visit=96, queue_cap=1 << 23)
+        o = orc.streamlines(field, grid, seeds, steps_per_visit=rafi.SL_STEPS_PER_VISIT, queue_cap=1 << 23)
     finally:
         orc.set_threads(1)
     assert g["counts"].shape[0] == r["rounds"] == o["rounds"]
@@ -221,7 +222,8 @@ def test_large_field_global_loads(orc, n, packed):
     assert f.numel() * 4 > 2**31 - 1
     seeds = W.streamline_seeds(256, n, seed=11)
     announce(f"sl large field n={n} packed={packed}")
-    r = rafi.sl_trace(f, (4, 4, 4), torch.from_numpy(seeds).to(dev), steps_per_visit=96, quad_items=0)
+    r = rafi.sl_trace(f, (4, 4, 4), torch.from_numpy(seeds).to(dev), steps_per_visit=rafi.SL_STEPS_PER_VISIT,
+                      quad_items=0)
     torch.cuda.synchronize()
     ep, st, why = r["endpoint"].cpu().numpy(), r["steps"].cpu().numpy(), r["reason"].cpu().numpy()
     r["ctx"].close()
