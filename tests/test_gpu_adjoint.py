@@ -31,7 +31,7 @@ def _gpu_loss_grad(vol_np, tgt_np, grid, views, ray_mask=None, bwd_tile_items=0)
     loss = (r * r).sum()
     loss.backward()
     torch.cuda.synchronize()
-    return float(loss), vol.grad.detach().cpu().numpy().astype(np.float64), target.cpu().numpy().astype(np.float64)
+    return float(loss.detach()), vol.grad.detach().cpu().numpy().astype(np.float64), target.cpu().numpy().astype(np.float64)
 
 
 def _rays_near(views, ids, voxel, n, radius=2.5):
