@@ -191,5 +191,5 @@ def test_gradient_of_a_permuted_volume(orc):
     del junk
     g = leaf.grad.permute(2, 1, 0).cpu().numpy().astype(np.float64)
     L64, g64, _ = orc.ea_loss_grad(vol_np, grid, views, target.cpu().numpy().astype(np.float64), c=C32)
-    assert abs(float(loss) - L64) <= 1e-4 * abs(L64)
+    assert abs(float(loss.detach()) - L64) <= 1e-4 * abs(L64)
     assert _rel_l2(g, g64) <= REL_L2, _rel_l2(g, g64)
