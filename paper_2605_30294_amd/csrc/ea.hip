@@ -84,28 +84,83 @@ __device__ inline void emit_ray(const rafi_device_view &view, const rafi_ea_job 
 }
 
 // ------------------------------------------------------------- march ----
+// One lane per ray. A wave marches until the longest chord among its 64 rays
+// ends, so each workgroup first orders its rays by the samples each has left
+// in its brick (a counting sort through LDS). Every ray is marched as if alone
+// and written to its own output slot, so results do not depend on the lane.
 __global__ void __launch_bounds__(256)
 march_kernel(rafi_device_view view, rafi_ea_job job, uint32_t n_rays)
 {
+    constexpr uint32_t kThreads = 256, kWaves = kThreads / 64, kBuckets = 16;
+    __shared__ uint32_t s_slot[kThreads];
+    __shared__ int32_t s_d[kThreads];
+    __shared__ uint32_t s_cnt[kWaves][kBuckets];
     // the grid may be sized for an upper bound: number the live workgroups only
     const uint64_t n_in = rafi_queue_length(view);
-    const uint32_t nb = (uint32_t)((n_in + blockDim.x - 1) / blockDim.x);
+    const uint32_t nb = (uint32_t)((n_in + kThreads - 1) / kThreads);
     if (blockIdx.x >= nb) return;
-    const uint64_t i = rafi_xcd_block(blockIdx.x, nb) * (uint64_t)blockDim.x + threadIdx.x;
-    if (i >= n_in) return;
+    const uint32_t t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const uint64_t base = rafi_xcd_block(blockIdx.x, nb) * (uint64_t)kThreads;
     const Geo g = job_geo(job);
-    const int32_t d = ea::find_domain(view.in_offsets, view.n_domains, i);
-    Item it = static_cast<const Item *>(view.in_items)[i];
-    if ((uint32_t)it.ray >= n_rays) {  // never true for items this library emitted
-        emit_item(view, job, i, it, RAFI_POISON);
-        return;
+    uint64_t slot = base + t;
+    int32_t d = 0;
+    uint32_t key = kBuckets - 1;
+    if (slot < n_in) {
+        d = ea::find_domain(view.in_offsets, view.n_domains, slot);
+        const Item it = static_cast<const Item *>(view.in_items)[slot];
+        if ((uint32_t)it.ray >= n_rays) {  // never true for items this library emitted
+            emit_item(view, job, slot, it, RAFI_POISON);
+        } else {
+            // samples left in the brick along a straight line (an estimate: it
+            // only orders the lanes)
+            float org[3], dir[3];
+            int32_t K;
+            job_ray(job, it.ray, org, dir, &K);
+            const Box box = ea::box_of(d, g);
+            const float lo[3] = {box.lo0, box.lo1, box.lo2}, hi[3] = {box.hi0, box.hi1, box.hi2};
+            float texit = 3.0e38f;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (dir[a] != 0.0f)
+                    texit = fminf(texit, ((dir[a] > 0.0f ? hi[a] : lo[a]) - org[a]) * __builtin_amdgcn_rcpf(dir[a]));
+            const float span = (float)(g.b0 + g.b1 + g.b2) * __builtin_amdgcn_rcpf(job.dt);
+            const float left = fminf(texit * __builtin_amdgcn_rcpf(job.dt) - 0.5f - (float)it.k, (float)(K - it.k));
+            key = (uint32_t)fminf(fmaxf(left * ((float)(kBuckets - 1) / span), 0.0f), (float)(kBuckets - 2));
+        }
     }
+    // Stable counting sort of the workgroup's lanes by key, through LDS: lanes
+    // with a similar number of samples left share a wave. Every thread reaches
+    // both barriers; threads left without a ray return after the second.
+    uint32_t rank = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kBuckets; ++k) {
+        const uint64_t m = __ballot(key == k);
+        if (lane == 0) s_cnt[w][k] = (uint32_t)__popcll(m);
+        if (key == k) rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+    }
+    __syncthreads();
+    uint32_t pos = rank, n_live = 0;
+    for (uint32_t k = 0; k < kBuckets; ++k) {
+#pragma unroll
+        for (uint32_t ww = 0; ww < kWaves; ++ww) {
+            const uint32_t c = s_cnt[ww][k];
+            pos += (k < key || (k == key && ww < w)) ? c : 0;
+            n_live += k < kBuckets - 1 ? c : 0;
+        }
+    }
+    s_slot[pos] = (uint32_t)(slot - base);
+    s_d[pos] = d;
+    __syncthreads();
+    if (t >= n_live) return;  // no barrier follows
+    slot = base + s_slot[t];
+    d = s_d[t];
+    Item it = static_cast<const Item *>(view.in_items)[slot];
     log_visit(job, it.ray, d);
     float org[3], dir[3];
     int32_t K;
     job_ray(job, it.ray, org, dir, &K);
     const int32_t dest = ea::march_through(job.volume, g, ea::box_of(d, g), org, dir, K, job.dt, job.c, it);
-    emit_ray(view, job, i, it, dest);
+    emit_ray(view, job, slot, it, dest);
 }
 
 // LDS-staged march: one workgroup per domain-pure tile of the input queue
