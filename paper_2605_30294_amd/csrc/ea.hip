@@ -86,12 +86,14 @@ __device__ inline void emit_ray(const rafi_device_view &view, const rafi_ea_job 
 // ------------------------------------------------------------- march ----
 // One lane per ray. A wave marches until the longest chord among its 64 rays
 // ends, so each workgroup first orders its rays by the samples each has left
-// in its brick (a counting sort through LDS). Every ray is marched as if alone
-// and written to its own output slot, so results do not depend on the lane.
+// in its brick (a counting sort through LDS), where chords can differ and
+// unless they all fall in one bucket. Every ray is marched as if alone and written to its own output
+// slot, so results do not depend on the lane.
 __global__ void __launch_bounds__(256)
 march_kernel(rafi_device_view view, rafi_ea_job job, uint32_t n_rays)
 {
     constexpr uint32_t kThreads = 256, kWaves = kThreads / 64, kBuckets = 16;
+    __shared__ Item s_item[kThreads];
     __shared__ uint32_t s_slot[kThreads];
     __shared__ int32_t s_d[kThreads];
     __shared__ uint32_t s_cnt[kWaves][kBuckets];
@@ -104,10 +106,39 @@ march_kernel(rafi_device_view view, rafi_ea_job job, uint32_t n_rays)
     const Geo g = job_geo(job);
     uint64_t slot = base + t;
     int32_t d = 0;
+    Item it{};
     uint32_t key = kBuckets - 1;
+    // Order the lanes only where chords can differ much: bricks whose chord
+    // can exceed 64 samples, and rays not along an axis (the same decision in
+    // every thread, taken from the workgroup's first ray; any choice gives the
+    // same results).
+    bool order = (float)(g.b0 + g.b1 + g.b2) >= 64.0f * job.dt;
+    if (order) {
+        const int32_t r0 = static_cast<const Item *>(view.in_items)[base].ray;
+        if ((uint32_t)r0 < n_rays) {
+            const float *dir0 = job.views[r0 / (job.width * job.height)].dir;
+            order = (dir0[0] != 0.0f) + (dir0[1] != 0.0f) + (dir0[2] != 0.0f) > 1;
+        }
+    }
+    if (!order) {
+        if (slot >= n_in) return;
+        d = ea::find_domain(view.in_offsets, view.n_domains, slot);
+        it = static_cast<const Item *>(view.in_items)[slot];
+        if ((uint32_t)it.ray >= n_rays) {  // never true for items this library emitted
+            emit_item(view, job, slot, it, RAFI_POISON);
+            return;
+        }
+        log_visit(job, it.ray, d);
+        float org[3], dir[3];
+        int32_t K;
+        job_ray(job, it.ray, org, dir, &K);
+        const int32_t dest = ea::march_through(job.volume, g, ea::box_of(d, g), org, dir, K, job.dt, job.c, it);
+        emit_ray(view, job, slot, it, dest);
+        return;
+    }
     if (slot < n_in) {
         d = ea::find_domain(view.in_offsets, view.n_domains, slot);
-        const Item it = static_cast<const Item *>(view.in_items)[slot];
+        it = static_cast<const Item *>(view.in_items)[slot];
         if ((uint32_t)it.ray >= n_rays) {  // never true for items this library emitted
             emit_item(view, job, slot, it, RAFI_POISON);
         } else {
@@ -129,8 +160,7 @@ march_kernel(rafi_device_view view, rafi_ea_job job, uint32_t n_rays)
         }
     }
     // Stable counting sort of the workgroup's lanes by key, through LDS: lanes
-    // with a similar number of samples left share a wave. Every thread reaches
-    // both barriers; threads left without a ray return after the second.
+    // with a similar number of samples left share a wave.
     uint32_t rank = 0;
 #pragma unroll
     for (uint32_t k = 0; k < kBuckets; ++k) {
@@ -139,22 +169,32 @@ march_kernel(rafi_device_view view, rafi_ea_job job, uint32_t n_rays)
         if (key == k) rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
     }
     __syncthreads();
-    uint32_t pos = rank, n_live = 0;
+    uint32_t pos = rank, n_live = 0, n_full = 0;
     for (uint32_t k = 0; k < kBuckets; ++k) {
+        uint32_t tot = 0;
 #pragma unroll
         for (uint32_t ww = 0; ww < kWaves; ++ww) {
             const uint32_t c = s_cnt[ww][k];
             pos += (k < key || (k == key && ww < w)) ? c : 0;
-            n_live += k < kBuckets - 1 ? c : 0;
+            tot += c;
         }
+        n_live += k < kBuckets - 1 ? tot : 0;
+        n_full += (k < kBuckets - 1 && tot > 0) ? 1 : 0;
     }
-    s_slot[pos] = (uint32_t)(slot - base);
-    s_d[pos] = d;
-    __syncthreads();
-    if (t >= n_live) return;  // no barrier follows
-    slot = base + s_slot[t];
-    d = s_d[t];
-    Item it = static_cast<const Item *>(view.in_items)[slot];
+    // One bucket (or none) holds every live ray: the order stays (the same
+    // decision in every thread, so the barrier below is met by all or none).
+    if (n_full > 1) {
+        s_item[pos] = it;
+        s_slot[pos] = (uint32_t)(slot - base);
+        s_d[pos] = d;
+        __syncthreads();
+        if (t >= n_live) return;  // no barrier follows
+        it = s_item[t];
+        slot = base + s_slot[t];
+        d = s_d[t];
+    } else if (key == kBuckets - 1) {
+        return;
+    }
     log_visit(job, it.ray, d);
     float org[3], dir[3];
     int32_t K;
