@@ -183,16 +183,63 @@ dt_raygen_kernel(rafi_device_view view, rafi_dt_job job, uint64_t n_paths)
 __global__ void __launch_bounds__(256)
 dt_trace_kernel(rafi_device_view view, rafi_dt_job job, uint64_t n_paths)
 {
+    constexpr uint32_t kThreads = 256, kWaves = kThreads / 64, kBuckets = 16;
+    __shared__ uint32_t s_slot[kThreads];
+    __shared__ int32_t s_d[kThreads];
+    __shared__ uint32_t s_cnt[kWaves][kBuckets];
     // the grid may be sized for an upper bound: number the live workgroups only
     const uint64_t n_in = rafi_queue_length(view);
-    const uint32_t nb = (uint32_t)((n_in + blockDim.x - 1) / blockDim.x);
+    const uint32_t nb = (uint32_t)((n_in + kThreads - 1) / kThreads);
     if (blockIdx.x >= nb) return;  // whole workgroups: no lane is left out of the counter sums
-    const uint64_t i = rafi_xcd_block(blockIdx.x, nb) * (uint64_t)blockDim.x + threadIdx.x;
-    const bool live = i < n_in;
+    const uint32_t t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const uint64_t base = rafi_xcd_block(blockIdx.x, nb) * (uint64_t)kThreads;
+    const ea::Geo g = ea::make_geo(job.n, job.grid);
+    // Order the workgroup's items into lanes by the tentative points they can
+    // expect in their brick (the straight-line chord times the majorant),
+    // through LDS; results do not depend on the lane.
+    uint64_t i = base + t;
+    int32_t d = 0;
+    uint32_t key = kBuckets - 1;
+    if (i < n_in) {
+        d = ea::find_domain(view.in_offsets, view.n_domains, i);
+        const DTItem q = static_cast<const DTItem *>(view.in_items)[i];
+        const ea::Box bx = ea::box_of(d, g);
+        const float lo[3] = {bx.lo0, bx.lo1, bx.lo2}, hi[3] = {bx.hi0, bx.hi1, bx.hi2};
+        const float p[3] = {q.px, q.py, q.pz}, dv[3] = {q.dx, q.dy, q.dz};
+        float texit = 3.0e38f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (dv[a] != 0.0f)
+                texit = fminf(texit, ((dv[a] > 0.0f ? hi[a] : lo[a]) - p[a]) * __builtin_amdgcn_rcpf(dv[a]));
+        const float span = (float)(g.b0 + g.b1 + g.b2);
+        key = (uint32_t)fminf(fmaxf(texit * ((float)(kBuckets - 1) / span), 0.0f), (float)(kBuckets - 2));
+    }
+    uint32_t rank = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kBuckets; ++k) {
+        const uint64_t m = __ballot(key == k);
+        if (lane == 0) s_cnt[w][k] = (uint32_t)__popcll(m);
+        if (key == k) rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+    }
+    __syncthreads();
+    uint32_t pos = rank, n_live = 0;
+    for (uint32_t k = 0; k < kBuckets; ++k) {
+#pragma unroll
+        for (uint32_t ww = 0; ww < kWaves; ++ww) {
+            const uint32_t c = s_cnt[ww][k];
+            pos += (k < key || (k == key && ww < w)) ? c : 0;
+            n_live += k < kBuckets - 1 ? c : 0;
+        }
+    }
+    s_slot[pos] = (uint32_t)(i - base);
+    s_d[pos] = d;
+    __syncthreads();
+    // no barrier follows: lanes without an item stay for the counter sums
+    const bool live = t < n_live;
     uint32_t points = 0, hits = 0;
     if (live) {
-        const ea::Geo g = ea::make_geo(job.n, job.grid);
-        const int32_t d = ea::find_domain(view.in_offsets, view.n_domains, i);
+        i = base + s_slot[t];
+        d = s_d[t];
         const ea::Box box = ea::box_of(d, g);
         DTItem it = static_cast<const DTItem *>(view.in_items)[i];
         DTItem out0 = it;
