@@ -440,8 +440,9 @@ typedef struct rafi_sl_job {
                                 values: RAFI_ERR_ARG. */
     uint32_t quad_items;     /* launches whose input queue holds at most this many particles
                                 (with refill_lanes 0) run four lanes per particle, one per
-                                coordinate, exchanging cell index, weights and tests within
-                                the lane quad (about a third of the dependent instructions
+                                coordinate, exchanging weights within the lane quad (and cell
+                                indices and tests when a lane flags a cell change or a
+                                possible stop: about a third of the dependent instructions
                                 per step), and gather each particle's cell two steps ahead
                                 while it integrates: for launches too small to fill the GPU,
                                 which are bound by each particle's step latency. 0: never.
