@@ -374,6 +374,17 @@ __global__ void __launch_bounds__(kNBThreads) nb_answer_size_wave_kernel(rafi_de
     if (lane == 0) cnt[j] = tot;
 }
 
+// Lane o's copy of v (every lane of the wave active).
+__device__ inline uint32_t lane_value(uint32_t v, uint32_t o)
+{
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(o << 2), (int)v);
+}
+
+// The answer items of 64 cells at a time (the same slots as the size kernel's
+// count, cell by cell): a lane per cell finds each cell's item count and the
+// wave scans them; then the wave writes those items 64 at a time, each lane
+// finding the cell its item belongs to by a binary search over the scan, so
+// an opened cell with many particles is copied by the whole wave.
 __global__ void __launch_bounds__(kNBThreads) nb_answer_wave_kernel(rafi_device_view V, rafi_device_view Rq,
                                                                    const NBParticle *__restrict__ q,
                                                                    const NBNode *__restrict__ cells,
@@ -384,7 +395,7 @@ __global__ void __launch_bounds__(kNBThreads) nb_answer_wave_kernel(rafi_device_
 {
     const uint64_t j = (uint64_t)wave_id();
     if (j >= Rq.n_in) return;  // whole waves
-    const int lane = threadIdx.x & 63;
+    const uint32_t lane = threadIdx.x & 63;
     const int32_t s = ea::find_domain(Rq.in_offsets, Rq.n_domains, j);
     const int32_t r = static_cast<const NBRequest *>(Rq.in_items)[j].sender;
     const NBBox b = boxes[r];
@@ -398,72 +409,113 @@ __global__ void __launch_bounds__(kNBThreads) nb_answer_wave_kernel(rafi_device_
         const bool a = valid && accepts(c.com, csize, b, theta);
         const uint32_t sz = valid ? (a ? 1u : c.count) : 0u;
         const uint32_t incl = dev::wave_incl_scan(sz);
-        uint64_t slot = base + (incl - sz);
-        base += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-        if (!valid) continue;
-        if (a) {
+        const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+        // per lane, for the search below: its cell's first item (wave-relative),
+        // first particle, and whether it answers with its moments
+        const uint32_t first_item = incl - sz, first_particle = c.first, accepted = a ? 1u : 0u;
+        for (uint32_t t0 = 0; t0 < total; t0 += 64) {
+            const uint32_t t = min(t0 + lane, total - 1);
+            // o = number of cells whose items all lie before t: the owner of item t
+            uint32_t o = 0;
+#pragma unroll
+            for (uint32_t st = 32; st > 0; st >>= 1)
+                if (lane_value(incl, o + st - 1) <= t) o += st;
+            const uint32_t off = t - lane_value(first_item, o);
+            const uint32_t p0 = lane_value(first_particle, o), acc = lane_value(accepted, o);
+            const uint32_t kk = k0 + o;
+            if (t0 + lane >= total) continue;
             NBVirtual v;
-            v.pos[0] = c.com[0];
-            v.pos[1] = c.com[1];
-            v.pos[2] = c.com[2];
-            v.mass = c.mass;
-            v.smax = csize;
-            v.src = s;
-            rafi_forward_t(V, slot, v, r);
-        } else {
-            for (uint32_t i = c.first; i < c.first + c.count; ++i) {
-                NBVirtual v;
-                v.pos[0] = q[i].pos[0];
-                v.pos[1] = q[i].pos[1];
-                v.pos[2] = q[i].pos[2];
-                v.mass = q[i].mass;
+            if (acc) {
+                const NBNode &cn = cells[kk];
+                v.pos[0] = cn.com[0];
+                v.pos[1] = cn.com[1];
+                v.pos[2] = cn.com[2];
+                v.mass = cn.mass;
+                v.smax = csize;
+            } else {
+                const NBParticle &pq = q[p0 + off];
+                v.pos[0] = pq.pos[0];
+                v.pos[1] = pq.pos[1];
+                v.pos[2] = pq.pos[2];
+                v.mass = pq.mass;
                 v.smax = 0.0f;
-                v.src = s;
-                rafi_forward_t(V, slot++, v, r);
             }
+            v.src = s;
+            rafi_forward_t(V, base + t, v, r);
         }
+        base += total;
     }
 }
 
-// Wave d handles domain d: coalesced loads of 64 particles at a time; the
-// box is a wave min/max (exact in any order); the moments are added in key
-// order, every lane taking the same values from the lane holding them.
-__global__ void __launch_bounds__(kNBThreads) nb_domain_wave_kernel(const NBParticle *__restrict__ q,
-                                                                   const uint64_t *__restrict__ off, int32_t D,
-                                                                   uint64_t n, const uint32_t *__restrict__ cell_of,
-                                                                   const uint32_t *__restrict__ n_cells,
-                                                                   NBNode *__restrict__ roots,
-                                                                   NBBox *__restrict__ boxes,
-                                                                   uint32_t *__restrict__ dcell)
+// Workgroup d handles domain d. Its four waves each add one of the moments
+// (mass, then mass times x, y, z) over the domain's particles in key order:
+// coalesced loads of 64 particles at a time, the next chunk's issued before
+// this chunk is summed, each lane taking the values from the lane that holds
+// them. Wave 0 also takes the box (a min/max: exact in any order).
+template <int A>
+__device__ inline float domain_moment(const NBParticle *__restrict__ q, uint32_t first, uint32_t count, int lane,
+                                      float lo[3], float hi[3])
 {
-    const int32_t d = wave_id();
-    if (d >= D) return;  // whole waves
-    const int lane = threadIdx.x & 63;
-    const uint32_t first = (uint32_t)off[d], count = (uint32_t)(off[d + 1] - off[d]);
-    float m = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
-    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    float sum = 0.0f;
+    float nw = 0.0f, npos[3] = {0.0f, 0.0f, 0.0f};
+    if ((uint32_t)lane < count) {
+        nw = q[first + lane].mass;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) npos[a] = q[first + lane].pos[a];
+    }
     for (uint32_t c0 = 0; c0 < count; c0 += 64) {
-        const bool valid = c0 + lane < count;
-        NBParticle p{};
-        if (valid) p = q[first + c0 + lane];
-        if (valid)
+        const float pw = nw, pc = A > 0 ? npos[A - 1] : 0.0f;
+        if (A == 0 && c0 + lane < count)
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                lo[a] = fminf(lo[a], p.pos[a]);
-                hi[a] = fmaxf(hi[a], p.pos[a]);
+                lo[a] = fminf(lo[a], npos[a]);
+                hi[a] = fmaxf(hi[a], npos[a]);
             }
-        const uint32_t nk = min(64u, count - c0);
-        for (uint32_t t = 0; t < nk; ++t) {
-            const float w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.mass), t));
-            const float x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.pos[0]), t));
-            const float y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.pos[1]), t));
-            const float z = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.pos[2]), t));
-            m = m + w;
-            mx = __fmaf_rn(w, x, mx);
-            my = __fmaf_rn(w, y, my);
-            mz = __fmaf_rn(w, z, mz);
+        const uint32_t nx = c0 + 64 + lane;
+        if (nx < count) {
+            nw = q[first + nx].mass;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) npos[a] = q[first + nx].pos[a];
+        }
+        auto add = [&](uint32_t t) {
+            const float w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pw), t));
+            if (A == 0) {
+                sum = sum + w;
+            } else {
+                const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pc), t));
+                sum = __fmaf_rn(w, c, sum);
+            }
+        };
+        if (count - c0 >= 64) {  // a full chunk: straight-line code, constant lanes
+#pragma unroll
+            for (uint32_t t = 0; t < 64; ++t) add(t);
+        } else {
+            for (uint32_t t = 0; t < count - c0; ++t) add(t);
         }
     }
+    return sum;
+}
+
+__global__ void __launch_bounds__(256) nb_domain_kernel(const NBParticle *__restrict__ q,
+                                                        const uint64_t *__restrict__ off, int32_t D, uint64_t n,
+                                                        const uint32_t *__restrict__ cell_of,
+                                                        const uint32_t *__restrict__ n_cells,
+                                                        NBNode *__restrict__ roots, NBBox *__restrict__ boxes,
+                                                        uint32_t *__restrict__ dcell)
+{
+    __shared__ float s_sum[4];
+    const int32_t d = blockIdx.x;  // the grid has D workgroups
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const uint32_t first = (uint32_t)off[d], count = (uint32_t)(off[d + 1] - off[d]);
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    float sum;
+    if (w == 0) sum = domain_moment<0>(q, first, count, lane, lo, hi);
+    else if (w == 1) sum = domain_moment<1>(q, first, count, lane, lo, hi);
+    else if (w == 2) sum = domain_moment<2>(q, first, count, lane, lo, hi);
+    else sum = domain_moment<3>(q, first, count, lane, lo, hi);
+    if (lane == 0) s_sum[w] = sum;
+    __syncthreads();
+    if (w != 0) return;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
         for (int o = 32; o > 0; o >>= 1) {
@@ -471,6 +523,7 @@ __global__ void __launch_bounds__(kNBThreads) nb_domain_wave_kernel(const NBPart
             hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o, 64));
         }
     if (lane != 0) return;
+    const float m = s_sum[0], mx = s_sum[1], my = s_sum[2], mz = s_sum[3];
     NBNode r{};
     NBBox b{};
     if (count) {
@@ -585,46 +638,40 @@ __global__ void __launch_bounds__(kNBThreads) nb_fold_kernel(NBParticle *__restr
     }
 }
 
-// Wave c handles cell c: the cell's particles are loaded 64 at a time and
-// their mass and first moments added in key order from zero (lane
-// broadcasts), then the centre of mass is the first moment over the mass.
-__global__ void __launch_bounds__(kNBThreads) nb_cells_wave_kernel(const NBParticle *__restrict__ q, uint64_t n,
-                                                                  const uint32_t *__restrict__ n_cells,
-                                                                  const uint32_t *__restrict__ cell_start,
-                                                                  NBNode *__restrict__ cells)
+// Workgroup c handles cell c: its four waves each add one of the cell's
+// moments (mass, then mass times x, y, z) over its particles in key order from
+// zero (the same sums as the domain moments above); then the centre of mass
+// is the first moment over the mass.
+__global__ void __launch_bounds__(256) nb_cells_kernel(const NBParticle *__restrict__ q, uint64_t n,
+                                                       const uint32_t *__restrict__ n_cells,
+                                                       const uint32_t *__restrict__ cell_start,
+                                                       NBNode *__restrict__ cells)
 {
-    const uint32_t c = (uint32_t)wave_id();
+    __shared__ float s_sum[4];
+    const uint32_t c = blockIdx.x;
     const uint32_t nc = *n_cells;
-    if (c >= nc) return;  // whole waves
-    const int lane = threadIdx.x & 63;
+    if (c >= nc) return;  // the whole workgroup
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const uint32_t first = cell_start[c];
     const uint32_t count = (c + 1 < nc ? cell_start[c + 1] : (uint32_t)n) - first;
-    float m = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
-    for (uint32_t c0 = 0; c0 < count; c0 += 64) {
-        NBParticle p{};
-        if (c0 + lane < count) p = q[first + c0 + lane];
-        const uint32_t nk = min(64u, count - c0);
-        for (uint32_t t = 0; t < nk; ++t) {
-            const float w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.mass), t));
-            const float x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.pos[0]), t));
-            const float y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.pos[1]), t));
-            const float z = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.pos[2]), t));
-            m = m + w;
-            mx = __fmaf_rn(w, x, mx);
-            my = __fmaf_rn(w, y, my);
-            mz = __fmaf_rn(w, z, mz);
-        }
-    }
-    if (lane == 0) {
-        NBNode nd;
-        nd.com[0] = mx / m;
-        nd.com[1] = my / m;
-        nd.com[2] = mz / m;
-        nd.mass = m;
-        nd.first = first;
-        nd.count = count;
-        cells[c] = nd;
-    }
+    float lo[3], hi[3];  // unused here
+    float sum;
+    if (w == 0) sum = domain_moment<0>(q, first, count, lane, lo, hi);
+    else if (w == 1) sum = domain_moment<1>(q, first, count, lane, lo, hi);
+    else if (w == 2) sum = domain_moment<2>(q, first, count, lane, lo, hi);
+    else sum = domain_moment<3>(q, first, count, lane, lo, hi);
+    if (lane == 0) s_sum[w] = sum;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const float m = s_sum[0];
+    NBNode nd;
+    nd.com[0] = s_sum[1] / m;
+    nd.com[1] = s_sum[2] / m;
+    nd.com[2] = s_sum[3] / m;
+    nd.mass = m;
+    nd.first = first;
+    nd.count = count;
+    cells[c] = nd;
 }
 
 uint32_t blocks_for(uint64_t n) { return (uint32_t)std::max<uint64_t>(1, (n + kNBThreads - 1) / kNBThreads); }
@@ -769,12 +816,12 @@ int rafi_nb_step(rafi_ctx *P, rafi_ctx *V, rafi_ctx *Rq, const rafi_nb_job *job,
         if (rc != RAFI_OK) return rc;
         hipLaunchKernelGGL(nb_cell_start_kernel, dim3(blocks_for(n)), dim3(kNBThreads), 0, s, flags, cell_of, n,
                            cell_start);
-        hipLaunchKernelGGL(nb_cells_wave_kernel, dim3(waves_blocks(n)), dim3(kNBThreads), 0, s, q, n, counters,
-                           cell_start, cells);
+        hipLaunchKernelGGL(nb_cells_kernel, dim3((uint32_t)std::max<uint64_t>(n, 1)), dim3(256), 0, s, q, n,
+                           counters, cell_start, cells);
         RAFI_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(nb_domain_wave_kernel, dim3(waves_blocks(D)), dim3(kNBThreads), 0, s, q, pv.in_offsets, D, n,
-                       cell_of, counters, roots, boxes, dcell);
+    hipLaunchKernelGGL(nb_domain_kernel, dim3((uint32_t)D), dim3(256), 0, s, q, pv.in_offsets, D, n, cell_of,
+                       counters, roots, boxes, dcell);
     RAFI_LAUNCH_CHECK();
 
     // 4. virtual particles, first round: the roots
