@@ -269,6 +269,43 @@ __global__ void __launch_bounds__(kNBThreads) nb_digit_kernel(const NBParticle *
     if (i < n) digit[i] = (int32_t)((morton_key(q[i].pos) >> shift) & (kDigitBuckets - 1));
 }
 
+// Key order within each domain in one launch: workgroup d sorts its domain's
+// (key, queue position) pairs in LDS with a bitonic network (the pairs are
+// distinct, so this is exactly the stable sort by key) and gathers the
+// particles in that order into dst. For domains of at most kSortMax
+// particles; the host takes the three digit passes otherwise.
+constexpr uint32_t kSortMax = 8192;
+constexpr uint32_t kSortThreads = 1024;
+
+__global__ void __launch_bounds__(kSortThreads) nb_domain_sort_kernel(const NBParticle *__restrict__ src,
+                                                                      const uint64_t *__restrict__ off,
+                                                                      NBParticle *__restrict__ dst)
+{
+    __shared__ uint64_t s_key[kSortMax];
+    const uint32_t d = blockIdx.x;
+    const uint32_t first = (uint32_t)off[d], count = (uint32_t)(off[d + 1] - off[d]);
+    uint32_t m = 1;  // a power of two >= count (count <= kSortMax)
+    while (m < count) m <<= 1;
+    for (uint32_t i = threadIdx.x; i < m; i += kSortThreads)
+        s_key[i] = i < count ? ((uint64_t)morton_key(src[first + i].pos) << 32) | i : ~0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= m; k <<= 1)
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < m; i += kSortThreads) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const uint64_t a = s_key[i], b = s_key[l];
+                    if ((a > b) == ((i & k) == 0)) {
+                        s_key[i] = b;
+                        s_key[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (uint32_t i = threadIdx.x; i < count; i += kSortThreads) dst[first + i] = src[first + (uint32_t)s_key[i]];
+}
+
 // flags[i] = 1 where a new cell starts: a new level-L key prefix or a new domain
 __global__ void __launch_bounds__(kNBThreads) nb_flag_kernel(const NBParticle *__restrict__ q, uint64_t n,
                                                             const uint32_t *__restrict__ K, int32_t D, int shift,
@@ -783,10 +820,18 @@ int rafi_nb_step(rafi_ctx *P, rafi_ctx *V, rafi_ctx *Rq, const rafi_nb_job *job,
     rafi_view(P, &pv);
     NBParticle *q = static_cast<NBParticle *>(const_cast<void *>(pv.in_items));
 
-    // 2. key order within each domain: three stable passes over 10-bit digits
+    // 2. key order within each domain: one sorting workgroup per domain, or
+    // three stable passes over 10-bit digits when a domain is too large
     NBParticle *tmp = at<NBParticle>(ws, L.off_tmp);
     int32_t *digit = at<int32_t>(ws, L.off_digit);
-    if (n) {
+    uint64_t largest = 0;
+    for (int32_t e = 0; e < D; ++e) largest = std::max(largest, pcount[e]);
+    if (n && largest <= kSortMax) {
+        hipLaunchKernelGGL(nb_domain_sort_kernel, dim3((uint32_t)D), dim3(kSortThreads), 0, s, q, pv.in_offsets,
+                           tmp);
+        RAFI_LAUNCH_CHECK();
+        RAFI_HIP_CHECK(hipMemcpyAsync(q, tmp, n * sizeof(NBParticle), hipMemcpyDeviceToDevice, s));
+    } else if (n) {
         const SplitPlan plan = split_plan(n, (int32_t)kDigitBuckets, RAFI_NB_PARTICLE_BYTES);
         NBParticle *src = q, *dst = tmp;
         for (int pass = 0; pass < 3; ++pass) {

@@ -87,6 +87,8 @@ def _run(orc, p, D, level, theta, eps, dts, debug=True):
     (2000, 16, 2, 0.0, 1e-3, [1e-3]),          # theta 0: every particle to every other domain
     (1000, 1, 4, 0.5, 1e-3, [0.0, 1e-3]),      # one domain: no exchange
     (777, 3, 10, 1.5, 1e-3, [1e-3, 1e-3]),     # finest cells
+    (8192, 1, 4, 0.5, 1e-3, [1e-3]),           # one domain of 8192: the largest sorted in LDS
+    (20000, 2, 4, 0.5, 1e-3, [0.0, 1e-3]),     # domains over 8192: the three digit passes
 ])
 def test_nbody_matches_oracle(orc, n, D, level, theta, eps, dts):
     announce(f"nbody n={n} D={D} L={level} theta={theta}")
