@@ -510,12 +510,6 @@ size_t max_lds_bytes()
     return (size_t)v;
 }
 
-// Tile size for LDS-staged launches: a few hundred workgroups per round.
-uint32_t staged_tile(uint64_t n_slots)
-{
-    return (uint32_t)std::min<uint64_t>(4096, std::max<uint64_t>(512, n_slots / 512));
-}
-
 bool job_ok(const rafi_ctx *c, const rafi_ea_job *j)
 {
     if (!c || !j || !j->volume || !j->views || !j->image) return false;
