@@ -258,7 +258,7 @@ def split_microbench(dev, reps, S=32):
         ctx.emit_bulk(items, dest)
         # workgroup shape of the scatter: every shape gives the same bytes
         shapes = {}
-        for v in range(1, 17):
+        for v in range(1, 18):
             rafi.split_set_variant(v)
             shapes[v] = timed(3)[0]
         best = min(shapes, key=shapes.get)

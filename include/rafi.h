@@ -236,8 +236,15 @@ int rafi_multisplit_workspace(uint64_t n, int32_t n_domains, uint32_t item_bytes
  * that are not a multiple of 16, else as 0) uses one workgroup per CU with
  * 2048-slot chunks whose bytes are staged in LDS in load order and written
  * as consecutive 4-byte words (automatic for those sizes when a tile holds a
- * chunk). For tuning. Every shape gives the same bytes. Not synchronised:
- * set it while no split is being launched. Outside 0..16: RAFI_ERR_ARG. */
+ * chunk); 17 (the sizes of 16, splits of at least 2^21 slots and at most
+ * 1024 destinations, else as 0) runs shape 16's chunks on a lockstep
+ * schedule: 256 persistent workgroups, the 32 of one XCD taking the 32
+ * consecutive chunks of one tile at a time, with each chunk's run bases
+ * from the histogram pass (automatic where it applies; its plan needs 2
+ * more workspace bytes per 2048 slots and destination, which
+ * rafi_multisplit_workspace includes while 0 or 17 is selected). For
+ * tuning. Every shape gives the same bytes. Not synchronised: set it while
+ * no split is being launched. Outside 0..17: RAFI_ERR_ARG. */
 int rafi_split_set_variant(int32_t variant);
 int rafi_multisplit(const void *items, const int32_t *dest, uint64_t n, uint32_t item_bytes,
                     int32_t n_domains, void *out, uint64_t *offsets, uint64_t *summary,

@@ -494,7 +494,10 @@ int rafi_multisplit(const void *items, const int32_t *dest, uint64_t n, uint32_t
     if ((reinterpret_cast<uintptr_t>(items) | reinterpret_cast<uintptr_t>(out) |
          reinterpret_cast<uintptr_t>(dest) | reinterpret_cast<uintptr_t>(workspace)) & 15)
         return RAFI_ERR_ARG;
-    const SplitPlan p = split_plan(n, n_domains, item_bytes);
+    SplitPlan p = split_plan(n, n_domains, item_bytes);
+    // a workspace sized while another scatter shape was selected may lack the
+    // lockstep plan's chunk prefixes: plan without them
+    if (workspace_bytes < p.bytes && p.lock) p = split_plan(n, n_domains, item_bytes, false);
     if (workspace_bytes < p.bytes) return RAFI_ERR_ARG;
     return split_run(p, items, dest, out, offsets, summary, nullptr, 1, workspace,
                      static_cast<hipStream_t>(hip_stream));
@@ -508,7 +511,8 @@ int rafi_multisplit_noalloc(const void *items, const int32_t *dest, uint64_t n, 
     if ((reinterpret_cast<uintptr_t>(items) | reinterpret_cast<uintptr_t>(out) |
          reinterpret_cast<uintptr_t>(dest)) & 15)
         return RAFI_ERR_ARG;
-    const SplitPlan p = split_plan(n, n_domains, item_bytes);
+    // no lockstep plan: its chunk prefixes grow with n, the scratch does not
+    const SplitPlan p = split_plan(n, n_domains, item_bytes, false);
     if (p.bytes > kNoAllocScratchBytes) return RAFI_ERR_TOO_LARGE;
     const hipStream_t s = static_cast<hipStream_t>(hip_stream);
     void *ws = nullptr;

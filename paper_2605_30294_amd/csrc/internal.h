@@ -48,10 +48,19 @@ struct SplitPlan {
     bool padded = false;
     // off_dummy: 16 bytes any scatter lane may overwrite; off_done: the finished-tile
     // counter of the fused histogram + scan launch (zero between launches)
+    // Lockstep scatter (large splits of items that are not whole 16-byte
+    // pieces): tiles of `lock` chunks of 2048 slots; the workspace at
+    // off_pre holds, per chunk and destination, the items bound there in the
+    // earlier chunks of the chunk's tile (u16). lock = 0: off.
+    uint32_t lock = 0;
+    uint32_t n_chunks = 0;
+    uint64_t off_pre = 0;
 };
 
-SplitPlan split_plan(uint64_t n, int32_t D, uint32_t S);
-// Select the staged scatter shape (0 = automatic, 1..4 = fixed shapes).
+// allow_lock: the plan may use the lockstep scatter (its workspace grows by
+// 2 bytes per chunk and destination).
+SplitPlan split_plan(uint64_t n, int32_t D, uint32_t S, bool allow_lock = true);
+// Select the staged scatter shape (0 = automatic, 1..17 = fixed shapes).
 int split_set_variant(int v);
 // A plan whose workspace covers every n <= cap.
 SplitPlan split_plan_bound(uint64_t cap, int32_t D, uint32_t S);

@@ -87,6 +87,65 @@ hist_kernel(const int32_t *__restrict__ dest, uint64_t n, int32_t D, uint32_t T,
     hist_tile(dest, n, D, T, n_tiles, table, h);
 }
 
+// Lockstep plans: tiles of kLockTile chunks of kLockChunk slots. Besides the
+// tile's column of the table, pre[c * D + e] = items of chunk c's tile bound
+// for e in the chunks before c (at most (kLockTile - 1) * kLockChunk, which
+// fits 16 bits).
+constexpr uint32_t kLockChunk = 2048;  // slots per chunk: 8 waves x 4 rounds x 64 lanes
+constexpr uint32_t kLockTile = 32;     // chunks per tile: one per CU of an XCD
+constexpr uint32_t kLockXcds = 8;
+static_assert((kLockTile - 1) * kLockChunk < 65536, "chunk prefixes are 16-bit");
+
+// s_waitcnt immediate for lgkmcnt(0) alone (vmcnt and expcnt at their
+// maxima, i.e. not waited on).
+constexpr int kWaitLds = 0xc07f;
+
+__global__ void __launch_bounds__(256)
+hist_lock_kernel(const int32_t *__restrict__ dest, uint64_t n, int32_t D, uint32_t n_tiles, uint32_t n_chunks,
+                 uint32_t *__restrict__ table, uint16_t *__restrict__ pre)
+{
+    extern __shared__ uint32_t h[];  // D + 2
+    const uint32_t rows = (uint32_t)D + 2u;
+    for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x) h[e] = 0;
+    __syncthreads();
+    const uint32_t c_first = blockIdx.x * kLockTile;
+    const uint32_t c_end = min(c_first + kLockTile, n_chunks);
+    static_assert(kLockChunk == 2 * 4 * 256, "two int4 groups per thread per chunk");
+    for (uint32_t c = c_first; c < c_end; ++c) {
+        const uint64_t s0 = (uint64_t)c * kLockChunk;
+        const bool full = s0 + kLockChunk <= n;
+        // dest is 16-byte aligned and chunks start at multiples of 2048
+        uint4 a = make_uint4(0, 0, 0, 0), b = make_uint4(0, 0, 0, 0);
+        if (full) {
+            a = load_nt4(dest + s0 + 4 * threadIdx.x);
+            b = load_nt4(dest + s0 + 1024 + 4 * threadIdx.x);
+        }
+        for (uint32_t e = threadIdx.x; e < (uint32_t)D; e += blockDim.x)
+            pre[(uint64_t)c * (uint32_t)D + e] = (uint16_t)h[e];
+        __syncthreads();  // every count read before it changes
+        if (full) {
+            atomicAdd(&h[bucket_of((int32_t)a.x, D)], 1u);
+            atomicAdd(&h[bucket_of((int32_t)a.y, D)], 1u);
+            atomicAdd(&h[bucket_of((int32_t)a.z, D)], 1u);
+            atomicAdd(&h[bucket_of((int32_t)a.w, D)], 1u);
+            atomicAdd(&h[bucket_of((int32_t)b.x, D)], 1u);
+            atomicAdd(&h[bucket_of((int32_t)b.y, D)], 1u);
+            atomicAdd(&h[bucket_of((int32_t)b.z, D)], 1u);
+            atomicAdd(&h[bucket_of((int32_t)b.w, D)], 1u);
+        } else {
+            for (uint64_t i = s0 + threadIdx.x; i < n; i += blockDim.x) atomicAdd(&h[bucket_of(dest[i], D)], 1u);
+        }
+        // Every wave's LDS atomics complete before the barrier: LDS requests
+        // of different waves can complete out of order, and the compiler
+        // has been seen to drop this wait when the next read of the counts
+        // is reached through the loop's back edge.
+        __builtin_amdgcn_s_waitcnt(kWaitLds);
+        __syncthreads();
+    }
+    for (uint32_t e = threadIdx.x; e < rows; e += blockDim.x)
+        table[(uint64_t)e * n_tiles + blockIdx.x] = h[e];
+}
+
 // ---------------------------------------------------------------- pass 2 ---
 __device__ inline void load16(const uint32_t *__restrict__ a, uint64_t M, uint64_t base, uint32_t v[kScanPer])
 {
@@ -487,7 +546,7 @@ scatter_wide_raw_kernel(const uint32_t *__restrict__ items, const int32_t *__res
     const uint64_t tend = min(tstart + T, n);
     const uint32_t tile = blockIdx.x;
     dev::wide_raw_scatter_tile<NW, R, W>(
-        items, dest, tstart, tend, words, D, 0, nbits,
+        items, dest, tstart, tend, words, D, nbits,
         [&](int32_t e) { return table[(uint64_t)e * n_tiles + tile]; }, out, n, dummy, lds);
 }
 
@@ -506,6 +565,46 @@ bool try_wide_raw(const SplitPlan &p, const uint32_t *items, const int32_t *dest
     while ((1 << nbits) < p.D) ++nbits;
     hipLaunchKernelGGL((scatter_wide_raw_kernel<NW, R, W>), dim3(p.n_tiles), dim3(64 * W), lds, s, items, dest, p.n,
                        words, p.D, nbits, p.tile, p.n_tiles, table, out, dummy);
+    return true;
+}
+
+// The raw shape over a lockstep schedule: kLockXcds * kLockTile persistent
+// workgroups, one per CU. The dispatcher deals workgroups to the XCDs in
+// turn, so workgroup b runs on XCD b % 8 as its (b / 8)-th. At step j the 32
+// workgroups of XCD x take the 32 chunks of tile 8 j + x: the line a
+// destination's runs in two neighbouring chunks share is then written twice
+// into one L2 within the same step and leaves it whole, where chunks far
+// apart in time would each send a partial line to HBM. Every workgroup loads
+// its next chunk (and that chunk's run bases) while it writes the current one.
+template <int NW, int R, int W>
+__global__ void __launch_bounds__(64 * W, (W + 3) / 4)
+scatter_lock_raw_kernel(const uint32_t *__restrict__ items, const int32_t *__restrict__ dest, uint64_t n,
+                        uint64_t words, int32_t D, int nbits, uint32_t n_tiles, uint32_t n_chunks,
+                        const uint32_t *__restrict__ table, const uint16_t *__restrict__ pre,
+                        uint32_t *__restrict__ out, uint32_t *__restrict__ dummy)
+{
+    static_assert(W * 64 * R == (int)kLockChunk, "a chunk of the schedule is one chunk of the kernel");
+    extern __shared__ __align__(16) uint32_t lds[];
+    const uint32_t x = blockIdx.x % kLockXcds, k = blockIdx.x / kLockXcds;
+    const dev::LockChunks<kLockChunk, kLockTile> sched{n, x * kLockTile + k, kLockXcds * kLockTile, n_chunks,
+                                                       n_tiles, D, table, pre};
+    dev::wide_raw_scatter<NW, R, W>(items, dest, words, D, nbits, sched, out, n, dummy, lds);
+}
+
+template <int NW>
+bool try_lock_raw(const SplitPlan &p, const uint32_t *items, const int32_t *dest, const uint32_t *table,
+                  const uint16_t *pre, uint32_t *out, uint32_t *dummy, hipStream_t s)
+{
+    constexpr int R = 4, W = 8;
+    const size_t lds = dev::wide_raw_lds_bytes_c<NW, R, W>(p.D) + 64;
+    if (p.lock != kLockTile || p.D > dev::kStagedMaxD || lds > dev::kStagedLdsPerCu) return false;
+    uint64_t words = p.n * (uint64_t)NW;
+    if (p.padded) words = (words + 3) & ~3ull;
+    if (words % 4 != 0 || words < 4) return false;
+    int nbits = 1;
+    while ((1 << nbits) < p.D) ++nbits;
+    hipLaunchKernelGGL((scatter_lock_raw_kernel<NW, R, W>), dim3(kLockXcds * kLockTile), dim3(64 * W), lds, s,
+                       items, dest, p.n, words, p.D, nbits, p.n_tiles, p.n_chunks, table, pre, out, dummy);
     return true;
 }
 
@@ -556,9 +655,15 @@ int g_split_variant = 0;
 
 template <int NW>
 bool launch_staged(const SplitPlan &p, const uint32_t *items, const int32_t *dest, const uint32_t *table,
-                   uint32_t *out, uint32_t *dummy, hipStream_t s)
+                   const uint16_t *pre, uint32_t *out, uint32_t *dummy, hipStream_t s)
 {
     int v = g_split_variant;
+    if constexpr (NW % 4 != 0 && NW >= 3 && NW <= 15) {
+        // large splits: the lockstep schedule (its plan has the chunk prefixes)
+        if ((v == 0 || v == 17) && p.lock && try_lock_raw<NW>(p, items, dest, table, pre, out, dummy, s))
+            return true;
+    }
+    if (v == 17) v = 0;  // no lockstep plan for this split: automatic
     if constexpr (NW % 4 != 0 && NW >= 3 && NW <= 15) {
         // item sizes that are not a multiple of 16 bytes: raw staging, one
         // workgroup per CU (automatic when a tile fills a 2048-slot chunk)
@@ -646,10 +751,10 @@ bool launch_staged(const SplitPlan &p, const uint32_t *items, const int32_t *des
 
 template <int NW>
 void launch_scatter(const SplitPlan &p, const uint32_t *items, const int32_t *dest,
-                    const uint32_t *table, uint32_t *out, uint32_t *dummy, hipStream_t s)
+                    const uint32_t *table, const uint16_t *pre, uint32_t *out, uint32_t *dummy, hipStream_t s)
 {
     if constexpr (NW > 0) {
-        if (launch_staged<NW>(p, items, dest, table, out, dummy, s)) return;
+        if (launch_staged<NW>(p, items, dest, table, pre, out, dummy, s)) return;
     }
     int nbits = 1;
     while ((1 << nbits) < p.D) ++nbits;
@@ -681,18 +786,50 @@ void finish_plan(SplitPlan &p)
     p.off_table = 512;
     p.off_part = p.off_table + (p.M * 4 + 255) / 256 * 256;
     p.bytes = p.off_part + ((uint64_t)std::max<uint32_t>(p.scan_blocks, 1) * 4 + 255) / 256 * 256;
+    p.off_pre = p.bytes;
+    if (p.lock) p.bytes += ((uint64_t)p.n_chunks * (uint64_t)p.D * 2 + 255) / 256 * 256;
+}
+
+// The lockstep scatter takes items that are not whole 16-byte pieces (the
+// raw shape's sizes), at most the staged shapes' destination count, and
+// splits of at least 2^21 slots (four chunks per workgroup) whose table the
+// scan takes in one partial-sum pass.
+constexpr uint64_t kLockMinN = 1ull << 21;
+
+bool lock_eligible(uint64_t n, int32_t D, uint32_t S)
+{
+    const uint32_t NW = S / 4;
+    const uint64_t tiles = (n + kLockTile * kLockChunk - 1) / (kLockTile * kLockChunk);
+    return S % 4 == 0 && NW % 4 != 0 && NW >= 3 && NW <= 15 && D <= dev::kStagedMaxD && n >= kLockMinN &&
+           ((uint64_t)D + 2) * tiles <= (uint64_t)kPartMax * kScanChunk;
+}
+
+SplitPlan lock_plan(uint64_t n, int32_t D, uint32_t S)
+{
+    SplitPlan p;
+    p.n = n;
+    p.D = D;
+    p.S = S;
+    p.tile = kLockTile * kLockChunk;
+    p.n_tiles = (uint32_t)((n + p.tile - 1) / p.tile);
+    p.lock = kLockTile;
+    p.n_chunks = (uint32_t)((n + kLockChunk - 1) / kLockChunk);
+    finish_plan(p);
+    return p;
 }
 }  // namespace
 
 int split_set_variant(int v)
 {
-    if (v < 0 || v > 16) return RAFI_ERR_ARG;
+    if (v < 0 || v > 17) return RAFI_ERR_ARG;
     g_split_variant = v;
     return RAFI_OK;
 }
 
-SplitPlan split_plan(uint64_t n, int32_t D, uint32_t S)
+SplitPlan split_plan(uint64_t n, int32_t D, uint32_t S, bool allow_lock)
 {
+    if (allow_lock && (g_split_variant == 0 || g_split_variant == 17) && lock_eligible(n, D, S))
+        return lock_plan(n, D, S);
     SplitPlan p;
     p.n = n;
     p.D = D;
@@ -715,6 +852,9 @@ SplitPlan split_plan_bound(uint64_t cap, int32_t D, uint32_t S)
     p.tile = (uint32_t)min_tile(D);
     p.n_tiles = (uint32_t)std::min<uint64_t>(kMaxTiles, (cap + p.tile - 1) / p.tile);
     finish_plan(p);
+    // a lockstep plan for some n <= cap (whatever shape is selected later):
+    // its workspace grows with n
+    if (lock_eligible(cap, D, S)) p.bytes = std::max(p.bytes, lock_plan(cap, D, S).bytes);
     return p;
 }
 
@@ -728,18 +868,23 @@ int split_run(const SplitPlan &p, const void *items, const int32_t *dest, void *
     uint32_t *part = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + p.off_part);
     uint32_t *dummy = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + p.off_dummy);
     uint32_t *counters = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + p.off_done);
+    uint16_t *pre = reinterpret_cast<uint16_t *>(static_cast<char *>(workspace) + p.off_pre);
     const uint32_t ti = tile_items ? tile_items : 1u;
     // The fused launch costs one device-scope fence (an L2 write-back on this
     // multi-XCD part) per workgroup: worth it only for small tables.
-    if (p.n_tiles > 0 && fused && p.M <= kFusedMaxM && p.n_tiles <= kFusedMaxTiles) {
+    if (p.n_tiles > 0 && fused && !p.lock && p.M <= kFusedMaxM && p.n_tiles <= kFusedMaxTiles) {
         hipLaunchKernelGGL(hist_scan_kernel, dim3(p.n_tiles), dim3(256), sizeof(uint32_t) * p.rows, s, dest, p.n,
                            p.D, p.tile, p.n_tiles, table, p.M, counters, offsets, summary, tile_offsets, ti,
                            dropped);
         RAFI_LAUNCH_CHECK();
     } else {
         if (p.n_tiles > 0) {
-            hipLaunchKernelGGL(hist_kernel, dim3(p.n_tiles), dim3(256), sizeof(uint32_t) * p.rows, s,
-                               dest, p.n, p.D, p.tile, p.n_tiles, table);
+            if (p.lock)
+                hipLaunchKernelGGL(hist_lock_kernel, dim3(p.n_tiles), dim3(256), sizeof(uint32_t) * p.rows, s,
+                                   dest, p.n, p.D, p.n_tiles, p.n_chunks, table, pre);
+            else
+                hipLaunchKernelGGL(hist_kernel, dim3(p.n_tiles), dim3(256), sizeof(uint32_t) * p.rows, s,
+                                   dest, p.n, p.D, p.tile, p.n_tiles, table);
             RAFI_LAUNCH_CHECK();
             hipLaunchKernelGGL(scan_reduce_kernel, dim3(p.scan_blocks), dim3(kScanThreads), 0, s, table,
                                p.M, part);
@@ -761,17 +906,17 @@ int split_run(const SplitPlan &p, const void *items, const int32_t *dest, void *
     const uint32_t *it = static_cast<const uint32_t *>(items);
     uint32_t *o = static_cast<uint32_t *>(out);
     switch (p.S / 4) {
-    case 1: launch_scatter<1>(p, it, dest, table, o, dummy, s); break;
-    case 2: launch_scatter<2>(p, it, dest, table, o, dummy, s); break;
-    case 3: launch_scatter<3>(p, it, dest, table, o, dummy, s); break;
-    case 4: launch_scatter<4>(p, it, dest, table, o, dummy, s); break;
-    case 6: launch_scatter<6>(p, it, dest, table, o, dummy, s); break;
-    case 8: launch_scatter<8>(p, it, dest, table, o, dummy, s); break;
-    case 10: launch_scatter<10>(p, it, dest, table, o, dummy, s); break;
-    case 11: launch_scatter<11>(p, it, dest, table, o, dummy, s); break;
-    case 12: launch_scatter<12>(p, it, dest, table, o, dummy, s); break;
-    case 16: launch_scatter<16>(p, it, dest, table, o, dummy, s); break;
-    default: launch_scatter<0>(p, it, dest, table, o, dummy, s); break;
+    case 1: launch_scatter<1>(p, it, dest, table, pre, o, dummy, s); break;
+    case 2: launch_scatter<2>(p, it, dest, table, pre, o, dummy, s); break;
+    case 3: launch_scatter<3>(p, it, dest, table, pre, o, dummy, s); break;
+    case 4: launch_scatter<4>(p, it, dest, table, pre, o, dummy, s); break;
+    case 6: launch_scatter<6>(p, it, dest, table, pre, o, dummy, s); break;
+    case 8: launch_scatter<8>(p, it, dest, table, pre, o, dummy, s); break;
+    case 10: launch_scatter<10>(p, it, dest, table, pre, o, dummy, s); break;
+    case 11: launch_scatter<11>(p, it, dest, table, pre, o, dummy, s); break;
+    case 12: launch_scatter<12>(p, it, dest, table, pre, o, dummy, s); break;
+    case 16: launch_scatter<16>(p, it, dest, table, pre, o, dummy, s); break;
+    default: launch_scatter<0>(p, it, dest, table, pre, o, dummy, s); break;
     }
     RAFI_LAUNCH_CHECK();
     if (ev) RAFI_HIP_CHECK(hipEventRecord(ev->end, s));

@@ -948,14 +948,55 @@ constexpr size_t wide_raw_lds_bytes_c(int32_t D)
     return sizeof(uint32_t) * ((size_t)CH * NW + D + CH) + sizeof(uint16_t) * ((size_t)W * D + 2 + CH);
 }
 
+// Chunk schedules of the raw scatter. A schedule names the chunks one
+// workgroup processes, in order (chunk j covers slots [begin(j), end(j)), at
+// most CH of them), and each destination's output slot for the first of its
+// items in a chunk: base(j, e), read for every chunk when kRebase, else only
+// for the first chunk, after which the cursor runs on.
+//
+// TileChunks: the consecutive chunks of one tile [tstart, tend).
+template <int CH, typename RunBase>
+struct TileChunks {
+    static constexpr bool kRebase = false;
+    uint64_t tstart, tend;
+    RunBase run_base;
+    __device__ bool has(uint32_t j) const { return tstart + (uint64_t)j * CH < tend; }
+    __device__ uint64_t begin(uint32_t j) const { return tstart + (uint64_t)j * CH; }
+    __device__ uint64_t end(uint32_t j) const { return min(begin(j) + CH, tend); }
+    __device__ uint32_t base(uint32_t, int32_t e) const { return run_base(e); }
+};
+
+// LockChunks: chunk c0 + j * stride, for every such chunk below n_chunks.
+// base(j, e) = the tile's run base (tiles of LC consecutive chunks) plus the
+// items bound for e in the earlier chunks of the same tile (pre: u16 per
+// chunk and destination).
+template <int CH, int LC>
+struct LockChunks {
+    static constexpr bool kRebase = true;
+    uint64_t n;
+    uint32_t c0, stride, n_chunks, n_tiles;
+    int32_t D;
+    const uint32_t *__restrict__ table;
+    const uint16_t *__restrict__ pre;
+    __device__ uint32_t chunk(uint32_t j) const { return c0 + j * stride; }
+    __device__ bool has(uint32_t j) const { return chunk(j) < n_chunks; }
+    __device__ uint64_t begin(uint32_t j) const { return (uint64_t)chunk(j) * CH; }
+    __device__ uint64_t end(uint32_t j) const { return min(begin(j) + CH, n); }
+    __device__ uint32_t base(uint32_t j, int32_t e) const
+    {
+        const uint32_t c = chunk(j);
+        return table[(uint64_t)e * n_tiles + c / LC] + (uint32_t)pre[(uint64_t)c * (uint32_t)D + (uint32_t)e];
+    }
+};
+
 // words: 32-bit words of `items` that may be read, a multiple of 4 (at
 // least 4); the host rounds the array's length up to it only where the
 // allocation is padded for that.
-template <int NW, int R, int W, typename RunBase>
-__device__ inline void wide_raw_scatter_tile(const uint32_t *__restrict__ items, const int32_t *__restrict__ dest,
-                                             uint64_t tstart, uint64_t tend, uint64_t words, int32_t D,
-                                             int32_t dbase, int nbits, RunBase run_base, uint32_t *__restrict__ out,
-                                             uint64_t out_cap, uint32_t *__restrict__ dummy, uint32_t *lds)
+template <int NW, int R, int W, typename Sched>
+__device__ inline void wide_raw_scatter(const uint32_t *__restrict__ items, const int32_t *__restrict__ dest,
+                                        uint64_t words, int32_t D, int nbits, const Sched &sched,
+                                        uint32_t *__restrict__ out, uint64_t out_cap, uint32_t *__restrict__ dummy,
+                                        uint32_t *lds)
 {
     constexpr int NT = 64 * W, SEG = 64 * R, CH = W * SEG;
     static_assert((R * NW) % 4 == 0, "a chunk is a whole number of 16-byte pieces per thread");
@@ -975,28 +1016,36 @@ __device__ inline void wide_raw_scatter_tile(const uint32_t *__restrict__ items,
     const int per = (D + NT - 1) / NT;
     const int e0 = tid * per;
 
-    uint32_t cursor[EPT];
+    // cursor: output slot of the next item bound for each owned destination;
+    // nbase: the same for the next chunk, read with its items (kRebase)
+    uint32_t cursor[EPT], nbase[EPT];
+    auto load_bases = [&](uint32_t j) {
 #pragma unroll
-    for (int k = 0; k < EPT; ++k) cursor[k] = (k < per && e0 + k < D) ? run_base(e0 + k) : 0u;
+        for (int k = 0; k < EPT; ++k) nbase[k] = (k < per && e0 + k < D) ? sched.base(j, e0 + k) : 0u;
+    };
 
     typedef uint4 Pieces[PPT];
     typedef int32_t Dests[R];
-    auto load_chunk = [&](Pieces &pc, Dests &dd, uint64_t cbase) {
+    // Slots [cbase, cend) of the chunk; pieces past the chunk's last word
+    // (rounded up to a whole piece: chunk ends are multiples of 4 items
+    // except at the array's end, whose padding `words` covers) read that
+    // piece instead: they belong to no item of the chunk and are never stored.
+    auto load_chunk = [&](Pieces &pc, Dests &dd, uint64_t cbase, uint64_t cend) {
         const uint64_t qbase = cbase + (uint64_t)w * SEG;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint64_t i = qbase + 64 * r + lane;
-            const uint64_t ic = i < tend ? i : tend - 1;
+            const uint64_t ic = i < cend ? i : cend - 1;
             const int32_t x = __builtin_nontemporal_load(dest + ic);
-            dd[r] = i < tend ? x - dbase : -1;
+            dd[r] = i < cend ? x : -1;
         }
         const uint64_t wb = cbase * NW;  // a multiple of 4
+        const uint64_t we = (cend * NW + 3) & ~3ull;
+        const uint64_t wlim = we < words ? we : words;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            // pieces past the readable words belong to no item of the tile
-            // (never stored): read the last piece instead
             const uint64_t w0 = wb + 4ull * (uint64_t)(k * NT + tid);
-            pc[k] = load_nt4(items + (w0 + 4 <= words ? w0 : words - 4));
+            pc[k] = load_nt4(items + (w0 + 4 <= wlim ? w0 : wlim - 4));
         }
         __asm__ __volatile__("" ::: "memory");
     };
@@ -1085,12 +1134,36 @@ __device__ inline void wide_raw_scatter_tile(const uint32_t *__restrict__ items,
         __syncthreads();
     };
 
-    if (tstart >= tend) return;
+    if (!sched.has(0)) return;
     Pieces pc;
     Dests dd;
-    load_chunk(pc, dd, tstart);
-    for (uint64_t cbase = tstart; cbase < tend; cbase += CH)
-        process(pc, dd, [&] { load_chunk(pc, dd, cbase + CH); });
+    load_chunk(pc, dd, sched.begin(0), sched.end(0));
+    load_bases(0);
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) cursor[k] = nbase[k];
+    for (uint32_t j = 0; sched.has(j); ++j) {
+        if constexpr (Sched::kRebase) {
+#pragma unroll
+            for (int k = 0; k < EPT; ++k) cursor[k] = nbase[k];
+        }
+        const bool more = sched.has(j + 1);  // the same for the whole workgroup
+        process(pc, dd, [&] {
+            if (more) {
+                load_chunk(pc, dd, sched.begin(j + 1), sched.end(j + 1));
+                if constexpr (Sched::kRebase) load_bases(j + 1);
+            }
+        });
+    }
+}
+
+template <int NW, int R, int W, typename RunBase>
+__device__ inline void wide_raw_scatter_tile(const uint32_t *__restrict__ items, const int32_t *__restrict__ dest,
+                                             uint64_t tstart, uint64_t tend, uint64_t words, int32_t D, int nbits,
+                                             RunBase run_base, uint32_t *__restrict__ out, uint64_t out_cap,
+                                             uint32_t *__restrict__ dummy, uint32_t *lds)
+{
+    const TileChunks<W * 64 * R, RunBase> sched{tstart, tend, run_base};
+    wide_raw_scatter<NW, R, W>(items, dest, words, D, nbits, sched, out, out_cap, dummy, lds);
 }
 
 }  // namespace dev

@@ -70,7 +70,7 @@ def test_argument_validation_without_device():
                                      C.c_void_p(2048), C.c_void_p(4096), None) == rafi.ERR_TOO_LARGE
     assert L.rafi_multisplit_noalloc(C.c_void_p(8), C.c_void_p(16), 10, 16, 4, C.c_void_p(32), C.c_void_p(64),
                                      C.c_void_p(128), None) == rafi.ERR_ARG
-    assert L.rafi_split_set_variant(17) == rafi.ERR_ARG
+    assert L.rafi_split_set_variant(18) == rafi.ERR_ARG
     assert L.rafi_split_set_variant(-1) == rafi.ERR_ARG
 
 

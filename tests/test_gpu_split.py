@@ -165,10 +165,63 @@ def test_split_raw_staged_shape(orc, variant, n, D, words, dist):
         rafi.split_set_variant(0)
 
 
+@pytest.mark.parametrize("variant", [0, 17])
+@pytest.mark.parametrize("n,D,words,dist", [
+    (2_097_152, 1024, 11, "mixed"), (2_500_003, 1024, 11, "mixed"), (3_000_000, 1000, 10, "zipf"),
+    (4_194_308, 64, 6, "cyclic"), (2_200_001, 1024, 3, "mixed"), (2_100_000, 1, 11, "mixed")])
+def test_split_lockstep_shape(orc, variant, n, D, words, dist):
+    """Large splits of items that are not whole 16-byte pieces: the lockstep
+    schedule (tiles of 32 chunks of 2048 slots, each chunk's run bases from
+    its tile's column plus the histogram pass's per-chunk prefixes, 256
+    persistent workgroups), automatic or forced. Through the stateless split
+    (which falls back to the staged shapes, on the lockstep plan's table,
+    when the array is not a whole number of 16-byte pieces) and a context;
+    ragged last chunks and tiles; 1 to 1024 destinations."""
+    try:
+        rafi.split_set_variant(variant)
+        _run_split(orc, n, D, words, seed=variant * 1000 + n + 4, dist=dist)
+        _run_ctx_split(orc, n, D, words, seed=variant * 1000 + n + 5, dist=dist)
+    finally:
+        rafi.split_set_variant(0)
+
+
+def test_split_lockstep_workspace_fallback(orc):
+    """A workspace sized while another scatter shape was selected lacks the
+    lockstep plan's chunk prefixes: the stateless split then plans without
+    them instead of failing, with the same result."""
+    dev = device()
+    n, D, words = 2_097_152, 1024, 11
+    try:
+        rafi.split_set_variant(16)
+        small = rafi.multisplit_workspace(n, D, 4 * words)
+    finally:
+        rafi.split_set_variant(0)
+    assert rafi.multisplit_workspace(n, D, 4 * words) > small
+    rng = np.random.default_rng(11)
+    dest = rng.integers(-1, D, n).astype(np.int32)
+    items = rng.integers(0, 2**32, (n, words), dtype=np.uint64).astype(np.uint32)
+    announce("split lockstep workspace fallback")
+    d_items = torch.from_numpy(items.view(np.int32)).to(dev)
+    d_dest = torch.from_numpy(dest).to(dev)
+    out = torch.empty_like(d_items)
+    offsets = torch.empty(D + 1, dtype=torch.int64, device=dev)
+    summary = torch.empty(4, dtype=torch.int64, device=dev)
+    ws = torch.empty(small, dtype=torch.uint8, device=dev)
+    rc = rafi.lib().rafi_multisplit(rafi._dptr(d_items), rafi._dptr(d_dest), n, 4 * words, D, rafi._dptr(out),
+                                    rafi._dptr(offsets), rafi._dptr(summary), rafi._dptr(ws), small, None)
+    assert rc == 0
+    torch.cuda.synchronize()
+    e_out, e_counts, e_off, e_done, e_bad = orc.multisplit(items, dest, D)
+    total = int(e_off[-1])
+    assert np.array_equal(offsets.cpu().numpy().astype(np.uint64), e_off)
+    assert int(summary[0]) == total and int(summary[1]) == e_done
+    assert np.array_equal(out[:total].cpu().numpy().view(np.uint32), e_out)
+
+
 @pytest.mark.parametrize("dist", ["uniform", "zipf"])
 def test_split_full_size_44_bytes(orc, dist):
     """The microbenchmark at the paper's 44-byte ray size: 64M items, 1024
-    destinations."""
+    destinations (the lockstep schedule)."""
     dev = device()
     n, D = 1 << 26, 1024
     dest = W.split_dest(n, D, dist)
