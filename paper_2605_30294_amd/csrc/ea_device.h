@@ -115,6 +115,30 @@ __device__ inline Tri tri_setup(int32_t n, const float p[3])
     return Tri{i0[0] + (int64_t)n * (i0[1] + (int64_t)n * i0[2]), i0[0], i0[1], i0[2], f[0], f[1], f[2]};
 }
 
+// tri_setup for volumes of at most 1290^3 voxels (n^3 < 2^31, the caller's
+// test): the same cell and weights, the clamp as one med3 (the clamp for any
+// non-NaN value), the floor limited to n - 2 in float (exact: an integer
+// below 2^24) and the corner's linear index from full-rate 24-bit
+// multiplies (every factor below 2^24, the sum below 2^31).
+constexpr int32_t kSmallN = 1290;
+
+__device__ inline Tri tri_setup_small(int32_t n, const float p[3])
+{
+    const float hi = (float)(n - 1), top = (float)(n - 2);
+    uint32_t i0[3];
+    float f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float u = __builtin_amdgcn_fmed3f(p[a] - 0.5f, 0.0f, hi);
+        const float fl = fminf(floorf(u), top);
+        i0[a] = (uint32_t)fl;
+        f[a] = u - fl;
+    }
+    const uint32_t nn = (uint32_t)n;
+    const uint32_t base = i0[0] + __umul24(i0[1], nn) + __umul24(i0[2], nn * nn);
+    return Tri{(int64_t)base, (int32_t)i0[0], (int32_t)i0[1], (int32_t)i0[2], f[0], f[1], f[2]};
+}
+
 // Trilinear density from the volume (voxel centres at i + 0.5).
 __device__ inline float density(const float *__restrict__ vol, int32_t n, const Tri &t)
 {
@@ -212,9 +236,15 @@ __device__ inline int32_t first_inside(const Geo &g, const float org[3], const f
 // Advance a ray through its brick (box) from sample it.k: accumulates tau and
 // I and leaves it.k at the first sample not taken. Returns the brick that owns
 // that sample, or -1 when the ray left the volume or ran out of samples.
-__device__ inline int32_t march_through(const float *__restrict__ vol, const Geo &g, const Box &box,
-                                        const float org[3], const float dir[3], int32_t K, float dt, float c,
-                                        Item &it)
+// kSmall: the volume has at most kSmallN^3 voxels (tri_setup_small).
+// The transmittance exp(-tau) is the hardware exponential (a base-2
+// exponential of -tau log2(e)); its relative error, about 1e-6 for the
+// optical depths of a ray, stays well inside the integrals' tolerance, and
+// the emission term keeps the accurate expm1.
+template <bool kSmall>
+__device__ inline int32_t march_through_n(const float *__restrict__ vol, const Geo &g, const Box &box,
+                                          const float org[3], const float dir[3], int32_t K, float dt, float c,
+                                          Item &it)
 {
     float tau = it.tau, I = it.I, ctau = 0.0f, cI = 0.0f;
     int32_t k = it.k;
@@ -227,9 +257,9 @@ __device__ inline int32_t march_through(const float *__restrict__ vol, const Geo
             dest = owner_of(p, g);
             break;
         }
-        const float rho = density_cached(vol, g.n, tri_setup(g.n, p), cc);
+        const float rho = density_cached(vol, g.n, kSmall ? tri_setup_small(g.n, p) : tri_setup(g.n, p), cc);
         const float sigma = c * rho;
-        const float w = expf(-tau) * -expm1f(-sigma);
+        const float w = __expf(-tau) * -expm1f(-sigma);
         // compensated I += w * rho
         const float yI = w * rho - cI;
         const float tI = I + yI;
@@ -245,6 +275,14 @@ __device__ inline int32_t march_through(const float *__restrict__ vol, const Geo
     it.tau = tau - ctau;
     it.I = I - cI;
     return dest;
+}
+
+__device__ inline int32_t march_through(const float *__restrict__ vol, const Geo &g, const Box &box,
+                                        const float org[3], const float dir[3], int32_t K, float dt, float c,
+                                        Item &it)
+{
+    return g.n <= kSmallN ? march_through_n<true>(vol, g, box, org, dir, K, dt, c, it)
+                          : march_through_n<false>(vol, g, box, org, dir, K, dt, c, it);
 }
 
 // A brick's voxels plus a one-voxel rim, staged in LDS: region origin
