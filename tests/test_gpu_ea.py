@@ -81,6 +81,51 @@ def test_cfg0_plusz_64cube(orc, tile_items):
     _compare(g, o)
 
 
+@pytest.mark.parametrize("n,w", [(1290, 86), (1292, 76)])
+def test_large_volume_cell_index(n, w):
+    """Volumes of at most 1290^3 voxels take the march's 32-bit cell index,
+    larger ones the 64-bit one (here 1292^3, 8.6 GB, where i + n j + n^2 k
+    passes 2^31). A density linear in x and z, which trilinear
+    interpolation reproduces to float32 rounding, 2x2x2 bricks, a +z view
+    whose rays sit at exactly representable x (pixel spacing n / w = 15 or
+    17 voxels). Reference: the emission-absorption sum over each ray's
+    samples of the analytic density, in float64 (no oracle)."""
+    dev = device()
+    a, bx, bz = 0.02, 1.0e-5, 2.0e-5
+    announce(f"ea large volume n={n}")
+    xx = torch.arange(n, device=dev, dtype=torch.float32).view(1, 1, n)
+    zz = torch.arange(n, device=dev, dtype=torch.float32).view(n, 1, 1)
+    vol = (a + bz * zz + bx * xx).expand(n, n, n).contiguous()       # [z, y, x]
+    del xx, zz
+    views = W.plusz_view(n, w, w)
+    ns = int(views[0]["n_samples"])
+    try:
+        r = rafi.ea_render(vol, (2, 2, 2), views, c=C32, want_tau=True)
+        torch.cuda.synchronize()
+        image = r["image"].cpu().numpy().reshape(w, w)
+        tau = r["tau"].cpu().numpy().reshape(w, w)
+        klast = r["klast"].cpu().numpy()
+        r["ctx"].close()
+    finally:
+        del vol
+        torch.cuda.empty_cache()
+    assert np.all(klast == ns)
+    sx = n / w
+    x = 0.5 * sx + sx * np.arange(w)                                   # every ray of a column shares x
+    z = (np.arange(ns) + 0.5) * 0.5
+    u_z = np.clip(z - 0.5, 0.0, n - 1)
+    rho = a + bx * (x[:, None] - 0.5) + bz * u_z[None, :]              # [x, sample]
+    sigma = C32 * rho
+    t_before = np.cumsum(sigma, axis=1) - sigma
+    I_ref = np.sum(np.exp(-t_before) * -np.expm1(-sigma) * rho, axis=1)
+    tau_ref = np.sum(sigma, axis=1)
+    # image rows are y, columns x: compare every ray with its column's reference
+    ok, i, rr = rel_close(image, np.broadcast_to(I_ref[None, :], (w, w)), RTOL, ATOL)
+    assert ok, f"image ray {i}: ({rr:.3g} x tol)"
+    ok, i, rr = rel_close(tau, np.broadcast_to(tau_ref[None, :], (w, w)), RTOL, ATOL)
+    assert ok, f"tau ray {i}: ({rr:.3g} x tol)"
+
+
 @pytest.mark.parametrize("n,grid,nv,w,h,seed", [
     (32, (4, 4, 4), 3, 20, 20, 1), (32, (2, 1, 4), 2, 33, 17, 2), (48, (3, 2, 1), 2, 40, 40, 3),
     (16, (1, 1, 1), 1, 7, 9, 4), (64, (4, 2, 2), 4, 64, 64, 5),
