@@ -56,9 +56,10 @@ __device__ inline int32_t owner_of(const float p[3], const Geo &g)
 // (the bounds are integers, so this equals owner_of(p) == d).
 struct Box {
     float lo0, hi0, lo1, hi1, lo2, hi2;
+    // the six compares combined without short-circuit branches
     __device__ bool contains(const float p[3]) const
     {
-        return p[0] >= lo0 && p[0] < hi0 && p[1] >= lo1 && p[1] < hi1 && p[2] >= lo2 && p[2] < hi2;
+        return (p[0] >= lo0) & (p[0] < hi0) & (p[1] >= lo1) & (p[1] < hi1) & (p[2] >= lo2) & (p[2] < hi2);
     }
 };
 
