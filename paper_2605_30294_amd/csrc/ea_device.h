@@ -141,9 +141,9 @@ __device__ inline Tri tri_setup_small(int32_t n, const float p[3])
 }
 
 // 1 - exp(-s). For |s| below 1/16, the Maclaurin series of the function to
-// the s^6 term (Horner form; the truncated terms are below 1.2e-11 |s|),
-// six fused multiply-adds instead of the library's expm1. Larger |s|, or a
-// NaN, take the library call.
+// the s^6 term (Horner form; the truncated terms are below 1.2e-11 |s|):
+// five fused multiply-adds and a product instead of the library's expm1.
+// Larger |s|, or a NaN, take the library call.
 __device__ inline float one_minus_exp_neg(float s)
 {
     if (fabsf(s) < 0.0625f) {
@@ -173,9 +173,9 @@ __device__ inline float density(const float *__restrict__ vol, int32_t n, const 
 
 // The 8 voxels of the last sampled cell, kept in registers. Samples half a
 // voxel apart along a ray often fall in the same cell, and then no memory is
-// read: on the 64-view render about a third of the gathers are skipped, the
-// texture-address pipeline being what bounds the march. The values and the
-// interpolation are those of density(), so the result is bit-identical.
+// read: on the 64-view render the texture-address unit's work drops by about
+// a third. The values and the interpolation are those of density(), so the
+// result is bit-identical.
 struct Corners {
     int64_t base = -1;  // linear index of the cached cell's corner; -1 = empty
     float v[8];
