@@ -81,6 +81,33 @@ def test_cfg0_plusz_64cube(orc, tile_items):
     _compare(g, o)
 
 
+@pytest.mark.parametrize("rho", [0.0, 0.4, 2.4, 2.6, 40.0])
+def test_uniform_medium_closed_form(rho):
+    """A uniform medium of density rho, 2x2x2 bricks, 32^3, a +z view: every
+    ray takes m = 64 samples of sigma = c rho, so I = rho (1 - exp(-m
+    sigma)) and tau = m sigma exactly (float64 here, no oracle). The
+    densities put sigma on both sides of 1/16, where the march's emission
+    weight changes from its series to the library expm1, and 40 gives
+    sigma = 1 per sample."""
+    dev = device()
+    n = 32
+    announce(f"ea uniform medium rho={rho}")
+    vol = torch.full((n, n, n), rho, dtype=torch.float32, device=dev)
+    views = W.plusz_view(n, 16, 16)
+    m = int(views[0]["n_samples"])
+    r = rafi.ea_render(vol, (2, 2, 2), views, c=C32, want_tau=True)
+    torch.cuda.synchronize()
+    image = r["image"].cpu().numpy()
+    tau = r["tau"].cpu().numpy()
+    r["ctx"].close()
+    sigma = C32 * float(np.float32(rho))
+    I_ref = float(np.float32(rho)) * -np.expm1(-m * sigma)
+    ok, i, rr = rel_close(image, np.full_like(image, I_ref, dtype=np.float64), RTOL, ATOL)
+    assert ok, f"image ray {i}: gpu {image[i]!r} closed form {I_ref!r} ({rr:.3g} x tol)"
+    ok, i, rr = rel_close(tau, np.full_like(tau, m * sigma, dtype=np.float64), RTOL, ATOL)
+    assert ok, f"tau ray {i}: gpu {tau[i]!r} closed form {m * sigma!r}"
+
+
 @pytest.mark.parametrize("n,w", [(1290, 86), (1292, 76)])
 def test_large_volume_cell_index(n, w):
     """Volumes of at most 1290^3 voxels take the march's 32-bit cell index,
