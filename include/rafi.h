@@ -220,10 +220,11 @@ int rafi_multisplit_workspace(uint64_t n, int32_t n_domains, uint32_t item_bytes
                               uint64_t *bytes);
 
 /* Process-wide choice of the scatter pass's workgroup shape (chunk size,
- * waves per workgroup, workgroups per CU): 0 = automatic (shape 14 when
- * one workgroup per CU spans at least two tiles and 16384 slots, else
- * shape 12 when a tile holds at least one of its chunks, else the first of
- * 1..4 that fits the LDS); 1..4 stage items
+ * waves per workgroup, workgroups per CU): 0 = automatic (for at most 128
+ * destinations and 256 MiB of 16- or 32-byte items shape 4 or 2, else
+ * shape 14 when one workgroup per CU spans at least two tiles and 16384
+ * slots, else shape 12 when a tile holds at least one of its chunks, else
+ * the first of 1..4 that fits the LDS); 1..4 stage items
  * in LDS; 5..7 stage only indices and read items in sorted order; 8..11 are
  * shapes 1..4 with the next chunk's loads issued before the current chunk is
  * ranked; 12..13 use one workgroup per CU with 4096-slot chunks (32-byte
