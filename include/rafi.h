@@ -221,7 +221,8 @@ int rafi_multisplit_workspace(uint64_t n, int32_t n_domains, uint32_t item_bytes
 
 /* Process-wide choice of the scatter pass's workgroup shape (chunk size,
  * waves per workgroup, workgroups per CU): 0 = automatic (for at most 128
- * destinations and 256 MiB of 16- or 32-byte items shape 4 or 2, else
+ * destinations: up to 256 MiB of 16- or 32-byte items shape 4 or 2, up to
+ * 64 MiB of items of 44 bytes or more the plain per-thread scatter; else
  * shape 14 when one workgroup per CU spans at least two tiles and 16384
  * slots, else shape 12 when a tile holds at least one of its chunks, else
  * the first of 1..4 that fits the LDS); 1..4 stage items

@@ -658,6 +658,13 @@ bool launch_staged(const SplitPlan &p, const uint32_t *items, const int32_t *des
                    const uint16_t *pre, uint32_t *out, uint32_t *dummy, hipStream_t s)
 {
     int v = g_split_variant;
+    if constexpr (NW >= 11) {
+        // automatic: items of 44 bytes and more, few destinations and at most
+        // 64 MiB: the plain per-thread scatter (each wave's run of a
+        // destination is already long; the staged shapes' ranking costs
+        // more than it saves there, 5-15% at 1M slots)
+        if (v == 0 && p.D <= 128 && p.n * (uint64_t)p.S <= (1ull << 26) && !p.lock) return false;
+    }
     if constexpr (NW % 4 != 0 && NW >= 3 && NW <= 15) {
         // large splits: the lockstep schedule (its plan has the chunk prefixes)
         if ((v == 0 || v == 17) && p.lock && try_lock_raw<NW>(p, items, dest, table, pre, out, dummy, s))
