@@ -165,6 +165,20 @@ def test_split_raw_staged_shape(orc, variant, n, D, words, dist):
         rafi.split_set_variant(0)
 
 
+@pytest.mark.parametrize("n,D,words", [
+    (16_777_216, 64, 4), (16_777_220, 64, 4),      # 16-byte items: shape 4 up to 2^28 bytes
+    (8_388_608, 128, 8), (8_388_612, 128, 8),      # 32-byte items: shape 2 up to 2^28 bytes
+    (1_525_201, 64, 11), (1_525_204, 64, 11),      # 44-byte items: plain scatter up to 2^26 bytes
+    (1_398_101, 64, 12), (1_398_104, 64, 12),      # 48-byte items
+])
+def test_split_automatic_shape_boundaries(orc, n, D, words):
+    """The automatic scatter shape for few destinations changes with the
+    array's size (small staged shapes or the plain per-thread scatter up
+    to a bound, the usual choice above): both sides of each bound, through
+    the stateless split, against the oracle."""
+    _run_split(orc, n, D, words, seed=n + D + 7, dist="mixed")
+
+
 @pytest.mark.parametrize("variant", [0, 17])
 @pytest.mark.parametrize("n,D,words,dist", [
     (2_097_152, 1024, 11, "mixed"), (2_500_003, 1024, 11, "mixed"), (3_000_000, 1000, 10, "zipf"),
