@@ -295,9 +295,9 @@ batch_finalize_kernel(BatchDev b)
 
 // ------------------------------------------------------------ scatter ---
 constexpr int kNW = RAFI_EA_ITEM_BYTES / 4;
-constexpr int kR = 12, kW = 4;  // 3072-slot chunks, two workgroups per CU
+constexpr int kR = 4, kW = 4;  // 1024-slot chunks, four workgroups per CU
 
-__global__ void __launch_bounds__(64 * kW, 2)
+__global__ void __launch_bounds__(64 * kW, 4)
 batch_scatter_kernel(BatchDev b, uint64_t cap)
 {
     extern __shared__ __align__(16) uint32_t lds[];
