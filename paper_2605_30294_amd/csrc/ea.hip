@@ -304,6 +304,7 @@ bwd_march_kernel(rafi_device_view view, rafi_ea_job job, const float *__restrict
     float tau = it.tau, ctau = 0.0f, B = it.I;
     int32_t k = it.k;
     int32_t dest = RAFI_DONE;
+    ea::Corners cc;
     for (; k >= 0; --k) {
         float p[3];
         ea::sample_pos(org, dir, job.dt, k, p);
@@ -312,15 +313,15 @@ bwd_march_kernel(rafi_device_view view, rafi_ea_job job, const float *__restrict
             break;
         }
         const Tri t = ea::tri_setup(g.n, p);
-        const float rho = ea::density(job.volume, g.n, t);
+        const float rho = ea::density_cached(job.volume, g.n, t, cc);
         const float sigma = c * rho;
         // compensated tau -= sigma
         const float yt = -sigma - ctau;
         const float tt = tau + yt;
         ctau = (tt - tau) - yt;
         tau = tt;
-        const float T = expf(-tau);
-        const float a = -expm1f(-sigma);
+        const float T = __expf(-tau);
+        const float a = ea::one_minus_exp_neg(sigma);
         const float dIdrho = T * __fmaf_rn(c * (1.0f - a), rho - B, a);
         if (gI != 0.0f) scatter8(grad, g.n, t, gI * dIdrho);
         B = __fmaf_rn(a, rho - B, B);
@@ -343,7 +344,8 @@ constexpr int kBwdThreads = 1024;
 // The backward of the queue items [first, last), all in domain d, by the whole
 // workgroup: zero the brick's gradient region in LDS, march every ray back
 // through the brick accumulating into it, then add its non-zero entries to
-// the global gradient.
+// the global gradient. kSmall: the volume has at most kSmallN^3 voxels.
+template <bool kSmall>
 __device__ inline void bwd_segment(const rafi_device_view &view, const rafi_ea_job &job,
                                    const float *__restrict__ grad_image, float *__restrict__ grad, uint32_t n_rays,
                                    int32_t d, uint64_t first, uint64_t last, float *gl)
@@ -374,6 +376,7 @@ __device__ inline void bwd_segment(const rafi_device_view &view, const rafi_ea_j
         // acc[q]: this lane's pending gradient for corner q = (q&1, q>>1&1, q>>2)
         // of the cell whose corner (0,0,0) is local voxel (cx, cy, cz)
         int32_t cell = -1, cx = 0, cy = 0, cz = 0;
+        ea::Corners cc;
         float acc[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[q] = 0.0f;
@@ -417,15 +420,17 @@ __device__ inline void bwd_segment(const rafi_device_view &view, const rafi_ea_j
                 dest = ea::owner_of(p, g);
                 break;
             }
-            const Tri t = ea::tri_setup(g.n, p);
-            const float rho = ea::density(job.volume, g.n, t);
+            // the forward march's per-sample forms: cached corners, the
+            // hardware exponential, the series for 1 - exp(-sigma)
+            const Tri t = kSmall ? ea::tri_setup_small(g.n, p) : ea::tri_setup(g.n, p);
+            const float rho = ea::density_cached(job.volume, g.n, t, cc);
             const float sigma = c * rho;
             const float yt = -sigma - ctau;
             const float tt = tau + yt;
             ctau = (tt - tau) - yt;
             tau = tt;
-            const float T = expf(-tau);
-            const float a = -expm1f(-sigma);
+            const float T = __expf(-tau);
+            const float a = ea::one_minus_exp_neg(sigma);
             const float dIdrho = T * __fmaf_rn(c * (1.0f - a), rho - B, a);
             B = __fmaf_rn(a, rho - B, B);
             if (gI == 0.0f) continue;
@@ -471,7 +476,10 @@ bwd_march_lds_kernel(rafi_device_view view, rafi_ea_job job, const float *__rest
     extern __shared__ float gl[];
     uint64_t tb, te;
     const int32_t d = rafi_tile(view, rafi_xcd_block(blockIdx.x, gridDim.x), &tb, &te);
-    bwd_segment(view, job, grad_image, grad, n_rays, d, tb, te, gl);
+    if (job.n <= ea::kSmallN)
+        bwd_segment<true>(view, job, grad_image, grad, n_rays, d, tb, te, gl);
+    else
+        bwd_segment<false>(view, job, grad_image, grad, n_rays, d, tb, te, gl);
 }
 
 // One workgroup per CU, each taking an equal contiguous slice of the queue
@@ -490,7 +498,10 @@ bwd_march_range_kernel(rafi_device_view view, rafi_ea_job job, const float *__re
     while (i < end) {
         const int32_t d = ea::find_domain(view.in_offsets, view.n_domains, i);
         const uint64_t seg_end = min(end, view.in_offsets[d + 1]);
-        bwd_segment(view, job, grad_image, grad, n_rays, d, i, seg_end, gl);
+        if (job.n <= ea::kSmallN)
+            bwd_segment<true>(view, job, grad_image, grad, n_rays, d, i, seg_end, gl);
+        else
+            bwd_segment<false>(view, job, grad_image, grad, n_rays, d, i, seg_end, gl);
         i = seg_end;
     }
 }
