@@ -341,6 +341,58 @@ bwd_march_kernel(rafi_device_view view, rafi_ea_job job, const float *__restrict
 // entries are added to the global gradient.
 constexpr int kBwdThreads = 1024;
 
+// Add v to a float in LDS as a compare-and-swap loop on the word's bits: the
+// same single rounded float addition as an atomic add, in the same
+// unspecified order. On gfx950 the native LDS float32 add (ds_add_f32) costs
+// about 200 cycles per full wave, some 3 per active lane, while a 32-bit
+// compare-and-swap costs about 27 (measured, 64 distinct words per wave).
+__device__ inline void lds_add(float *p, float v)
+{
+    uint32_t *q = reinterpret_cast<uint32_t *>(p);
+    uint32_t old = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    for (;;) {
+        uint32_t seen = old;
+        if (__hip_atomic_compare_exchange_strong(q, &seen, __float_as_uint(__uint_as_float(old) + v), __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+            return;
+        old = seen;
+    }
+}
+
+// Add acc[q] to the LDS words base[o[q]] for the corners q with fl[q]: every
+// word read, then every compare-and-swap issued, then one wait, so a cell
+// change pays two LDS round trips instead of two per corner. A corner that
+// is not flushed takes a swap of its read value's bits with one bit flipped
+// for that same value: it fails, or rewrites the word unchanged. Corners
+// whose swap lost a race to another lane are added again one by one.
+__device__ inline void lds_add_corners(float *base, const int32_t o[8], const float acc[8], const bool fl[8])
+{
+    uint32_t *w = reinterpret_cast<uint32_t *>(base);
+    uint32_t old[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) old[q] = __hip_atomic_load(w + o[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    // seen[q]: the word as each swap found it (equal to old[q] when it took)
+    uint32_t seen[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        seen[q] = fl[q] ? old[q] : old[q] ^ 1u;
+        const uint32_t want = fl[q] ? __float_as_uint(__uint_as_float(old[q]) + acc[q]) : seen[q];
+        (void)__hip_atomic_compare_exchange_strong(w + o[q], &seen[q], want, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    bool ok[8], all = true;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        ok[q] = !fl[q] || seen[q] == old[q];
+        all &= ok[q];
+    }
+    if (!all) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (!ok[q]) lds_add(base + o[q], acc[q]);
+    }
+}
+
 // The backward of the queue items [first, last), all in domain d, by the whole
 // workgroup: zero the brick's gradient region in LDS, march every ray back
 // through the brick accumulating into it, then add its non-zero entries to
@@ -383,9 +435,10 @@ __device__ inline void bwd_segment(const rafi_device_view &view, const rafi_ea_j
         const int32_t o[8] = {0, 1, ex, ex + 1, sxy, sxy + 1, sxy + ex, sxy + ex + 1};
         auto flush = [&]() {
             if (cell < 0) return;
+            bool fl[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (acc[q] != 0.0f) atomicAdd(&gl[cell + o[q]], acc[q]);
+            for (int q = 0; q < 8; ++q) fl[q] = acc[q] != 0.0f;
+            lds_add_corners(gl + cell, o, acc, fl);
         };
         // Move to the cell with corner (tx, ty, tz). Across one face the 4
         // shared corners stay in registers (renumbered); only the other 4 are
@@ -396,13 +449,15 @@ __device__ inline void bwd_segment(const rafi_device_view &view, const rafi_ea_j
             const int bit = mx ? 1 : (my ? 2 : 4);
             const bool up = mx + my + mz > 0;
             float keep[8];
+            bool fl[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 // a corner on the far side of the crossed face survives as corner q ^ bit
                 const bool kept = face && (((q & bit) != 0) == up);
-                if (!kept && cell >= 0 && acc[q] != 0.0f) atomicAdd(&gl[cell + o[q]], acc[q]);
+                fl[q] = !kept && acc[q] != 0.0f;
                 keep[q] = kept ? acc[q] : 0.0f;
             }
+            if (cell >= 0) lds_add_corners(gl + cell, o, acc, fl);
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const float from = bit == 1 ? keep[q ^ 1] : (bit == 2 ? keep[q ^ 2] : keep[q ^ 4]);
