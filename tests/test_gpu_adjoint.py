@@ -130,6 +130,31 @@ def test_uniform_medium_gradient_sum():
     assert float(vol.grad.sum()) == pytest.approx(64 * dI, rel=1e-4)
 
 
+def test_repeated_views_gradient_scales():
+    """One view repeated 32 times: coinciding rays add to the same LDS words
+    of the gradient region at nearly the same moments, so the flush's
+    compare-and-swaps lose races and retry. Every add must still land once:
+    the gradient is 32 times the single view's, up to float32 rounding."""
+    dev = device()
+    n = 32
+    vol_np = W.blob_volume(n, 71)
+    one = W.random_views(1, n, 32, 32, seed=72)
+    rep = np.concatenate([one] * 32)
+    announce("adjoint repeated views x32")
+
+    def grad_of(views):
+        vol = torch.from_numpy(vol_np).to(dev).requires_grad_(True)
+        img = rafi.ea_render_differentiable(vol, (2, 2, 2), views, c=C32)
+        img.sum().backward()                                      # dL/dI = 1 for every ray
+        torch.cuda.synchronize()
+        return vol.grad.detach().cpu().numpy().astype(np.float64)
+
+    g1 = grad_of(one)
+    g32 = grad_of(rep)
+    assert np.abs(g1).max() > 0
+    assert _rel_l2(g32, 32.0 * g1) <= 1e-5, _rel_l2(g32, 32.0 * g1)
+
+
 def test_adjoint_scale_sampled(orc):
     """128^3 in 4x4x4 bricks, 64 views x 256^2 rays, target from a second volume.
     The whole forward and backward run on the GPU; the float64 oracle checks
