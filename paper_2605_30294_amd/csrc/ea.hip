@@ -478,7 +478,13 @@ __device__ inline void bwd_segment(const rafi_device_view &view, const rafi_ea_j
             // the forward march's per-sample forms: cached corners, the
             // hardware exponential, the series for 1 - exp(-sigma)
             const Tri t = kSmall ? ea::tri_setup_small(g.n, p) : ea::tri_setup(g.n, p);
-            const float rho = ea::density_cached(job.volume, g.n, t, cc);
+            ea::fetch_corners(job.volume, g.n, t, cc);
+            // local corner (i0, j0, k0) of the sample's cell. A move flushes
+            // the corners the lane leaves, which hold only earlier samples'
+            // terms: its LDS round trips overlap the gathers just issued.
+            const int32_t tx = t.x - ox, ty = t.y - oy, tz = t.z - oz;
+            if (gI != 0.0f && (cell < 0 || tx != cx || ty != cy || tz != cz)) move_to(tx, ty, tz);
+            const float rho = ea::interp_corners(cc, t);
             const float sigma = c * rho;
             const float yt = -sigma - ctau;
             const float tt = tau + yt;
@@ -489,9 +495,6 @@ __device__ inline void bwd_segment(const rafi_device_view &view, const rafi_ea_j
             const float dIdrho = T * __fmaf_rn(c * (1.0f - a), rho - B, a);
             B = __fmaf_rn(a, rho - B, B);
             if (gI == 0.0f) continue;
-            // local corner (i0, j0, k0) of the sample's cell
-            const int32_t tx = t.x - ox, ty = t.y - oy, tz = t.z - oz;
-            if (cell < 0 || tx != cx || ty != cy || tz != cz) move_to(tx, ty, tz);
             const float s = gI * dIdrho;
             const float gx0 = 1.0f - t.f0, gy0 = 1.0f - t.f1, gz0 = 1.0f - t.f2;
             const float a00 = s * gz0 * gy0, a01 = s * gz0 * t.f1, a10 = s * t.f2 * gy0, a11 = s * t.f2 * t.f1;

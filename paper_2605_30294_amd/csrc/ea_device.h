@@ -181,7 +181,9 @@ struct Corners {
     float v[8];
 };
 
-__device__ inline float density_cached(const float *__restrict__ vol, int32_t n, const Tri &t, Corners &cc)
+// density_cached in two halves: the loads of a new cell's corners (issued,
+// not waited for), and the interpolation that uses them.
+__device__ inline void fetch_corners(const float *__restrict__ vol, int32_t n, const Tri &t, Corners &cc)
 {
     if (t.base != cc.base) {
         const int64_t sy = n, sz = (int64_t)n * n;
@@ -196,6 +198,10 @@ __device__ inline float density_cached(const float *__restrict__ vol, int32_t n,
         cc.v[7] = b[sz + sy + 1];
         cc.base = t.base;
     }
+}
+
+__device__ inline float interp_corners(const Corners &cc, const Tri &t)
+{
     const float x00 = lerpf(cc.v[0], cc.v[1], t.f0);
     const float x10 = lerpf(cc.v[2], cc.v[3], t.f0);
     const float x01 = lerpf(cc.v[4], cc.v[5], t.f0);
@@ -203,6 +209,12 @@ __device__ inline float density_cached(const float *__restrict__ vol, int32_t n,
     const float y0 = lerpf(x00, x10, t.f1);
     const float y1 = lerpf(x01, x11, t.f1);
     return lerpf(y0, y1, t.f2);
+}
+
+__device__ inline float density_cached(const float *__restrict__ vol, int32_t n, const Tri &t, Corners &cc)
+{
+    fetch_corners(vol, n, t, cc);
+    return interp_corners(cc, t);
 }
 
 // First k in [0, K] for which pred(k) flips from `from` to !from (K if never).
