@@ -32,6 +32,10 @@ constexpr int kScanPer = 16;                       // elements per thread
 constexpr int kScanChunk = kScanThreads * kScanPer;  // 4096
 constexpr int kPartThreads = 1024;
 constexpr int kPartMax = kPartThreads * kScanPer;  // 16384 partial sums
+// Up to this many scan chunks, each chunk of the apply pass sums the earlier
+// chunks' totals itself (at most 2 MiB read over the whole launch), which
+// saves the launch that scans the partial sums.
+constexpr uint32_t kDirectMaxBlocks = 1024;
 
 using dev::block_excl_scan;
 using dev::bucket_of;
@@ -232,6 +236,27 @@ scan_apply_kernel(uint32_t *__restrict__ a, uint64_t M, const uint32_t *__restri
     for (int k = 0; k < kScanPer; ++k) s += v[k];
     uint32_t tot;
     uint32_t run = block_excl_scan<kScanThreads>(s, lds, &tot) + part[blockIdx.x];
+    store16_excl(a, M, base, v, run);
+}
+
+// scan_apply_kernel with the chunk's offset summed here from the chunks'
+// totals (part as scan_reduce_kernel left it) instead of by a separate scan.
+__global__ void __launch_bounds__(kScanThreads)
+scan_apply_direct_kernel(uint32_t *__restrict__ a, uint64_t M, const uint32_t *__restrict__ part)
+{
+    __shared__ uint32_t lds[kScanThreads / 64 + 1];
+    uint32_t before = 0;
+    for (uint32_t j = threadIdx.x; j < blockIdx.x; j += kScanThreads) before += part[j];
+    uint32_t off;
+    (void)block_excl_scan<kScanThreads>(before, lds, &off);
+    uint32_t v[kScanPer];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanPer;
+    load16(a, M, base, v);
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) s += v[k];
+    uint32_t tot;
+    uint32_t run = block_excl_scan<kScanThreads>(s, lds, &tot) + off;
     store16_excl(a, M, base, v, run);
 }
 
@@ -908,10 +933,15 @@ int split_run(const SplitPlan &p, const void *items, const int32_t *dest, void *
             RAFI_LAUNCH_CHECK();
             hipLaunchKernelGGL(scan_reduce_kernel, dim3(p.scan_blocks), dim3(kScanThreads), 0, s, table,
                                p.M, part);
-            hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kPartThreads), 0, s, part,
-                               p.scan_blocks);
-            hipLaunchKernelGGL(scan_apply_kernel, dim3(p.scan_blocks), dim3(kScanThreads), 0, s, table,
-                               p.M, part);
+            if (p.scan_blocks <= kDirectMaxBlocks) {
+                hipLaunchKernelGGL(scan_apply_direct_kernel, dim3(p.scan_blocks), dim3(kScanThreads), 0, s,
+                                   table, p.M, part);
+            } else {
+                hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kPartThreads), 0, s, part,
+                                   p.scan_blocks);
+                hipLaunchKernelGGL(scan_apply_kernel, dim3(p.scan_blocks), dim3(kScanThreads), 0, s, table,
+                                   p.M, part);
+            }
             RAFI_LAUNCH_CHECK();
         }
         hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, s, table, p.n_tiles, p.D, p.n,
